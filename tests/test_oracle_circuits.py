@@ -1,0 +1,112 @@
+"""Pins of the circuit builder and DEM against Table III, Table I and the tableau."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.circuits import build_circuit
+from oracle.dem import build_dem
+from oracle.frame import K_OF, inject
+from oracle.tableau import run
+from workloads import MEMORY, NLCNOT, TELEPORT, bb, sc
+
+T3 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table3.json")))
+
+
+def _spec(key, op):
+    if key.startswith("sc"):
+        return sc(int(key[2:]), op, 4, 3)
+    return bb(key, op, 4, 3)
+
+
+@pytest.mark.parametrize("op", [NLCNOT, TELEPORT])
+@pytest.mark.parametrize("key", list(T3["nlcnot"].keys()))
+def test_table3_counts(key, op):
+    """1q, 2q, M (without the final readout) and rows: exact closed numbers."""
+    c = build_circuit(_spec(key, op))
+    k = c.counts()
+    final = c.code.n * (2 if op == NLCNOT else 1)
+    exp = T3[op][key]
+    assert (k["q1"], k["q2"], k["meas"] - final, k["dets"]) == tuple(exp[:4])
+    assert k["obs"] == c.code.k * (2 if op == NLCNOT else 1)
+
+
+@pytest.mark.parametrize("key", ["sc3", "sc5", "sc7", "sc9", "sc11", "bb18", "bb36", "bb54"])
+def test_table3_columns_nlcnot(key):
+    """Number of distinct error mechanisms equals Table III's cols."""
+    dem = build_dem(build_circuit(_spec(key, NLCNOT)))
+    assert dem.num_cols == T3["nlcnot"][key][4]
+    assert not dem.undetectable
+
+
+@pytest.mark.parametrize("key", ["sc3", "sc5", "sc7", "sc9"])
+def test_table3_columns_teleport_sc(key):
+    dem = build_dem(build_circuit(_spec(key, TELEPORT)))
+    assert dem.num_cols == T3["teleport"][key][4]
+
+
+def _sites_kinds(c):
+    kinds = []
+    for name, arg, t in c.ops:
+        if name in K_OF:
+            kinds += [K_OF[name]] * (len(t) // (2 if name == "DEPOLARIZE2" else 1))
+    return kinds
+
+
+SMALL = [sc(3, MEMORY, 3, 0), sc(3, NLCNOT, 2, 2), sc(3, TELEPORT, 2, 2),
+         bb("bb18", MEMORY, 2, 0), bb("bb18", NLCNOT, 1, 1), bb("bb18", TELEPORT, 1, 1)]
+
+
+@pytest.mark.parametrize("spec", SMALL, ids=lambda s: f"{s.code}{s.d if s.code=='sc' else s.bb}-{s.op}")
+def test_noiseless_detectors_deterministic(spec):
+    """Tableau with random measurement outcomes: every detector/observable is 0."""
+    c = build_circuit(spec)
+    for seed in range(3):
+        d, o, rnd = run(c, np.random.default_rng(seed))
+        assert not d.any() and not o.any()
+        assert rnd.any()   # the circuits do contain random outcomes
+
+
+@pytest.mark.parametrize("spec", SMALL, ids=lambda s: f"{s.code}{s.d if s.code=='sc' else s.bb}-{s.op}")
+def test_frame_matches_tableau(spec):
+    c = build_circuit(spec)
+    kinds = _sites_kinds(c)
+    rng = np.random.default_rng(11)
+    shots = []
+    for _ in range(6):
+        f = []
+        for _ in range(int(rng.integers(1, 5))):
+            s = int(rng.integers(c.num_sites))
+            f.append((s, int(rng.integers(kinds[s]))))
+        shots.append(f)
+    fd, fo = inject(c, shots)
+    for i, f in enumerate(shots):
+        td, to, _ = run(c, np.random.default_rng(100 + i), f)
+        assert (td == fd[:, i]).all() and (to == fo[:, i]).all()
+
+
+@pytest.mark.parametrize("op", [MEMORY, NLCNOT, TELEPORT])
+def test_sc3_circuit_distance(op):
+    """Table I: the d=3 surface-code operations have circuit distance 3."""
+    spec = sc(3, op, 4 if op != MEMORY else 3, 3 if op != MEMORY else 0)
+    dem = build_dem(build_circuit(spec))
+    assert not dem.undetectable                           # no weight-1 logical
+    by = {}
+    for dts, om, _ in dem.cols:
+        by.setdefault(frozenset(dts), set()).add(om)
+    assert all(len(v) == 1 for v in by.values())          # no weight-2 logical
+    found = False
+    cols = dem.cols
+    for a in range(len(cols)):
+        for b in range(a + 1, len(cols)):
+            s = frozenset(cols[a][0]) ^ frozenset(cols[b][0])
+            for om in by.get(s, ()):
+                if om ^ cols[a][1] ^ cols[b][1]:
+                    found = True
+                    break
+            if found:
+                break
+        if found:
+            break
+    assert found                                          # a weight-3 logical exists
