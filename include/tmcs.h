@@ -1,0 +1,203 @@
+/*
+ * tmcs.h - C ABI of the MI355X Monte-Carlo shot pipeline for distributed
+ * transversal QEC operations (non-local transversal CNOT and logical
+ * teleportation over ebit layers, on rotated surface codes and
+ * bivariate-bicycle codes).
+ *
+ * The pipeline follows the paper's statement of the problem (Methods,
+ * "Simulation" and "Decoding"): build a noisy Clifford circuit for the
+ * operation, extract its detector error model (DEM) - a parity-check matrix
+ * whose rows are detectors and whose columns are distinct error mechanisms -
+ * sample detector and observable bits shot by shot, decode each syndrome, and
+ * count the shots in which any logical observable is wrong (the whole-operation
+ * logical error rate).
+ *
+ * Conventions
+ *  - Every call returns a tmcs_status and never aborts; tmcs_last_error()
+ *    returns a thread-local message describing the last failure.
+ *  - Handles (tmcs_circuit, tmcs_dem) are owned by the library and released
+ *    with tmcs_free_*.  All other buffers are owned by the caller.
+ *  - "_dev" pointers are device (HBM) pointers on the current HIP device;
+ *    "stream" is a hipStream_t passed as void* (NULL = default stream).
+ *    Device work is enqueued on that stream and returns without waiting,
+ *    except where a function says it synchronises.
+ *  - Bit-packed shot arrays are row-major [rows][ceil(n_shots/64)] uint64:
+ *    shot i of the call is bit (i % 64) of word (i / 64), least significant
+ *    bit first.  Bits past n_shots in the last word are written as 0.
+ *  - Outputs are pure functions of (spec, seed, instance, shot range): they
+ *    do not depend on launch shapes, tile sizes or the order of calls.
+ */
+#ifndef TMCS_H
+#define TMCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TMCS_OK = 0,
+  TMCS_EINVAL = 1,            /* invalid argument (message says which) */
+  TMCS_ENOMEM = 2,            /* host or device allocation failed */
+  TMCS_EDEVICE = 3,           /* a HIP call failed (possibly an earlier async fault) */
+  TMCS_EUNSUPPORTED = 4,      /* valid request outside what this build supports */
+  TMCS_ENONDETERMINISTIC = 5, /* reserved: a detector is random in the noiseless circuit */
+  TMCS_ENOTINSPAN = 6         /* reserved: OSD found a syndrome outside H's column space */
+} tmcs_status;
+
+enum { TMCS_SC = 0, TMCS_BB = 1 };                                  /* code family */
+enum { TMCS_MEMORY = 0, TMCS_NONLOCAL_CNOT = 1, TMCS_TELEPORT = 2 }; /* operation */
+
+/* Circuit specification.
+ *  Rotated surface code [[d^2,1,d]] (Supplementary Note 2): code = TMCS_SC, d odd >= 3.
+ *  Bivariate-bicycle code (Supplementary Note 3, Table IV): code = TMCS_BB with
+ *  x = S_l (x) I_m, y = I_l (x) S_m, a(x,y) = sum_k x^bb_a[k][0] y^bb_a[k][1],
+ *  b(x,y) likewise; H_X = [A|B], H_Z = [B^T|A^T].
+ *  op: TMCS_MEMORY (rounds_before rounds, rounds_after ignored),
+ *      TMCS_NONLOCAL_CNOT (Methods, "Non-local CNOT circuit"; Fig. 1b),
+ *      TMCS_TELEPORT (Methods, "State teleportation circuit"; Fig. 1c);
+ *      the paper's runs use rounds_before = 4, rounds_after = 3.
+ *  p: circuit-level error rate (reset/measurement flips, gate depolarizing,
+ *     BB idle depolarizing); p_ebit: 2-qubit depolarizing on each ebit pair
+ *     (Methods, "Simulation").  0 <= p, p_ebit < 0.5.
+ */
+typedef struct {
+  int32_t code;
+  int32_t d;
+  int32_t bb_l, bb_m;
+  int32_t bb_a[3][2];
+  int32_t bb_b[3][2];
+  int32_t op;
+  int32_t rounds_before, rounds_after;
+  double p, p_ebit;
+} tmcs_circuit_spec;
+
+typedef struct tmcs_circuit tmcs_circuit; /* opaque, library-owned */
+typedef struct tmcs_dem tmcs_dem;         /* opaque, library-owned */
+
+/* Indices into the info arrays. */
+enum {
+  TMCS_INFO_QUBITS = 0, TMCS_INFO_GATES_1Q, TMCS_INFO_GATES_2Q, TMCS_INFO_MEAS,
+  TMCS_INFO_MEAS_FINAL, TMCS_INFO_DETECTORS, TMCS_INFO_OBSERVABLES,
+  TMCS_INFO_NOISE_SITES, TMCS_INFO_INSTRUCTIONS, TMCS_INFO_CODE_N, TMCS_INFO_CODE_K,
+  TMCS_INFO_LEN = 16
+};
+enum {
+  TMCS_DEM_ROWS = 0, TMCS_DEM_COLS, TMCS_DEM_OBS, TMCS_DEM_EDGES, TMCS_DEM_RANK,
+  TMCS_DEM_UNDETECTABLE, TMCS_DEM_MAX_ROW_DEG, TMCS_DEM_MAX_COL_DEG,
+  TMCS_DEM_INFO_LEN = 16
+};
+
+/* Build the noisy circuit of an operation (host only, no device work).
+ * Noise model and schedules: Methods "Simulation"; Table III fixes the gate
+ * and measurement counts the builder reproduces.  *out receives a new handle. */
+tmcs_status tmcs_build_circuit(const tmcs_circuit_spec* spec, tmcs_circuit** out);
+void tmcs_free_circuit(tmcs_circuit* c);
+
+/* Counts (Table III style): info[TMCS_INFO_*]; TMCS_INFO_MEAS includes the final
+ * data readout, TMCS_INFO_MEAS_FINAL is that readout alone. */
+tmcs_status tmcs_circuit_info(const tmcs_circuit* c, int64_t info[TMCS_INFO_LEN]);
+
+/* Canonical text of the circuit (stim-like syntax, relative record indices).
+ * Writes at most cap bytes including the terminating NUL; *len receives the
+ * full length without NUL (call with buf = NULL, cap = 0 to size the buffer). */
+tmcs_status tmcs_circuit_text(const tmcs_circuit* c, char* buf, size_t cap, size_t* len);
+
+/* Detector error model (Methods, "Decoding"): every single fault of every noise
+ * site is propagated to the detectors and observables it flips (a backward
+ * sensitivity sweep over the circuit); identical symptoms are merged with
+ * p <- pa + pb - 2 pa pb in circuit order; columns are sorted by (detector
+ * list, observable mask).  Host only; device copies are made on first use. */
+tmcs_status tmcs_build_dem(const tmcs_circuit* c, tmcs_dem** out);
+void tmcs_free_dem(tmcs_dem* d);
+tmcs_status tmcs_dem_info(const tmcs_dem* d, int64_t info[TMCS_DEM_INFO_LEN]);
+
+/* Host copy of the DEM: column-compressed H (col_ptr[cols+1], row_idx[edges],
+ * rows ascending within a column), priors[cols], obs_mask[cols] (bit o set when
+ * the mechanism flips observable o; observables <= 64).  NULL pointers skip. */
+tmcs_status tmcs_dem_export(const tmcs_dem* d, int32_t* col_ptr, int32_t* row_idx,
+                            double* priors, uint64_t* obs_mask);
+
+/* Sample n_shots shots [shot_begin, shot_begin + n_shots) of circuit c.
+ * Noise: Philox4x32-10 keyed by (seed) with counter (block, site, instance, call),
+ * 4096-shot blocks with geometric gaps between events (the bit definition is in
+ * the design notes of the library).  shot_begin must be a multiple of 64.
+ * det_dev: [detectors][ceil(n/64)] uint64; obs_dev: [observables][ceil(n/64)].
+ * Scratch device memory is cached on the circuit handle and grows on demand;
+ * the call synchronises the stream once to check the event-buffer capacity. */
+tmcs_status tmcs_sample(const tmcs_circuit* c, uint64_t seed, uint32_t instance,
+                        uint64_t shot_begin, uint64_t n_shots, uint64_t* det_dev,
+                        uint64_t* obs_dev, void* stream);
+
+/* Decoder configuration: flooding min-sum BP over the DEM with an OSD-0 fallback
+ * (Supplementary Note 7 names BP-OSD; the update rules are stated in the
+ * library's design notes). */
+typedef struct {
+  int32_t max_iter;         /* BP iterations T (>= 1) */
+  float alpha;              /* scalar scaling of check messages (plain BP) */
+  const float* weights_dev; /* NULL, or FP32 [max_iter][edges] per-edge, per-iteration
+                               weights (edges in row-major order of H) replacing alpha */
+  int32_t use_osd;          /* 1: OSD-0 on shots where BP did not converge */
+  int32_t bp_threads;       /* threads per BP workgroup; 0 = library default */
+  /* optional per-shot outputs (NULL to skip), each indexed by shot of the call: */
+  uint8_t* ehat_dev;        /* [n_shots][cols] final correction (0/1 bytes) */
+  float* llr_dev;           /* [n_shots][cols] final BP posterior LLRs */
+  int32_t* iters_dev;       /* [n_shots] BP iterations (0 for an all-zero syndrome) */
+  uint8_t* flags_dev;       /* [n_shots] bit0 converged, bit1 OSD ran, bit2 OSD not in span */
+} tmcs_decoder_cfg;
+
+/* Decode statistics, accumulated on the device (caller zeroes them). */
+typedef struct {
+  uint64_t shots;        /* shots decoded */
+  uint64_t nontrivial;   /* shots with a non-zero syndrome */
+  uint64_t converged;    /* shots where BP satisfied the syndrome */
+  uint64_t osd;          /* shots sent to OSD-0 */
+  uint64_t not_in_span;  /* OSD shots whose syndrome was not in H's column space */
+  uint64_t bp_iters;     /* sum of BP iterations */
+  uint64_t reserved[2];
+} tmcs_decode_stats;
+
+/* Decode det_dev ([rows][ceil(n/64)], as written by tmcs_sample) and write the
+ * predicted observable flips pred_obs_dev ([observables][ceil(n/64)]).
+ * stats_dev (device, may be NULL) is incremented. */
+tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg,
+                        const uint64_t* det_dev, uint64_t n_shots, uint64_t* pred_obs_dev,
+                        tmcs_decode_stats* stats_dev, void* stream);
+
+/* Whole-operation logical error rate (Methods, "Decoding": a shot fails when
+ * any of the k observables is predicted wrongly).  Synchronises the stream.
+ * n_errors_host receives the failing-shot count, ler = errors / n_shots and
+ * sigma = sqrt(ler (1 - ler) / n_shots) (binomial standard deviation). */
+tmcs_status tmcs_logical_error_rate(const uint64_t* pred_obs_dev, const uint64_t* obs_dev,
+                                    uint32_t k, uint64_t n_shots, uint64_t* n_errors_host,
+                                    double* ler, double* sigma, void* stream);
+
+/* Weighted (neural) min-sum BP, unrolled for T iterations without early stop,
+ * for training per-edge per-iteration weights w[t][e] (FP32 [T][edges]).
+ *  tmcs_wbp_workspace_size: bytes of device workspace forward/backward need for
+ *  n_shots (per-iteration LLRs and compressed check states; the per-edge
+ *  messages are recomputed in the backward pass, not stored).
+ *  tmcs_wbp_forward: llr_dev receives FP32 [T][n_shots][cols], L_v after every
+ *  iteration; the workspace keeps what the backward pass needs.
+ *  tmcs_wbp_backward: given dLoss/dL as FP32 [T][n_shots][cols], accumulates
+ *  dLoss/dw into grad_w_dev (FP32 [T][edges], caller zeroes it). */
+tmcs_status tmcs_wbp_workspace_size(const tmcs_dem* d, int32_t T, uint64_t n_shots,
+                                    size_t* bytes);
+tmcs_status tmcs_wbp_forward(const tmcs_dem* d, const float* weights_dev, int32_t T,
+                             const uint64_t* det_dev, uint64_t n_shots, float* llr_dev,
+                             void* workspace_dev, size_t workspace_bytes, void* stream);
+tmcs_status tmcs_wbp_backward(const tmcs_dem* d, const float* weights_dev, int32_t T,
+                              const uint64_t* det_dev, uint64_t n_shots,
+                              const float* grad_llr_dev, float* grad_w_dev,
+                              const void* workspace_dev, size_t workspace_bytes,
+                              void* stream);
+
+/* Thread-local description of the last error ("" if none). */
+const char* tmcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TMCS_H */

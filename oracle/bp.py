@@ -25,6 +25,8 @@ graphs by brute force (tests/test_oracle_bp.py).
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 BIG = 1e30
@@ -62,8 +64,9 @@ class Graph:
 
 
 def prior_llr(priors: np.ndarray) -> np.ndarray:
-    p = np.asarray(priors, dtype=np.float64)
-    return np.log((1.0 - p) / p)
+    """lambda_v = ln((1 - p_v) / p_v), FP64, one libm call per entry."""
+    return np.array([math.log((1.0 - p) / p) for p in np.asarray(priors, dtype=np.float64)],
+                    dtype=np.float64)
 
 
 def syndrome_of(H: np.ndarray, e: np.ndarray) -> np.ndarray:

@@ -1,0 +1,138 @@
+"""GPU parity of the BP + OSD-0 decoder against the oracle.
+
+FP32 decisions (iterations, hard decisions, OSD orderings and corrections,
+predicted observables) are compared bit for bit with the oracle run in FP32
+in the same operation order; LLRs are also compared with the FP64 oracle at
+relative tolerance 1e-4 (|LLR| >= 1e-3, shots where both stopped together).
+"""
+import numpy as np
+import pytest
+
+from oracle.circuits import build_circuit
+from oracle.dem import build_dem
+from oracle.frame import unpack_bits
+from oracle.osd import Decoder, logical_errors
+from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("sc3-memory", sc(3, MEMORY, 3, 0, 2e-2), 4096 + 300, 30),
+    ("sc3-teleport", sc(3, TELEPORT, 2, 2, 8e-3, 2e-2), 2048 + 17, 30),
+    ("sc5-nlcnot", sc(5, NLCNOT, 5, 5, 3e-3, 2e-2), 1024 + 5, 30),
+    ("bb18-nlcnot", bb("bb18", NLCNOT, 2, 2, 4e-3, 1e-2), 512 + 3, 30),
+    ("bb144-memory", bb("bb144", MEMORY, 4, 0, 2e-3), 96, 20),
+]
+
+
+def _run_lib(tmcs, spec, shots, T, seed=3, alpha=1.0):
+    import torch
+    c = tmcs.Circuit(spec)
+    dem = tmcs.DEM(c)
+    det, obs = c.alloc_outputs(shots)
+    c.sample(seed, 0, 0, shots, det, obs)
+    N = dem.cols
+    k = max(c.num_observables, 1)
+    w = (shots + 63) // 64
+    pred = torch.zeros((k, w), dtype=torch.int64, device="cuda")
+    ehat = torch.zeros((shots, N), dtype=torch.uint8, device="cuda")
+    llr = torch.zeros((shots, N), dtype=torch.float32, device="cuda")
+    iters = torch.zeros(shots, dtype=torch.int32, device="cuda")
+    flags = torch.zeros(shots, dtype=torch.uint8, device="cuda")
+    stats = tmcs.new_stats()
+    dem.decode(det, shots, pred, max_iter=T, alpha=alpha, ehat=ehat, llr=llr, iters=iters,
+               flags=flags, stats=stats)
+    pred2 = torch.zeros_like(pred)
+    dem.decode(det, shots, pred2, max_iter=T, alpha=alpha)          # compacted path
+    torch.cuda.synchronize()
+    out = dict(det=det.cpu().numpy().view(np.uint64), obs=obs.cpu().numpy().view(np.uint64),
+               pred=pred.cpu().numpy().view(np.uint64), pred2=pred2.cpu().numpy().view(np.uint64),
+               ehat=ehat.cpu().numpy().astype(bool), llr=llr.cpu().numpy(),
+               iters=iters.cpu().numpy(), flags=flags.cpu().numpy(), stats=tmcs.read_stats(stats),
+               dem=dem, circuit=c)
+    ne, ler, sig = tmcs.logical_error_rate(pred, obs, c.num_observables, shots)
+    out["n_err"] = ne
+    return out
+
+
+@pytest.mark.parametrize("name,spec,shots,T", CASES, ids=[c[0] for c in CASES])
+def test_decoder_parity(gpu_lib, name, spec, shots, T):
+    print(f"[decoder] {name} shots={shots} T={T}", flush=True)
+    r = _run_lib(gpu_lib, spec, shots, T)
+    oc = build_circuit(spec)
+    od = build_dem(oc)
+    synd = unpack_bits(r["det"], shots).T
+    obs = unpack_bits(r["obs"], shots).T[:, : oc.num_obs]
+    dec32 = Decoder(od.H(), od.priors(), od.L(), max_iter=T, dtype=np.float32)
+    o32 = dec32.decode(synd, chunk=64)
+    conv = (r["flags"] & 1).astype(bool)
+    osd = (r["flags"] & 2).astype(bool)
+    assert (r["iters"] == o32["iters"]).all()
+    assert (conv == o32["converged"]).all()
+    assert (osd == o32["osd"]).all()
+    assert (r["llr"] == o32["llr"].astype(np.float32)).all()          # bit-exact FP32
+    assert (r["ehat"] == o32["e_hat"]).all()                           # BP and OSD-0 corrections
+    assert not (r["flags"] & 4).any()
+    pred = unpack_bits(r["pred"], shots).T[:, : oc.num_obs]
+    assert (pred == o32["pred_obs"]).all()
+    assert (r["pred2"] == r["pred"]).all()
+    H = od.H().astype(np.int64)
+    assert ((r["ehat"].astype(np.int64) @ H.T) % 2 == synd).all()    # every correction explains s
+    n_err = int(logical_errors(o32["pred_obs"], obs).sum())
+    assert r["n_err"] == n_err
+    st = r["stats"]
+    assert st["shots"] == shots and st["osd"] == int(osd.sum())
+    assert st["converged"] == int(conv.sum())
+    # FP64 reference LLRs
+    dec64 = Decoder(od.H(), od.priors(), od.L(), max_iter=T, dtype=np.float64, use_osd=False)
+    o64 = dec64.decode(synd, chunk=64)
+    same = o64["iters"] == r["iters"]
+    assert same.mean() > 0.9
+    a64 = o64["llr"][same]
+    a32 = r["llr"][same].astype(np.float64)
+    big = np.abs(a64) >= 1e-3
+    rel = np.abs(a32 - a64)[big] / np.abs(a64)[big]
+    assert np.quantile(rel, 0.999) < 1e-4 if rel.size else True
+    hard_diff = (a32 < 0) != (a64 < 0)
+    assert not (hard_diff & big).any()
+
+
+def test_decoder_alpha_and_no_osd(gpu_lib):
+    spec = sc(5, NLCNOT, 3, 3, 4e-3, 2e-2)
+    r = _run_lib(gpu_lib, spec, 700, 25, alpha=0.75)
+    od = build_dem(build_circuit(spec))
+    synd = unpack_bits(r["det"], 700).T
+    o32 = Decoder(od.H(), od.priors(), od.L(), max_iter=25, alpha=0.75, dtype=np.float32).decode(synd)
+    assert (r["llr"] == o32["llr"].astype(np.float32)).all()
+    assert (r["ehat"] == o32["e_hat"]).all()
+
+
+def test_decoder_full_size_sampled(gpu_lib):
+    """sc5 non-local CNOT at 10^6 shots, bench launch shape: oracle on sampled shots."""
+    import torch
+    w = WORKLOADS["sc5_nlcnot"]
+    spec = w.specs[0]
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    N = w.shots
+    det, obs = c.alloc_outputs(N)
+    c.sample(w.seed, 0, 0, N, det, obs)
+    pred = torch.zeros_like(obs)
+    stats = gpu_lib.new_stats()
+    dem.decode(det, N, pred, max_iter=w.bp_iters, stats=stats)
+    ne, ler, sig = gpu_lib.logical_error_rate(pred, obs, c.num_observables, N)
+    torch.cuda.synchronize()
+    st = gpu_lib.read_stats(stats)
+    print(f"[decoder-full] errors={ne} ler={ler:.3e} stats={st}", flush=True)
+    assert st["shots"] == N and st["not_in_span"] == 0
+    d = det.cpu().numpy().view(np.uint64)
+    p = pred.cpu().numpy().view(np.uint64)
+    od = build_dem(build_circuit(spec))
+    dec = Decoder(od.H(), od.priors(), od.L(), max_iter=w.bp_iters, dtype=np.float32)
+    rng = np.random.default_rng(0)
+    words = np.sort(rng.choice(N // 64, size=12, replace=False))
+    for wd in words:
+        synd = unpack_bits(d[:, wd:wd + 1], 64).T
+        o = dec.decode(synd)
+        got = unpack_bits(p[:, wd:wd + 1], 64).T[:, : od.num_obs]
+        assert (got == o["pred_obs"]).all()

@@ -1,0 +1,82 @@
+"""CPU tests of the library's host side: ABI symbols, circuits and DEMs vs the oracle.
+
+These call only host-side entry points (circuit and DEM construction); nothing
+here touches a GPU.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.circuits import build_circuit
+from oracle.dem import build_dem
+from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    so = os.path.join(ROOT, "paper_2504_05611_amd", "libtmcs.so")
+    if not os.path.exists(so):
+        from paper_2504_05611_amd.build import build
+        build(verbose=False)
+    from paper_2504_05611_amd import tmcs
+    return tmcs
+
+
+def test_exports_every_declared_symbol(lib):
+    text = open(os.path.join(ROOT, "include", "tmcs.h")).read()
+    declared = set(re.findall(r"\b(tmcs_[a-z0-9_]+)\s*\(", text))
+    assert len(declared) >= 15
+    import ctypes
+    so = ctypes.CDLL(lib.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(so, name), name
+    assert declared == set(lib.EXPORTED)
+
+
+SPECS = [sc(3, MEMORY, 3, 0), sc(3, NLCNOT, 4, 3, 1e-3, 1e-2), sc(3, TELEPORT, 4, 3),
+         sc(5, NLCNOT, 5, 5, 1e-3, 1e-2), bb("bb18", NLCNOT, 4, 3), bb("bb18", TELEPORT, 4, 3),
+         bb("bb36", MEMORY, 2, 0, 2e-3)]
+
+
+@pytest.mark.parametrize("spec", SPECS, ids=lambda s: f"{s.code}{s.d if s.code == 'sc' else s.bb}-{s.op}")
+def test_circuit_and_dem_match_oracle(lib, spec):
+    lc = lib.Circuit(spec)
+    oc = build_circuit(spec)
+    assert lc.text() == oc.text()
+    k = oc.counts()
+    assert lc.info["detectors"] == k["dets"] and lc.info["noise_sites"] == k["sites"]
+    assert lc.info["gates_1q"] == k["q1"] and lc.info["gates_2q"] == k["q2"]
+    ld = lib.DEM(lc)
+    od = build_dem(oc)
+    assert ld.cols == od.num_cols and ld.rows == od.num_dets
+    h = ld.export()
+    assert (ld.H() == od.H()).all()
+    assert (h.priors == od.priors()).all()                      # same FP64 operations, same order
+    assert (h.obs_mask == np.array([c[1] for c in od.cols], dtype=np.uint64)).all()
+    from oracle.codes import rank
+    assert ld.info["rank"] == rank(od.H())
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", ["bb144_memory", "bb144_teleport"])
+def test_full_size_dem_matches_oracle(lib, name):
+    spec = WORKLOADS[name].specs[0]
+    lc = lib.Circuit(spec)
+    oc = build_circuit(spec)
+    assert lc.text() == oc.text()
+    ld = lib.DEM(lc)
+    od = build_dem(oc)
+    assert (ld.H() == od.H()).all() and (ld.export().priors == od.priors()).all()
+
+
+def test_invalid_specs_are_rejected(lib):
+    with pytest.raises(lib.TmcsError):
+        lib.Circuit(sc(4, MEMORY, 3, 0))                       # even distance
+    with pytest.raises(lib.TmcsError):
+        lib.Circuit(sc(3, NLCNOT, 3, 0))                       # no rounds after the CNOT
+    with pytest.raises(lib.TmcsError):
+        lib.Circuit(sc(3, MEMORY, 3, 0, p=0.7))
