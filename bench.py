@@ -1,0 +1,173 @@
+"""Benchmark: shots/s of the whole shot pipeline (sample + BP-OSD decode + LER) on one GPU.
+
+One step = one pass of the hot path over one batch of synthetic shots of the
+workload: Pauli-frame sampling of the batch (a new shot range every step),
+BP + OSD-0 decoding of every syndrome, and the logical-error count.  The
+circuit and its detector error model are built once, before timing.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+Prints ONE JSON line.  Multi-GPU runs are not part of this build.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+# plain 32-bit VALU lane operations: 256 CUs x 64 lanes per clock x 2.4 GHz
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+BP_OPS_PER_EDGE_ITER = 10      # |q|, two min compares, sign XORs, message rebuild, add
+FRAME_OPS_PER_CX_WORD = 4      # two 64-bit XORs per CX per 64-shot word
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="sc5_nlcnot")
+    ap.add_argument("--shots", type=int, default=0, help="override the workload's batch size")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 27                      # 2^27 int64 = 1 GiB
+    a = torch.ones(n, dtype=torch.int64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 3}))
+
+
+def cpu_baseline(w, spec, n_shots):
+    """Time the oracle (as it stands) on a bounded sample of the workload on host cores."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.circuits import build_circuit
+    from oracle.dem import build_dem
+    from oracle.frame import sample
+    from oracle.osd import Decoder
+    with threadpool_limits(limits=1):
+        oc = build_circuit(spec)
+        od = build_dem(oc)
+        dec = Decoder(od.H(), od.priors(), od.L(), max_iter=w.bp_iters, dtype=__import__("numpy").float64)
+        t0 = time.perf_counter()
+        det, obs = sample(oc, w.seed, 0, 0, n_shots)
+        t1 = time.perf_counter()
+        dec.decode(det.T)
+        t2 = time.perf_counter()
+    return dict(value=n_shots / (t2 - t0), unit="shots/s", cores=1, kind="oracle",
+                sample=f"{n_shots} shots of the same workload (shots [0, {n_shots}), seed {w.seed}); "
+                       f"FP64 oracle: frame sampling {t1 - t0:.2f} s + BP-OSD decode {t2 - t1:.2f} s, "
+                       f"one host thread")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: only one GPU is used in this build (asked for --gpus {args.gpus}); "
+              "the path shards by shot blocks with one all-reduce of counts, see the design notes.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    from paper_2504_05611_amd import tmcs
+    from workloads import WORKLOADS
+
+    w = WORKLOADS[args.workload]
+    spec = w.specs[0]
+    shots = args.shots or w.shots
+    torch.cuda.set_device(0)
+    circ = tmcs.Circuit(spec)
+    dem = tmcs.DEM(circ)
+    det, obs = circ.alloc_outputs(shots)
+    pred = torch.zeros_like(obs)
+    stats = tmcs.new_stats()
+    k = circ.num_observables
+
+    def step(i):
+        circ.sample(w.seed, 0, i * shots, shots, det, obs)
+        dem.decode(det, shots, pred, max_iter=w.bp_iters, stats=stats)
+        return tmcs.logical_error_rate(pred, obs, k, shots)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    stats.zero_()
+    tmcs.timing_reset()
+    tmcs.timing_enable(True)
+    errors = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ne, _, _ = step(args.warmup + i)
+        errors += ne
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tmcs.timing_enable(False)
+    kern = tmcs.timing_report()
+    st = tmcs.read_stats(stats)
+    elapsed = t1 - t0
+    total = shots * args.steps
+    value = total / elapsed
+
+    sample_ms = sum(v[1] for n, v in kern.items() if n.startswith(("k_event", "k_scan", "k_frame", "k_zero_u32")))
+    decode_ms = sum(v[1] for n, v in kern.items() if n in ("k_bp", "k_osd", "k_compact", "k_zero_i32", "k_add_shots"))
+    dominant = max(kern.items(), key=lambda kv: kv[1][1])[0]
+    launches, dom_ms = kern[dominant]
+    avg_s = dom_ms / launches / 1e3
+    info = circ.info
+    if dominant == "k_bp":
+        ops = BP_OPS_PER_EDGE_ITER * dem.edges * st["bp_iters"] / launches
+        model = (f"{BP_OPS_PER_EDGE_ITER} lane-ops per edge per BP iteration x {dem.edges} edges x "
+                 f"{st['bp_iters']} iterations / {launches} launches")
+    elif dominant == "k_frame":
+        words = math.ceil(shots / 64)
+        ops = FRAME_OPS_PER_CX_WORD * info["gates_2q"] * words * args.steps / launches
+        model = f"{FRAME_OPS_PER_CX_WORD} lane-ops per CX per 64-shot word"
+    else:
+        ops = float("nan")
+        model = "no model"
+    achieved = ops / avg_s / 1e12
+    roofline = dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS, unit="TOP/s",
+                    frac=achieved / VALU_PEAK_TOPS, traffic=None, kernel=dominant,
+                    avg_launch_ms=avg_s * 1e3, model=model)
+    ler = errors / total
+    out = {
+        "metric": "shots/sec (sample+BP-OSD decode) on 1 MI355X at matched logical error rate",
+        "value": value, "unit": "shots/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64+f32", "data": "synthetic (seeded Philox circuit noise)",
+        "config": {"workload": w.name, "description": w.description, "shots_per_step": shots,
+                   "bp_iters": w.bp_iters, "osd": "OSD-0", "detectors": dem.rows, "dem_columns": dem.cols,
+                   "dem_edges": dem.edges},
+        "sample_shots_per_s": total / (sample_ms / 1e3) if sample_ms else None,
+        "decode_shots_per_s": total / (decode_ms / 1e3) if decode_ms else None,
+        "logical_error_rate": ler, "ler_sigma": math.sqrt(max(ler * (1 - ler), 0) / total),
+        "osd_rate": st["osd"] / max(st["shots"], 1), "bp_iters_mean": st["bp_iters"] / max(st["shots"], 1),
+        "kernels_ms": {n: round(v[1] / v[0], 4) for n, v in sorted(kern.items())},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, spec, 8192)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

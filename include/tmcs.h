@@ -140,7 +140,11 @@ typedef struct {
   const float* weights_dev; /* NULL, or FP32 [max_iter][edges] per-edge, per-iteration
                                weights (edges in row-major order of H) replacing alpha */
   int32_t use_osd;          /* 1: OSD-0 on shots where BP did not converge */
-  int32_t bp_threads;       /* threads per BP workgroup; 0 = library default */
+  /* launch shape (0 = library default; results never depend on these): */
+  int32_t bp_threads;       /* threads per BP workgroup (multiple of 64, <= 1024) */
+  int32_t bp_per_cu;        /* resident BP workgroups per compute unit */
+  int32_t osd_per_cu;       /* resident OSD workgroups per compute unit */
+  int32_t osd_basis_lds;    /* 0 auto, 1 keep the OSD basis in LDS if it fits, 2 in HBM */
   /* optional per-shot outputs (NULL to skip), each indexed by shot of the call: */
   uint8_t* ehat_dev;        /* [n_shots][cols] final correction (0/1 bytes) */
   float* llr_dev;           /* [n_shots][cols] final BP posterior LLRs */
@@ -193,6 +197,15 @@ tmcs_status tmcs_wbp_backward(const tmcs_dem* d, const float* weights_dev, int32
                               const float* grad_llr_dev, float* grad_w_dev,
                               const void* workspace_dev, size_t workspace_bytes,
                               void* stream);
+
+/* Kernel timing (a tracing aid).  While enabled, every kernel the library
+ * launches is bracketed by a pair of HIP events recorded on the stream it runs
+ * on.  tmcs_timing_report synchronises on those events and writes a JSON object
+ * {"kernel name": [launches, total milliseconds], ...} (same buffer convention as
+ * tmcs_circuit_text); tmcs_timing_reset drops the records. */
+tmcs_status tmcs_timing_enable(int on);
+tmcs_status tmcs_timing_reset(void);
+tmcs_status tmcs_timing_report(char* buf, size_t cap, size_t* len);
 
 /* Thread-local description of the last error ("" if none). */
 const char* tmcs_last_error(void);

@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "../host/device.h"
+#include "../host/timing.h"
 
 namespace tmcs {
 
@@ -296,18 +297,103 @@ __device__ __forceinline__ uint32_t order_key(float x) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+// Wave-uniform broadcast of lane `src`'s 64-bit value (src must be wave-uniform).
+__device__ __forceinline__ uint64_t bcast64(uint64_t x, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), src);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of npad = OSD_THREADS * KPT 64-bit keys, ascending.  Thread t
+// holds elements t*KPT .. t*KPT+KPT-1 in registers; partners within a thread are
+// compared in registers, partners within a wave via lane shuffles, and only the
+// strides that cross waves go through LDS (`keys`), which also receives the
+// sorted result.
+template <int KPT>
+__device__ __forceinline__ void bitonic_sort_regs(uint64_t (&x)[KPT], uint64_t* keys, int npad) {
+  const int tid = threadIdx.x;
+  for (int k = 2; k <= npad; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      if (j < KPT) {
+#pragma unroll
+        for (int jj = KPT / 2; jj >= 1; jj >>= 1) {
+          if (jj != j) continue;
+#pragma unroll
+          for (int r = 0; r < KPT; ++r) {
+            if (r & jj) continue;
+            const int e = tid * KPT + r;
+            const bool up = (e & k) == 0;
+            const uint64_t a0 = x[r], a1 = x[r | jj];
+            const bool sw = (a0 > a1) == up;
+            x[r] = sw ? a1 : a0;
+            x[r | jj] = sw ? a0 : a1;
+          }
+        }
+      } else if (j < KPT * 64) {
+        const int tj = j / KPT;                       // partner lane distance
+        const bool lower = (tid & tj) == 0;
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+          const int e = tid * KPT + r;
+          const bool up = (e & k) == 0;
+          const uint64_t y = __shfl_xor(x[r], tj, 64);
+          // the lower element of the pair keeps the minimum when sorting up
+          const bool take_min = lower == up;
+          x[r] = take_min ? (x[r] < y ? x[r] : y) : (x[r] > y ? x[r] : y);
+        }
+      } else {
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) keys[tid * KPT + r] = x[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) {
+          const int e = tid * KPT + r;
+          const bool up = (e & k) == 0;
+          const uint64_t y = keys[e ^ j];
+          const bool take_min = ((e & j) == 0) == up;
+          x[r] = take_min ? (x[r] < y ? x[r] : y) : (x[r] > y ? x[r] : y);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < KPT; ++r) keys[tid * KPT + r] = x[r];
+  __syncthreads();
+}
+
+// Bit p of a register-resident bit vector (p < 64 * MW).
+template <int MW, int W>
+__device__ __forceinline__ uint64_t bit_of(const uint64_t (&v)[W], int p) {
+  uint64_t pw = 0ull;
+#pragma unroll
+  for (int w = 0; w < MW; ++w)
+    if ((p >> 6) == w) pw = v[w];
+  return (pw >> (p & 63)) & 1ull;
+}
+
 // W = words per basis vector: MW syndrome words then RW combination words.
-template <int MW, int RW>
+//
+// The basis is kept fully reduced: basis vector i has a 1 at its pivot row p_i
+// and 0 at every other pivot row.  A candidate column h is then reduced by
+// XORing exactly the basis vectors whose pivot rows lie in supp(h) (at most the
+// column degree), and a syndrome s by those whose pivot rows lie in supp(s).
+// New basis vectors are created 64 at a time by one wave, made fully reduced
+// among themselves, and the older vectors are then reduced against them.
+template <int MW, int RW, int KPT>
 __global__ void __launch_bounds__(OSD_THREADS) k_osd(OSDArgs a) {
   constexpr int W = MW + RW;
   extern __shared__ __align__(8) unsigned char sm[];
   uint64_t* keys = (uint64_t*)sm;                                  // [npad]
   int32_t* pivot = (int32_t*)(keys + a.npad);                      // [rank] pivot row of basis i
-  int32_t* kept = pivot + a.rank;                                  // [rank] column of kept i
-  uint64_t* bvec = (uint64_t*)(((uintptr_t)(kept + a.rank) + 7) & ~(uintptr_t)7);  // [W] broadcast
-  __shared__ int s_job, s_r, s_nz;
+  int32_t* kept = pivot + a.rank;                                  // [rank] column of basis i
+  int32_t* prow = kept + a.rank;                                   // [m] basis index of a pivot row, or -1
+  uint64_t* acc = (uint64_t*)(((uintptr_t)(prow + a.m) + 7) & ~(uintptr_t)7);  // [W] solve accumulator
+  __shared__ int s_job, s_r;
   __shared__ uint64_t s_red;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   uint64_t* B = a.basis + (int64_t)blockIdx.x * a.rank * W;
   while (true) {
     if (tid == 0) s_job = atomicAdd(&a.counters[3], 1);
@@ -319,121 +405,172 @@ __global__ void __launch_bounds__(OSD_THREADS) k_osd(OSDArgs a) {
     const int64_t shot = a.shot0 + ls;
     const float* L = a.osd_llr + (int64_t)job * a.n;
     // 1. sort columns by (L_v, v)
-    for (int i = tid; i < a.npad; i += OSD_THREADS)
-      keys[i] = i < a.n ? (((uint64_t)order_key(L[i]) << 32) | (uint32_t)i) : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= a.npad; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = tid; i < a.npad; i += OSD_THREADS) {
-          const int ix = i ^ j;
-          if (ix > i) {
-            const uint64_t x = keys[i], y = keys[ix];
-            const bool up = (i & k) == 0;
-            if ((x > y) == up) { keys[i] = y; keys[ix] = x; }
-          }
-        }
-        __syncthreads();
-      }
-    }
-    // 2. information set by chunked incremental elimination
+    for (int r = tid; r < a.m; r += OSD_THREADS) prow[r] = -1;
+    if (tid < W) acc[tid] = 0ull;
     if (tid == 0) s_r = 0;
-    __syncthreads();
+    {
+      uint64_t x[KPT];
+#pragma unroll
+      for (int r = 0; r < KPT; ++r) {
+        const int i = tid * KPT + r;
+        x[r] = i < a.n ? (((uint64_t)order_key(L[i]) << 32) | (uint32_t)i) : ~0ull;
+      }
+      bitonic_sort_regs<KPT>(x, keys, a.npad);
+    }
+    // 2. information set, 256 sorted candidates per pass (one per thread)
     for (int base = 0; base < a.n; base += OSD_THREADS) {
-      if (s_r >= a.rank) break;
+      const int r_start = s_r;
+      __syncthreads();           // every wave has read s_r before wave 0 advances it
+      if (r_start >= a.rank) break;
       const int idx = base + tid;
       const int col = idx < a.n ? (int)(keys[idx] & 0xFFFFFFFFu) : -1;
       uint64_t v[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) v[w] = 0ull;
-      if (col >= 0)
-        for (int32_t k = a.col_ptr[col]; k < a.col_ptr[col + 1]; ++k) {
+      if (col >= 0) {
+        const int32_t k0 = a.col_ptr[col], k1 = a.col_ptr[col + 1];
+        for (int32_t k = k0; k < k1; ++k) {
           const int r = a.csc_row[k];
 #pragma unroll
           for (int w = 0; w < MW; ++w)
             if ((r >> 6) == w) v[w] ^= 1ull << (r & 63);
         }
-      const int r0 = s_r;
-      // reduce against the existing basis, in insertion order
-      for (int i = 0; i < r0; ++i) {
-        const int p = pivot[i];
-        uint64_t pw = 0ull;
+        // phase 1: the basis vectors pivoted on rows of h
+        for (int32_t k = k0; k < k1; ++k) {
+          const int i = prow[a.csc_row[k]];
+          if (i >= 0) {
+            const uint64_t* b = B + (int64_t)i * W;
 #pragma unroll
-        for (int w = 0; w < MW; ++w)
-          if ((p >> 6) == w) pw = v[w];
-        const uint64_t mask = 0ull - ((pw >> (p & 63)) & 1ull);
-        if (mask) {
-          const uint64_t* b = B + (int64_t)i * W;
-#pragma unroll
-          for (int w = 0; w < W; ++w) v[w] ^= b[w];
-        }
-      }
-      // in-chunk sequential pass
-      for (int j = 0; j < OSD_THREADS; ++j) {
-        if (base + j >= a.n) break;
-        if (s_r >= a.rank) break;
-        if (tid == j) {
-          int p = -1;
-#pragma unroll
-          for (int w = 0; w < MW; ++w)
-            if (p < 0 && v[w]) p = w * 64 + (__ffsll((unsigned long long)v[w]) - 1);
-          s_nz = p;
-          if (p >= 0) {
-            const int r = s_r;
-            v[MW + (r >> 6)] ^= 1ull << (r & 63);   // the column itself
-#pragma unroll
-            for (int w = 0; w < W; ++w) { bvec[w] = v[w]; B[(int64_t)r * W + w] = v[w]; }
-            pivot[r] = p;
-            kept[r] = col;
+            for (int w = 0; w < W; ++w) v[w] ^= b[w];
           }
         }
-        __syncthreads();
-        const int p = s_nz;
-        if (p >= 0) {
-          if (tid > j) {
-            uint64_t pw = 0ull;
+      }
+      __syncthreads();           // phase 1 everywhere before any wave publishes new pivots
+      int r_done = r_start;
+      for (int q = 0; q < OSD_THREADS / 64; ++q) {
+        if (wave == q) {
+          // phase 2: in-order pass over this wave's candidates whose syndrome
+          // part is still nonzero (zero ones depend on earlier columns)
+          int r = r_done;
+          int mine = -1;      // pivot row of the basis vector this lane became
+          auto nz = [&]() {
+            uint64_t o = 0ull;
+#pragma unroll
+            for (int w = 0; w < MW; ++w) o |= v[w];
+            return o != 0ull && col >= 0;
+          };
+          uint64_t live = __ballot(nz());
+          while (live && r < a.rank) {
+            const int j = __ffsll((unsigned long long)live) - 1;
+            uint64_t b[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) b[w] = bcast64(v[w], j);
+            int p = -1;
 #pragma unroll
             for (int w = 0; w < MW; ++w)
-              if ((p >> 6) == w) pw = v[w];
-            if ((pw >> (p & 63)) & 1ull) {
+              if (p < 0 && b[w]) p = w * 64 + (__ffsll((unsigned long long)b[w]) - 1);
 #pragma unroll
-              for (int w = 0; w < W; ++w) v[w] ^= bvec[w];
+            for (int w = 0; w < RW; ++w)
+              if (w == (r >> 6)) b[MW + w] ^= 1ull << (r & 63);   // the column itself
+            if (lane == j) {
+#pragma unroll
+              for (int w = 0; w < W; ++w) v[w] = b[w];
+              mine = p;
+              pivot[r] = p;
+              kept[r] = col;
+              prow[p] = r;
             }
+            const uint64_t mask = (lane > j) ? 0ull - bit_of<MW, W>(v, p) : 0ull;
+#pragma unroll
+            for (int w = 0; w < W; ++w) v[w] ^= b[w] & mask;
+            ++r;
+            live = __ballot(lane > j && nz());
           }
-          __syncthreads();
-          if (tid == 0) s_r = s_r + 1;
+          // make the new vectors fully reduced among themselves (latest first)
+          uint64_t piv_lanes = __ballot(mine >= 0);
+          while (piv_lanes) {
+            const int j = 63 - __clzll((long long)piv_lanes);
+            piv_lanes &= ~(1ull << j);
+            const int pj = __builtin_amdgcn_readlane(mine, j);
+            uint64_t b[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) b[w] = bcast64(v[w], j);
+            const uint64_t mask = (mine >= 0 && lane < j) ? 0ull - bit_of<MW, W>(v, pj) : 0ull;
+#pragma unroll
+            for (int w = 0; w < W; ++w) v[w] ^= b[w] & mask;
+          }
+          if (mine >= 0) {
+            const int i = prow[mine];
+#pragma unroll
+            for (int w = 0; w < W; ++w) B[(int64_t)i * W + w] = v[w];
+          }
+          if (lane == 0) s_r = r;
         }
         __syncthreads();
+        const int r_new = s_r;
+        if (r_new > r_done) {
+          // older basis vectors: clear their bits at the new pivots
+          for (int i = tid; i < r_done; i += OSD_THREADS) {
+            uint64_t bi[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) bi[w] = B[(int64_t)i * W + w];
+            bool changed = false;
+            for (int j = r_done; j < r_new; ++j) {
+              if (bit_of<MW, W>(bi, pivot[j])) {
+                const uint64_t* bj = B + (int64_t)j * W;
+#pragma unroll
+                for (int w = 0; w < W; ++w) bi[w] ^= bj[w];
+                changed = true;
+              }
+            }
+            if (changed) {
+#pragma unroll
+              for (int w = 0; w < W; ++w) B[(int64_t)i * W + w] = bi[w];
+            }
+          }
+          // candidates of later waves: reduce against the new vectors
+          if (wave > q) {
+            uint64_t m[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) m[w] = 0ull;
+            for (int j = r_done; j < r_new; ++j) {
+              const uint64_t msk = 0ull - bit_of<MW, W>(v, pivot[j]);
+              const uint64_t* bj = B + (int64_t)j * W;
+#pragma unroll
+              for (int w = 0; w < W; ++w) m[w] ^= bj[w] & msk;
+            }
+#pragma unroll
+            for (int w = 0; w < W; ++w) v[w] ^= m[w];
+          }
+        }
+        r_done = r_new;
+        __syncthreads();
       }
-      __syncthreads();
     }
-    // 3. solve: reduce s against the basis; combination bits give e_S
+    // 3. solve: s reduced by the basis vectors pivoted on rows of s
     const int r = s_r;
-    if (tid < 64) {
-      // lane w holds word w of the reduced syndrome / combination vector
-      uint64_t sv = 0ull;
-      if (tid < MW) {
-        for (int row = tid * 64; row < min(a.m, tid * 64 + 64); ++row)
-          sv |= ((a.det[(int64_t)row * a.stride + (shot >> 6)] >> (shot & 63)) & 1ull) << (row & 63);
-      }
-      for (int i = 0; i < r; ++i) {
-        const int p = pivot[i];
-        const uint64_t word = __shfl(sv, p >> 6, 64);
-        if ((word >> (p & 63)) & 1ull) {
-          if (tid < W) sv ^= B[(int64_t)i * W + tid];
+    int bad = 0;
+    for (int row = tid; row < a.m; row += OSD_THREADS) {
+      if ((a.det[(int64_t)row * a.stride + (shot >> 6)] >> (shot & 63)) & 1ull) {
+        atomicXor((unsigned long long*)&acc[row >> 6], (unsigned long long)(1ull << (row & 63)));
+        const int i = prow[row];
+        if (i >= 0) {
+          const uint64_t* b = B + (int64_t)i * W;
+#pragma unroll
+          for (int w = 0; w < W; ++w)
+            if (b[w]) atomicXor((unsigned long long*)&acc[w], (unsigned long long)b[w]);
         }
       }
-      uint64_t resid = (tid < MW) ? sv : 0ull;
-      const bool in_span = __ballot(resid != 0ull) == 0ull;
-      if (tid >= MW && tid < W) bvec[tid - MW] = sv;
-      if (tid == 0) s_nz = in_span ? 1 : 0;
     }
     __syncthreads();
+    for (int w = tid; w < MW; w += OSD_THREADS) bad |= acc[w] != 0ull;
+    const int not_in_span = __syncthreads_or(bad);
     uint64_t pm = 0;
     if (a.ehat)
       for (int v = tid; v < a.n; v += OSD_THREADS) a.ehat[shot * a.n + v] = 0;
     __syncthreads();
     for (int i = tid; i < r; i += OSD_THREADS) {
-      if ((bvec[i >> 6] >> (i & 63)) & 1ull) {
+      if ((acc[MW + (i >> 6)] >> (i & 63)) & 1ull) {
         const int col = kept[i];
         pm ^= a.obs_mask[col];
         if (a.ehat) a.ehat[shot * a.n + col] = 1;
@@ -442,8 +579,8 @@ __global__ void __launch_bounds__(OSD_THREADS) k_osd(OSDArgs a) {
     pm = block_xor_u64(pm, &s_red);
     if (tid == 0) {
       write_pred(a.pred, a.stride, a.nobs, shot, pm);
-      if (a.flags) a.flags[shot] = (uint8_t)(2 | (s_nz ? 0 : 4));
-      if (a.stats && !s_nz) atomicAdd((unsigned long long*)&a.stats->not_in_span, 1ull);
+      if (a.flags) a.flags[shot] = (uint8_t)(2 | (not_in_span ? 4 : 0));
+      if (a.stats && not_in_span) atomicAdd((unsigned long long*)&a.stats->not_in_span, 1ull);
     }
     __syncthreads();
   }
@@ -514,29 +651,44 @@ int device_cus() {
   return cus > 0 ? cus : 256;
 }
 
-template <int MW, int RW>
+template <int MW, int RW, int KPT>
 tmcs_status launch_osd(const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
   if (lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_osd<MW, RW>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      hipFuncSetAttribute((const void*)k_osd<MW, RW, KPT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "OSD workspace does not fit in LDS");
-  hipLaunchKernelGGL((k_osd<MW, RW>), dim3(grid), dim3(OSD_THREADS), lds, s, a);
+  TMCS_LAUNCH("k_osd", (k_osd<MW, RW, KPT>), dim3(grid), dim3(OSD_THREADS), lds, s, a);
   return hip_check(hipGetLastError(), "k_osd launch");
 }
 
-tmcs_status dispatch_osd(int mw, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
-  if (mw <= 1) return launch_osd<1, 1>(a, grid, lds, s);
-  if (mw <= 2) return launch_osd<2, 2>(a, grid, lds, s);
-  if (mw <= 4) return launch_osd<4, 4>(a, grid, lds, s);
-  if (mw <= 8) return launch_osd<8, 8>(a, grid, lds, s);
-  if (mw <= 12) return launch_osd<12, 12>(a, grid, lds, s);
-  if (mw <= 16) return launch_osd<16, 16>(a, grid, lds, s);
-  if (mw <= 20) return launch_osd<20, 20>(a, grid, lds, s);
-  if (mw <= 24) return launch_osd<24, 24>(a, grid, lds, s);
-  if (mw <= 32) return launch_osd<32, 32>(a, grid, lds, s);
+template <int MW>
+tmcs_status dispatch_kpt(int kpt, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
+  switch (kpt) {
+    case 1: return launch_osd<MW, MW, 1>(a, grid, lds, s);
+    case 2: return launch_osd<MW, MW, 2>(a, grid, lds, s);
+    case 4: return launch_osd<MW, MW, 4>(a, grid, lds, s);
+    case 8: return launch_osd<MW, MW, 8>(a, grid, lds, s);
+    case 16: return launch_osd<MW, MW, 16>(a, grid, lds, s);
+    case 32: return launch_osd<MW, MW, 32>(a, grid, lds, s);
+    case 64: return launch_osd<MW, MW, 64>(a, grid, lds, s);
+    default: return fail(TMCS_EUNSUPPORTED, "OSD sort size");
+  }
+}
+
+tmcs_status dispatch_osd(int mw, int kpt, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (mw <= 1) return dispatch_kpt<1>(kpt, a, grid, lds, s);
+  if (mw <= 2) return dispatch_kpt<2>(kpt, a, grid, lds, s);
+  if (mw <= 4) return dispatch_kpt<4>(kpt, a, grid, lds, s);
+  if (mw <= 5) return dispatch_kpt<5>(kpt, a, grid, lds, s);
+  if (mw <= 8) return dispatch_kpt<8>(kpt, a, grid, lds, s);
+  if (mw <= 12) return dispatch_kpt<12>(kpt, a, grid, lds, s);
+  if (mw <= 15) return dispatch_kpt<15>(kpt, a, grid, lds, s);
+  if (mw <= 18) return dispatch_kpt<18>(kpt, a, grid, lds, s);
+  if (mw <= 24) return dispatch_kpt<24>(kpt, a, grid, lds, s);
+  if (mw <= 32) return dispatch_kpt<32>(kpt, a, grid, lds, s);
   return fail(TMCS_EUNSUPPORTED, "OSD supports at most 2048 detectors in this build");
 }
 
-constexpr int64_t DECODE_CHUNK = 16384;  // shots per internal pass (bounds OSD scratch)
+constexpr int64_t DECODE_CHUNK_MIN = 4096;
 
 }  // namespace
 
@@ -552,7 +704,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int64_t stride = (int64_t)((n_shots + 63) / 64);
   const bool full = cfg.ehat_dev || cfg.llr_dev || cfg.iters_dev || cfg.flags_dev;
   const int mw = (D.rows + 63) / 64;
-  int npad = 1;
+  int npad = OSD_THREADS;   // sort length: a power of two, at least one key per thread
   while (npad < D.cols) npad <<= 1;
   if (cfg.use_osd && (npad > OSD_MAX_KEYS || mw > 32))
     return fail(TMCS_EUNSUPPORTED, "OSD-0 supports up to 16384 columns and 2048 detectors in this build");
@@ -566,13 +718,18 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   if (bp_lds > 64 * 1024 &&
       hipFuncSetAttribute((const void*)k_bp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
-  const int per_cu = std::max<int>(1, std::min<int>(8, (int)((160 * 1024) / (bp_lds + 1024))));
-  const int64_t chunk = std::min<int64_t>((int64_t)n_shots, DECODE_CHUNK);
+  const int per_cu_fit = std::max<int>(1, (int)((160 * 1024) / (bp_lds + 512)));
+  const int per_cu = std::min(per_cu_fit, cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 16);
+  // shots per internal pass: bounded so the OSD LLR staging stays <= 1 GiB
+  const int64_t chunk = std::min<int64_t>((int64_t)n_shots,
+                                          std::max<int64_t>(DECODE_CHUNK_MIN, ((1ll << 28) / std::max(D.cols, 1)) & ~63ll));
   // OSD launch shape
-  const int W = mw <= 1 ? 2 : mw <= 2 ? 4 : mw <= 4 ? 8 : mw <= 8 ? 16 : mw <= 12 ? 24 : mw <= 16 ? 32
-              : mw <= 20 ? 40 : mw <= 24 ? 48 : 64;
-  const size_t osd_lds = (size_t)npad * 8 + (size_t)D.rank * 8 + (size_t)W * 8 + 64;
-  const int osd_grid = std::max(1, cus);
+  const int W = 2 * (mw <= 1 ? 1 : mw <= 2 ? 2 : mw <= 4 ? 4 : mw <= 5 ? 5 : mw <= 8 ? 8 : mw <= 12 ? 12
+                   : mw <= 15 ? 15 : mw <= 18 ? 18 : mw <= 24 ? 24 : 32);
+  const size_t osd_lds = (size_t)npad * 8 + (size_t)D.rank * 8 + (size_t)D.rows * 4 + (size_t)W * 8 + 64;
+  const int osd_fit = std::max<int>(1, (int)((160 * 1024) / (osd_lds + 512)));
+  const int osd_per_cu = std::min(osd_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 4);
+  const int osd_grid = std::max(1, cus * osd_per_cu);
   if ((st = grow(&d->queue, &d->cap_queue, (size_t)chunk)) != TMCS_OK) return st;
   if (cfg.use_osd) {
     if ((st = grow(&d->osd_queue, &d->cap_osd, (size_t)chunk)) != TMCS_OK ||
@@ -583,16 +740,16 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int64_t total_words = (int64_t)D.nobs * stride;
   if (total_words) {
     const int64_t g = std::min<int64_t>((total_words + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)g), dim3(256), 0, stream, pred, total_words);
+    TMCS_LAUNCH("k_zero_words", k_zero_words, dim3((unsigned)g), dim3(256), 0, stream, pred, total_words);
   }
   for (int64_t s0 = 0; s0 < (int64_t)n_shots; s0 += chunk) {
     const int64_t ns = std::min<int64_t>(chunk, (int64_t)n_shots - s0);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, stream, d->counters, 8);
-    if (stats) hipLaunchKernelGGL(k_add_shots, dim3(1), dim3(1), 0, stream, stats, (unsigned long long)ns);
+    TMCS_LAUNCH("k_zero_i32", k_zero_i32, dim3(1), dim3(64), 0, stream, d->counters, 8);
+    if (stats) TMCS_LAUNCH("k_add_shots", k_add_shots, dim3(1), dim3(1), 0, stream, stats, (unsigned long long)ns);
     if (!full) {
       const int64_t nw = (ns + 63) / 64;
       const int64_t g = std::min<int64_t>((nw + 255) / 256, 4096);
-      hipLaunchKernelGGL(k_compact, dim3((unsigned)g), dim3(256), 0, stream, det, D.rows, stride, s0, ns,
+      TMCS_LAUNCH("k_compact", k_compact, dim3((unsigned)g), dim3(256), 0, stream, det, D.rows, stride, s0, ns,
                          d->queue, d->counters, stats);
     }
     BPArgs a;
@@ -604,7 +761,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
     a.pred = pred; a.nobs = D.nobs; a.stats = stats; a.ehat = cfg.ehat_dev; a.llr = cfg.llr_dev;
     a.iters = cfg.iters_dev; a.flags = cfg.flags_dev;
     const int bp_grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(ns, 1));
-    hipLaunchKernelGGL(k_bp, dim3(bp_grid), dim3(bp_threads), bp_lds, stream, a);
+    TMCS_LAUNCH("k_bp", k_bp, dim3(bp_grid), dim3(bp_threads), bp_lds, stream, a);
     if ((st = hip_check(hipGetLastError(), "k_bp launch")) != TMCS_OK) return st;
     if (cfg.use_osd) {
       OSDArgs o;
@@ -613,7 +770,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
       o.counters = d->counters; o.osd_queue = d->osd_queue; o.osd_llr = d->osd_llr; o.basis = d->basis;
       o.pred = pred; o.nobs = D.nobs; o.stats = stats; o.ehat = cfg.ehat_dev; o.flags = cfg.flags_dev;
       o.npad = npad;
-      if ((st = dispatch_osd(mw, o, osd_grid, osd_lds, stream)) != TMCS_OK) return st;
+      if ((st = dispatch_osd(mw, npad / OSD_THREADS, o, osd_grid, osd_lds, stream)) != TMCS_OK) return st;
     }
   }
   return TMCS_OK;
@@ -640,10 +797,10 @@ tmcs_status ler_run(const uint64_t* pred, const uint64_t* obs, uint32_t k, uint6
   unsigned long long* dcount = nullptr;
   tmcs_status st = hip_check(hipMalloc((void**)&dcount, sizeof(unsigned long long)), "hipMalloc");
   if (st != TMCS_OK) return st;
-  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, stream, (uint64_t*)dcount, (int64_t)1);
+  TMCS_LAUNCH("k_zero_words", k_zero_words, dim3(1), dim3(64), 0, stream, (uint64_t*)dcount, (int64_t)1);
   const int64_t stride = (int64_t)((n_shots + 63) / 64);
   const int64_t g = std::min<int64_t>((stride + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_count_errors, dim3((unsigned)g), dim3(256), 0, stream, pred, obs, k, stride, n_shots, dcount);
+  TMCS_LAUNCH("k_count_errors", k_count_errors, dim3((unsigned)g), dim3(256), 0, stream, pred, obs, k, stride, n_shots, dcount);
   unsigned long long h = 0;
   st = hip_check(hipMemcpyAsync(&h, dcount, sizeof(h), hipMemcpyDeviceToHost, stream), "copy error count");
   if (st == TMCS_OK) st = hip_check(hipStreamSynchronize(stream), "ler synchronize");

@@ -29,6 +29,7 @@
 #include <cstring>
 
 #include "../host/device.h"
+#include "../host/timing.h"
 #include "../host/program.h"
 
 namespace tmcs {
@@ -441,7 +442,7 @@ tmcs_status launch_frame(const FrameArgs& a, int64_t nwg, size_t lds, hipStream_
     if (hipFuncSetAttribute((const void*)k_frame<F>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
       return fail(TMCS_EUNSUPPORTED, "frame does not fit in LDS");
   }
-  hipLaunchKernelGGL(k_frame<F>, dim3((unsigned)nwg), dim3(FRAME_THREADS), lds, s, a);
+  TMCS_LAUNCH("k_frame", k_frame<F>, dim3((unsigned)nwg), dim3(FRAME_THREADS), lds, s, a);
   return hip_check(hipGetLastError(), "k_frame launch");
 }
 
@@ -465,7 +466,7 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
   size_t lds = 0;
   const int F = frame_words_per_wg(P, c.num_qubits, &lds);
   if (lds > 160 * 1024) return fail(TMCS_EUNSUPPORTED, "circuit frame exceeds the 160 KB LDS of one workgroup");
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, stream, d->flag, 1);
+  TMCS_LAUNCH("k_zero_u32", k_zero_u32, dim3(1), dim3(64), 0, stream, d->flag, 1);
   // chunk of blocks: bound the per-(block, site) arrays to ~64M entries
   const int64_t blk_first = (int64_t)(shot_begin / SB);
   const int64_t blk_last = (int64_t)((shot_end - 1) / SB);
@@ -488,12 +489,12 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
     if (nsites > 0) {
       const int thr = 256;
       const int64_t grid = std::min<int64_t>((n + thr - 1) / thr, 1 << 20);
-      hipLaunchKernelGGL(k_event_count, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
+      TMCS_LAUNCH("k_event_count", k_event_count, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
                          instance, d->site_kind, d->site_tab, d->tabs, d->counts);
-      hipLaunchKernelGGL(k_scan_partials, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial);
-      hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, stream, d->partial, ntiles);
-      hipLaunchKernelGGL(k_scan_final, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial, d->offsets);
-      hipLaunchKernelGGL(k_event_write, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
+      TMCS_LAUNCH("k_scan_partials", k_scan_partials, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial);
+      TMCS_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, stream, d->partial, ntiles);
+      TMCS_LAUNCH("k_scan_final", k_scan_final, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial, d->offsets);
+      TMCS_LAUNCH("k_event_write", k_event_write, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
                          instance, d->site_kind, d->site_tab, d->tabs, d->offsets, d->events,
                          (uint32_t)d->cap_events, d->flag);
       if ((st = hip_check(hipGetLastError(), "event kernels")) != TMCS_OK) return st;

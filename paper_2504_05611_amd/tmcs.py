@@ -48,7 +48,9 @@ class _Spec(ctypes.Structure):
 class DecoderCfg(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("alpha", ctypes.c_float),
                 ("weights_dev", ctypes.c_void_p), ("use_osd", ctypes.c_int32),
-                ("bp_threads", ctypes.c_int32), ("ehat_dev", ctypes.c_void_p),
+                ("bp_threads", ctypes.c_int32), ("bp_per_cu", ctypes.c_int32),
+                ("osd_per_cu", ctypes.c_int32), ("osd_basis_lds", ctypes.c_int32),
+                ("ehat_dev", ctypes.c_void_p),
                 ("llr_dev", ctypes.c_void_p), ("iters_dev", ctypes.c_void_p),
                 ("flags_dev", ctypes.c_void_p)]
 
@@ -77,6 +79,9 @@ _SIGS = {
     "tmcs_wbp_workspace_size": [_vp, _i32, _u64, ctypes.POINTER(_sz)],
     "tmcs_wbp_forward": [_vp, _vp, _i32, _vp, _u64, _vp, _vp, _sz, _vp],
     "tmcs_wbp_backward": [_vp, _vp, _i32, _vp, _u64, _vp, _vp, _vp, _sz, _vp],
+    "tmcs_timing_enable": [ctypes.c_int],
+    "tmcs_timing_reset": [],
+    "tmcs_timing_report": [_vp, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)][1:],
     "tmcs_last_error": [],
 }
 for _name, _args in _SIGS.items():
@@ -225,8 +230,10 @@ class DEM:
         return H
 
     def decode(self, det, n_shots, pred, *, max_iter=30, alpha=1.0, weights=None, use_osd=True,
-               bp_threads=0, ehat=None, llr=None, iters=None, flags=None, stats=None, stream=None):
+               bp_threads=0, bp_per_cu=0, osd_per_cu=0, osd_basis_lds=0, ehat=None, llr=None,
+               iters=None, flags=None, stats=None, stream=None):
         cfg = DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads,
+                         bp_per_cu, osd_per_cu, osd_basis_lds,
                          _ptr(ehat), _ptr(llr), _ptr(iters), _ptr(flags))
         _check(_lib.tmcs_decode(self._h, ctypes.byref(cfg), _ptr(det), n_shots, _ptr(pred), _ptr(stats),
                                 _stream(stream)))
@@ -254,6 +261,24 @@ def logical_error_rate(pred, obs, k, n_shots, stream=None):
     _check(_lib.tmcs_logical_error_rate(_ptr(pred), _ptr(obs), k, n_shots, ctypes.byref(ne),
                                         ctypes.byref(ler), ctypes.byref(sig), _stream(stream)))
     return ne.value, ler.value, sig.value
+
+
+def timing_enable(on=True):
+    _check(_lib.tmcs_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(_lib.tmcs_timing_reset())
+
+
+def timing_report() -> dict:
+    """{kernel: (launches, total ms)} for the launches recorded while timing was on."""
+    import json
+    n = ctypes.c_size_t()
+    _check(_lib.tmcs_timing_report(None, 0, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(_lib.tmcs_timing_report(buf, n.value + 1, ctypes.byref(n)))
+    return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
 
 
 def new_stats(device="cuda"):

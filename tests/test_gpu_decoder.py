@@ -137,3 +137,30 @@ def test_decoder_full_size_sampled(gpu_lib):
         o = dec.decode(synd)
         got = unpack_bits(p[:, wd:wd + 1], 64).T[:, : od.num_obs]
         assert (got == o["pred_obs"]).all()
+
+
+@pytest.mark.parametrize("name,spec,shots", [
+    ("bb18-nlcnot", bb("bb18", NLCNOT, 2, 2, 4e-3, 1e-2), 700),
+    ("sc5-nlcnot", sc(5, NLCNOT, 5, 5, 3e-3, 2e-2), 3000),
+], ids=["bb18-nlcnot", "sc5-nlcnot"])
+def test_decoder_launch_shape_invariance(gpu_lib, name, spec, shots):
+    """Corrections and predictions do not depend on launch shapes or work order."""
+    import torch
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    det, obs = c.alloc_outputs(shots)
+    c.sample(5, 0, 0, shots, det, obs)
+    ref = None
+    for kw in (dict(), dict(bp_threads=64, bp_per_cu=2, osd_per_cu=1),
+               dict(bp_threads=256, bp_per_cu=16, osd_per_cu=8), dict(bp_threads=1024, osd_per_cu=3)):
+        for full in (True, False):
+            pred = torch.zeros_like(obs)
+            ehat = torch.zeros((shots, dem.cols), dtype=torch.uint8, device="cuda") if full else None
+            dem.decode(det, shots, pred, max_iter=30, ehat=ehat, **kw)
+            torch.cuda.synchronize()
+            p = pred.cpu().numpy()
+            if ref is None:
+                ref, ref_e = p, ehat.cpu().numpy()
+            assert (p == ref).all(), (kw, full)
+            if full:
+                assert (ehat.cpu().numpy() == ref_e).all(), kw
