@@ -144,7 +144,7 @@ typedef struct {
   int32_t bp_threads;       /* threads per BP workgroup (multiple of 64, <= 1024) */
   int32_t bp_per_cu;        /* resident BP workgroups per compute unit */
   int32_t osd_per_cu;       /* resident OSD workgroups per compute unit */
-  int32_t osd_basis_lds;    /* 0 auto, 1 keep the OSD basis in LDS if it fits, 2 in HBM */
+  int32_t bp_slots;         /* shots a BP workgroup carries at once (<= 16) */
   /* optional per-shot outputs (NULL to skip), each indexed by shot of the call: */
   uint8_t* ehat_dev;        /* [n_shots][cols] final correction (0/1 bytes) */
   float* llr_dev;           /* [n_shots][cols] final BP posterior LLRs */

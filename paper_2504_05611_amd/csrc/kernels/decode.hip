@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "../host/device.h"
@@ -52,7 +53,8 @@ struct DecodeDevice {
   int32_t* osd_queue = nullptr;
   float* osd_llr = nullptr;
   uint64_t* basis = nullptr;
-  size_t cap_queue = 0, cap_osd = 0, cap_llr = 0, cap_basis = 0;
+  uint64_t* synd = nullptr;
+  size_t cap_queue = 0, cap_osd = 0, cap_llr = 0, cap_basis = 0, cap_synd = 0;
 };
 
 struct BPArgs {
@@ -68,8 +70,9 @@ struct BPArgs {
   int32_t T;
   float alpha;
   const float* w;            // nullable [T][E]
-  const uint64_t* det;       // [m][stride]
-  int64_t stride;
+  const uint64_t* synd;      // [chunk shots][mw] shot-major syndrome words
+  int32_t mw;
+  int64_t stride;            // words per row of pred
   int64_t shot0;             // first shot of this chunk (within the call)
   int64_t nshots;            // shots in this chunk
   const int32_t* queue;      // nullable: identity
@@ -116,157 +119,282 @@ __global__ void k_zero_i32(int32_t* p, int n) {
   if (i < n) p[i] = 0;
 }
 
-// Queue the shots of [shot0, shot0 + nshots) whose syndrome is non-zero.
-__global__ void k_compact(const uint64_t* __restrict__ det, int32_t m, int64_t stride, int64_t shot0,
-                          int64_t nshots, int32_t* __restrict__ queue, int32_t* __restrict__ counters,
-                          tmcs_decode_stats* stats) {
-  const int64_t nw = (nshots + 63) / 64;
-  for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nw; w += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t gw = (shot0 >> 6) + w;   // shot0 is a multiple of 64
-    uint64_t any = 0;
-    for (int r = 0; r < m; ++r) any |= det[(int64_t)r * stride + gw];
-    const int64_t left = nshots - w * 64;
-    if (left < 64) any &= (1ull << left) - 1ull;
-    const int cnt = __popcll(any);
-    if (cnt) {
-      int pos = atomicAdd(&counters[0], cnt);
-      while (any) {
-        const int b = __ffsll((unsigned long long)any) - 1;
-        any &= any - 1;
-        queue[pos++] = (int32_t)(w * 64 + b);
-      }
-    }
+// Detector-major bit planes -> shot-major syndrome words for the chunk
+// [shot0, shot0 + nshots): one workgroup per (64-shot word, 64-detector tile),
+// a 64 x 64 bit transpose through LDS.
+__global__ void __launch_bounds__(64) k_synd_transpose(const uint64_t* __restrict__ det, int32_t m, int64_t stride,
+                                                       int64_t shot0, int64_t nshots, int32_t mw,
+                                                       uint64_t* __restrict__ synd) {
+  __shared__ uint64_t tile[64];
+  const int lane = threadIdx.x;
+  const int64_t w = blockIdx.x;             // shot word within the chunk
+  const int rt = blockIdx.y;                // detector tile
+  const int row = rt * 64 + lane;
+  tile[lane] = row < m ? det[(int64_t)row * stride + (shot0 >> 6) + w] : 0ull;
+  __syncthreads();
+  uint64_t out = 0ull;
+#pragma unroll 16
+  for (int i = 0; i < 64; ++i) out |= ((tile[i] >> lane) & 1ull) << i;
+  const int64_t s = w * 64 + lane;
+  if (s < nshots) synd[s * mw + rt] = out;
+}
+
+// Queue the shots of the chunk whose syndrome is non-zero.
+__global__ void k_compact(const uint64_t* __restrict__ synd, int32_t mw, int64_t nshots,
+                          int32_t* __restrict__ queue, int32_t* __restrict__ counters) {
+  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nshots; s += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t any = 0ull;
+    for (int k = 0; k < mw; ++k) any |= synd[s * mw + k];
+    if (any) queue[atomicAdd(&counters[0], 1)] = (int32_t)s;
   }
 }
 
-__global__ void k_bp(BPArgs a) {
+// Slot states of the BP kernel.
+enum : int32_t { SLOT_EMPTY = 0, SLOT_NEW = 1, SLOT_ACTIVE = 2, SLOT_DONE = 3 };
+
+// BP over a persistent workgroup that carries S shots ("slots") at once, each at
+// its own iteration; a slot whose shot has converged (or used its T iterations)
+// is finalised and refilled from the queue independently of the others.
+//
+// MSG = true keeps every check-to-variable message m_{c->v} in LDS (CSR edge
+// order); the check pass first turns m_old into q = L_v - m_old in place, then
+// writes the new messages, and the variable pass is a plain sum.  MSG = false
+// keeps the compressed check state instead - (min1, min2, argmin edge, sign
+// parity) per check and one sign bit per edge - and rebuilds messages from it;
+// it needs ~4 bytes per column + 13 per check instead of 4 per edge, for DEMs
+// whose messages do not fit.
+template <bool MSG>
+__global__ void k_bp(BPArgs a, int32_t S) {
   extern __shared__ __align__(8) unsigned char sm[];
-  float* Lf = (float*)sm;
-  float* min1 = Lf + a.n;
-  float* min2 = min1 + a.m;
-  int32_t* arg = (int32_t*)(min2 + a.m);
-  uint32_t* esign = (uint32_t*)(arg + a.m);
-  uint8_t* cflag = (uint8_t*)(esign + (a.E + 31) / 32);
-  __shared__ int s_job;
-  __shared__ uint64_t s_red;
   const int tid = threadIdx.x, nt = blockDim.x;
+  const int m = a.m, n = a.n;
+  const int64_t E = a.E;
+  const int64_t nwords = (E + 31) / 32;
+  // per-slot arrays (slot-major)
+  float* Lf = (float*)sm;                                             // [S][n]
+  float* msg = Lf + (size_t)S * n;                                    // MSG:  [S][E]
+  float* min1 = msg;                                                  // !MSG: [S][m]
+  float* min2 = min1 + (size_t)S * m;                                 // !MSG: [S][m]
+  int32_t* arg = (int32_t*)(min2 + (size_t)S * m);                    // !MSG: [S][m]
+  uint32_t* esign = (uint32_t*)(arg + (size_t)S * m);                 // !MSG: [S][nwords]
+  uint8_t* cflag = MSG ? (uint8_t*)(msg + (size_t)S * E) : (uint8_t*)(esign + (size_t)S * nwords);  // [S][m]
+  __shared__ int32_t st[16], tt[16], ls_of[16], flag[16], osdpos[16], itr[16];
+  __shared__ unsigned long long pmask[16];
+  __shared__ int s_exit;
   const int32_t total = a.queue ? a.counters[0] : (int32_t)a.nshots;
+  if (tid < S) {
+    const int job = atomicAdd(&a.counters[1], 1);
+    st[tid] = job < total ? SLOT_NEW : SLOT_EMPTY;
+    ls_of[tid] = job < total ? (a.queue ? a.queue[job] : job) : 0;
+    flag[tid] = 0;
+  }
+  __syncthreads();
   while (true) {
-    if (tid == 0) s_job = atomicAdd(&a.counters[1], 1);
-    __syncthreads();
-    const int job = s_job;
-    __syncthreads();
-    if (job >= total) break;
-    const int64_t ls = a.queue ? a.queue[job] : job;   // shot within the chunk
-    const int64_t shot = a.shot0 + ls;                  // shot within the call
-    int has = 0;
-    for (int c = tid; c < a.m; c += nt) {
-      const int s = (int)((a.det[(int64_t)c * a.stride + (shot >> 6)] >> (shot & 63)) & 1ull);
-      has |= s;
-      cflag[c] = (uint8_t)(s << 1);
-      min1[c] = 0.0f;
-      min2[c] = 0.0f;
-      arg[c] = -1;
+    // 1. initialise new slots: syndrome bits, zero messages / check state, L = lambda
+    for (int sl = 0; sl < S; ++sl) {
+      if (st[sl] != SLOT_NEW) continue;
+      const uint64_t* sy = a.synd + (int64_t)ls_of[sl] * a.mw;
+      uint8_t* cf = cflag + sl * m;
+      for (int c = tid; c < m; c += nt) {
+        const int sb = (int)((sy[c >> 6] >> (c & 63)) & 1ull);
+        cf[c] = (uint8_t)(sb << 1);
+        if (!MSG) {
+          min1[sl * m + c] = 0.0f;
+          min2[sl * m + c] = 0.0f;
+          arg[sl * m + c] = -1;
+        }
+        if (sb) flag[sl] = 1;                              // benign race: every writer stores 1
+      }
+      float* L = Lf + (size_t)sl * n;
+      for (int v = tid; v < n; v += nt) L[v] = a.lam[v];
+      if (MSG) {
+        float* ms = msg + (size_t)sl * E;
+        for (int64_t e = tid; e < E; e += nt) ms[e] = 0.0f;
+      } else {
+        uint32_t* es = esign + (size_t)sl * nwords;
+        for (int64_t i = tid; i < nwords; i += nt) es[i] = 0u;
+      }
     }
-    for (int v = tid; v < a.n; v += nt) Lf[v] = a.lam[v];
-    for (int64_t i = tid; i < (a.E + 31) / 32; i += nt) esign[i] = 0u;
-    const int nonzero = __syncthreads_or(has);
-    int iters = 0;
-    bool conv = !nonzero;
-    if (nonzero) {
-      for (int t = 1; t <= a.T + 1; ++t) {
-        // check pass: convergence of L^{(t-1)}, then new check state from q^{(t-1)}
-        const bool update = t <= a.T;
-        int unsat = 0;
-        for (int c = tid; c < a.m; c += nt) {
-          const int32_t r0 = a.row_ptr[c], r1 = a.row_ptr[c + 1];
-          const float m1 = min1[c], m2 = min2[c];
-          const int32_t ag = arg[c];
-          const uint8_t fl = cflag[c];
-          const int sc = (fl >> 1) & 1, sp = fl & 1;
-          int hard = 0, npar = 0;
-          float n1 = BP_BIG, n2 = BP_BIG;
-          int32_t nag = -1;
+    __syncthreads();
+    if (tid < S && st[tid] == SLOT_NEW) {
+      if (flag[tid]) { st[tid] = SLOT_ACTIVE; tt[tid] = 1; flag[tid] = 0; }
+      else { st[tid] = SLOT_DONE; itr[tid] = 0; osdpos[tid] = -1; flag[tid] = 1; pmask[tid] = 0ull; }
+    }
+    __syncthreads();
+    // 2. check pass: convergence of L^{(t-1)} and the messages of iteration t
+    for (int sl = 0; sl < S; ++sl) {
+      if (st[sl] != SLOT_ACTIVE) continue;
+      const int t = tt[sl];
+      const bool update = t <= a.T;
+      const float* L = Lf + (size_t)sl * n;
+      const uint8_t* cf = cflag + sl * m;
+      int unsat = 0;
+      for (int c = tid; c < m; c += nt) {
+        const int32_t r0 = a.row_ptr[c], r1 = a.row_ptr[c + 1];
+        const int sc = (cf[c] >> 1) & 1;
+        int hard = 0, npar = 0;
+        float n1 = BP_BIG, n2 = BP_BIG;
+        int32_t nag = -1;
+        if (MSG) {
+          float* ms = msg + (size_t)sl * E;
           for (int32_t e = r0; e < r1; ++e) {
-            const int32_t v = a.col_idx[e];
-            const float Lv = Lf[v];
+            const float Lv = L[a.col_idx[e]];
             hard ^= Lv < 0.0f ? 1 : 0;
-            if (!update) continue;
-            const int se = (int)((esign[e >> 5] >> (e & 31)) & 1u);
-            const float aold = (t == 1) ? 1.0f : (a.w ? a.w[(int64_t)(t - 2) * a.E + e] : a.alpha);
-            const float mag = __fmul_rn(aold, e == ag ? m2 : m1);
-            const float mo = (sc ^ sp ^ se) ? -mag : mag;
-            const float q = __fsub_rn(Lv, mo);
+            const float q = __fsub_rn(Lv, ms[e]);           // q_{v->c} = L_v - m_old
+            ms[e] = q;
             const float aq = fabsf(q);
-            const int ng = q < 0.0f ? 1 : 0;
             if (aq < n1) { n2 = n1; n1 = aq; nag = e; }
             else if (aq < n2) { n2 = aq; }
-            npar ^= ng;
-            if (ng != se) atomicXor(&esign[e >> 5], 1u << (e & 31));
+            npar ^= q < 0.0f ? 1 : 0;
           }
-          unsat |= hard != sc;
           if (update) {
-            min1[c] = n1;
-            min2[c] = n2;
-            arg[c] = nag;
-            cflag[c] = (uint8_t)((sc << 1) | npar);
+            const float* wt = a.w ? a.w + (int64_t)(t - 1) * E : nullptr;
+            for (int32_t e = r0; e < r1; ++e) {
+              const float q = ms[e];
+              const float at = wt ? wt[e] : a.alpha;
+              const float mag = __fmul_rn(at, e == nag ? n2 : n1);
+              ms[e] = (sc ^ npar ^ (q < 0.0f ? 1 : 0)) ? -mag : mag;
+            }
+          }
+        } else {
+          uint32_t* es = esign + (size_t)sl * nwords;
+          const float m1 = min1[sl * m + c], m2 = min2[sl * m + c];
+          const int32_t ag = arg[sl * m + c];
+          const int sp = cf[c] & 1;
+          for (int32_t e0 = r0; e0 < r1; e0 += 4) {
+            int32_t vv[4];
+            float Lv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) vv[u] = e0 + u < r1 ? a.col_idx[e0 + u] : 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) Lv[u] = L[vv[u]];
+            const int32_t elast = e0 + 3 < r1 ? e0 + 3 : r1 - 1;   // a batch spans <= 2 sign words
+            const uint32_t sw0 = es[e0 >> 5], sw1 = es[elast >> 5];
+            uint32_t flip0 = 0u, flip1 = 0u;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int32_t e = e0 + u;
+              if (e >= r1) break;
+              hard ^= Lv[u] < 0.0f ? 1 : 0;
+              if (!update) continue;
+              const bool hi = (e >> 5) != (e0 >> 5);
+              const int se = (int)(((hi ? sw1 : sw0) >> (e & 31)) & 1u);
+              const float aold = (t == 1) ? 1.0f : (a.w ? a.w[(int64_t)(t - 2) * E + e] : a.alpha);
+              const float mag = __fmul_rn(aold, e == ag ? m2 : m1);
+              const float mo = (sc ^ sp ^ se) ? -mag : mag;
+              const float q = __fsub_rn(Lv[u], mo);
+              const float aq = fabsf(q);
+              const int ng = q < 0.0f ? 1 : 0;
+              if (aq < n1) { n2 = n1; n1 = aq; nag = e; }
+              else if (aq < n2) { n2 = aq; }
+              npar ^= ng;
+              if (ng != se) {
+                if (hi) flip1 |= 1u << (e & 31); else flip0 |= 1u << (e & 31);
+              }
+            }
+            if (flip0) atomicXor(&es[e0 >> 5], flip0);
+            if (flip1) atomicXor(&es[elast >> 5], flip1);
+          }
+          if (update) {
+            min1[sl * m + c] = n1;
+            min2[sl * m + c] = n2;
+            arg[sl * m + c] = nag;
+            cflag[sl * m + c] = (uint8_t)((sc << 1) | npar);
           }
         }
-        const int any_unsat = __syncthreads_or(unsat);
-        if (!any_unsat) { conv = true; iters = t - 1; break; }
-        if (!update) { iters = a.T; break; }
-        // variable pass
-        for (int v = tid; v < a.n; v += nt) {
-          float acc = a.lam[v];
-          const int32_t k0 = a.col_ptr[v], k1 = a.col_ptr[v + 1];
-          for (int32_t k = k0; k < k1; ++k) {
-            const int32_t c = a.csc_row[k], e = a.csc_edge[k];
-            const uint8_t fl = cflag[c];
-            const int se = (int)((esign[e >> 5] >> (e & 31)) & 1u);
-            const float at = a.w ? a.w[(int64_t)(t - 1) * a.E + e] : a.alpha;
-            const float mag = __fmul_rn(at, e == arg[c] ? min2[c] : min1[c]);
-            const int neg = ((fl >> 1) ^ fl ^ se) & 1;
-            acc = __fadd_rn(acc, neg ? -mag : mag);
-          }
-          Lf[v] = acc;
-        }
-        __syncthreads();
+        unsat |= hard != sc;
       }
+      if (unsat) flag[sl] = 1;                               // benign race: every writer stores 1
     }
-    // outputs
-    const bool to_osd = !conv && a.use_osd;
-    int osd_pos = 0;
-    if (to_osd) {
-      if (tid == 0) s_job = atomicAdd(&a.counters[2], 1);
-      __syncthreads();
-      osd_pos = s_job;
-      __syncthreads();
-    }
-    uint64_t pm = 0;
-    for (int v = tid; v < a.n; v += nt) {
-      const float L = Lf[v];
-      if (!to_osd && L < 0.0f) pm ^= a.obs_mask[v];
-      if (to_osd) a.osd_llr[(int64_t)osd_pos * a.n + v] = L;
-      if (a.llr) a.llr[shot * a.n + v] = L;
-      if (a.ehat && !to_osd) a.ehat[shot * a.n + v] = L < 0.0f ? 1 : 0;
-    }
-    if (!to_osd) {
-      pm = block_xor_u64(pm, &s_red);
-      if (tid == 0) write_pred(a.pred, a.stride, a.nobs, shot, pm);
-    } else if (tid == 0) {
-      a.osd_queue[osd_pos] = (int32_t)ls;
-    }
-    if (tid == 0) {
-      if (a.iters) a.iters[shot] = iters;
-      if (a.flags) a.flags[shot] = (uint8_t)((conv ? 1 : 0) | (to_osd ? 2 : 0));
-      if (a.stats) {
-        if (nonzero) atomicAdd((unsigned long long*)&a.stats->nontrivial, 1ull);
-        if (conv) atomicAdd((unsigned long long*)&a.stats->converged, 1ull);
-        if (to_osd) atomicAdd((unsigned long long*)&a.stats->osd, 1ull);
-        atomicAdd((unsigned long long*)&a.stats->bp_iters, (unsigned long long)iters);
+    __syncthreads();
+    // 3. per-slot decision: converged, out of iterations, or one more iteration
+    if (tid < S && st[tid] == SLOT_ACTIVE) {
+      const int t = tt[tid];
+      const bool conv = flag[tid] == 0;
+      if (conv || t > a.T) {
+        st[tid] = SLOT_DONE;
+        itr[tid] = conv ? t - 1 : a.T;
+        flag[tid] = conv ? 1 : 0;                           // flag now = converged
+        pmask[tid] = 0ull;
+        osdpos[tid] = (!conv && a.use_osd) ? atomicAdd(&a.counters[2], 1) : -1;
+      } else {
+        flag[tid] = 0;
       }
     }
     __syncthreads();
+    // 4. variable pass for active slots, finalisation for finished ones
+    for (int sl = 0; sl < S; ++sl) {
+      const int state = st[sl];
+      float* L = Lf + (size_t)sl * n;
+      if (state == SLOT_ACTIVE) {
+        if (MSG) {
+          const float* ms = msg + (size_t)sl * E;
+          for (int v = tid; v < n; v += nt) {
+            float acc = a.lam[v];
+            const int32_t k0 = a.col_ptr[v], k1 = a.col_ptr[v + 1];
+            for (int32_t k = k0; k < k1; ++k) acc = __fadd_rn(acc, ms[a.csc_edge[k]]);
+            L[v] = acc;
+          }
+        } else {
+          const int t = tt[sl];
+          const uint32_t* es = esign + (size_t)sl * nwords;
+          for (int v = tid; v < n; v += nt) {
+            float acc = a.lam[v];
+            const int32_t k0 = a.col_ptr[v], k1 = a.col_ptr[v + 1];
+            for (int32_t k = k0; k < k1; ++k) {
+              const int32_t c = sl * m + a.csc_row[k], e = a.csc_edge[k];
+              const uint8_t fl = cflag[c];
+              const int se = (int)((es[e >> 5] >> (e & 31)) & 1u);
+              const float at = a.w ? a.w[(int64_t)(t - 1) * E + e] : a.alpha;
+              const float mag = __fmul_rn(at, e == arg[c] ? min2[c] : min1[c]);
+              const int neg = ((fl >> 1) ^ fl ^ se) & 1;
+              acc = __fadd_rn(acc, neg ? -mag : mag);
+            }
+            L[v] = acc;
+          }
+        }
+      } else if (state == SLOT_DONE) {
+        const int64_t shot = a.shot0 + ls_of[sl];
+        const int pos = osdpos[sl];
+        for (int v = tid; v < n; v += nt) {
+          const float Lv = L[v];
+          if (pos < 0 && Lv < 0.0f && a.obs_mask[v]) atomicXor(&pmask[sl], (unsigned long long)a.obs_mask[v]);
+          if (pos >= 0) a.osd_llr[(int64_t)pos * n + v] = Lv;
+          if (a.llr) a.llr[shot * n + v] = Lv;
+          if (a.ehat && pos < 0) a.ehat[shot * n + v] = Lv < 0.0f ? 1 : 0;
+        }
+      }
+    }
+    __syncthreads();
+    // 5. finished slots: predictions, statistics, refill
+    if (tid < S) {
+      if (st[tid] == SLOT_ACTIVE) {
+        tt[tid] += 1;
+      } else if (st[tid] == SLOT_DONE) {
+        const int64_t shot = a.shot0 + ls_of[tid];
+        const bool conv = flag[tid] != 0;
+        const int pos = osdpos[tid];
+        if (pos < 0) write_pred(a.pred, a.stride, a.nobs, shot, pmask[tid]);
+        else a.osd_queue[pos] = ls_of[tid];
+        if (a.iters) a.iters[shot] = itr[tid];
+        if (a.flags) a.flags[shot] = (uint8_t)((conv ? 1 : 0) | (pos >= 0 ? 2 : 0));
+        if (a.stats) {
+          if (itr[tid] > 0 || !conv) atomicAdd((unsigned long long*)&a.stats->nontrivial, 1ull);
+          if (conv) atomicAdd((unsigned long long*)&a.stats->converged, 1ull);
+          if (pos >= 0) atomicAdd((unsigned long long*)&a.stats->osd, 1ull);
+          atomicAdd((unsigned long long*)&a.stats->bp_iters, (unsigned long long)itr[tid]);
+        }
+        const int job = atomicAdd(&a.counters[1], 1);
+        st[tid] = job < total ? SLOT_NEW : SLOT_EMPTY;
+        ls_of[tid] = job < total ? (a.queue ? a.queue[job] : job) : 0;
+        flag[tid] = 0;
+      }
+    }
+    if (tid == 0) s_exit = 1;
+    __syncthreads();
+    if (tid < S && st[tid] != SLOT_EMPTY) s_exit = 0;     // benign race: every writer stores 0
+    __syncthreads();
+    if (s_exit) break;
   }
 }
 
@@ -609,7 +737,7 @@ tmcs_status grow(T** p, size_t* cap, size_t need) {
 void free_device(DecodeDevice* d) {
   hipFree(d->row_ptr); hipFree(d->col_idx); hipFree(d->col_ptr); hipFree(d->csc_row); hipFree(d->csc_edge);
   hipFree(d->lam); hipFree(d->obs_mask); hipFree(d->counters); hipFree(d->queue); hipFree(d->osd_queue);
-  hipFree(d->osd_llr); hipFree(d->basis);
+  hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd);
   *d = DecodeDevice();
 }
 
@@ -709,14 +837,21 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   if (cfg.use_osd && (npad > OSD_MAX_KEYS || mw > 32))
     return fail(TMCS_EUNSUPPORTED, "OSD-0 supports up to 16384 columns and 2048 detectors in this build");
   const int cus = device_cus();
-  // BP launch shape
-  int bp_threads = cfg.bp_threads > 0 ? cfg.bp_threads : (D.cols > 4096 ? 256 : (D.cols > 512 ? 128 : 64));
+  // BP launch shape: explicit messages when they fit, S shots per workgroup
+  int bp_threads = cfg.bp_threads > 0 ? cfg.bp_threads : (D.cols > 4096 ? 512 : 256);
   bp_threads = std::min(1024, std::max(64, (bp_threads + 63) / 64 * 64));
-  const size_t bp_lds = (size_t)D.cols * 4 + (size_t)D.rows * 12 + (size_t)((D.edges + 31) / 32) * 4 +
-                        (size_t)D.rows + 16;
-  if (bp_lds > 160 * 1024) return fail(TMCS_EUNSUPPORTED, "BP state exceeds the 160 KB LDS of one workgroup");
+  const size_t per_shot_msg = (size_t)D.cols * 4 + (size_t)D.edges * 4 + (size_t)D.rows;
+  const size_t per_shot_cmp = (size_t)D.cols * 4 + (size_t)D.rows * 13 + (size_t)((D.edges + 31) / 32) * 4;
+  const bool use_msg = per_shot_msg + 16 <= 64 * 1024;
+  const size_t per_shot = use_msg ? per_shot_msg : per_shot_cmp;
+  if (per_shot + 16 > 160 * 1024) return fail(TMCS_EUNSUPPORTED, "BP state exceeds the 160 KB LDS of one workgroup");
+  int slots = cfg.bp_slots > 0 ? cfg.bp_slots : 1;
+  slots = std::max(1, std::min(16, slots));
+  while (slots > 1 && per_shot * slots + 16 > 160 * 1024) --slots;
+  const size_t bp_lds = per_shot * slots + 16;
+  const void* bp_fn = use_msg ? (const void*)k_bp<true> : (const void*)k_bp<false>;
   if (bp_lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_bp, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess)
+      hipFuncSetAttribute(bp_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
   const int per_cu_fit = std::max<int>(1, (int)((160 * 1024) / (bp_lds + 512)));
   const int per_cu = std::min(per_cu_fit, cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 16);
@@ -731,6 +866,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int osd_per_cu = std::min(osd_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 4);
   const int osd_grid = std::max(1, cus * osd_per_cu);
   if ((st = grow(&d->queue, &d->cap_queue, (size_t)chunk)) != TMCS_OK) return st;
+  if ((st = grow(&d->synd, &d->cap_synd, (size_t)chunk * (size_t)std::max(mw, 1))) != TMCS_OK) return st;
   if (cfg.use_osd) {
     if ((st = grow(&d->osd_queue, &d->cap_osd, (size_t)chunk)) != TMCS_OK ||
         (st = grow(&d->osd_llr, &d->cap_llr, (size_t)chunk * (size_t)D.cols)) != TMCS_OK ||
@@ -746,22 +882,30 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
     const int64_t ns = std::min<int64_t>(chunk, (int64_t)n_shots - s0);
     TMCS_LAUNCH("k_zero_i32", k_zero_i32, dim3(1), dim3(64), 0, stream, d->counters, 8);
     if (stats) TMCS_LAUNCH("k_add_shots", k_add_shots, dim3(1), dim3(1), 0, stream, stats, (unsigned long long)ns);
-    if (!full) {
+    {
       const int64_t nw = (ns + 63) / 64;
-      const int64_t g = std::min<int64_t>((nw + 255) / 256, 4096);
-      TMCS_LAUNCH("k_compact", k_compact, dim3((unsigned)g), dim3(256), 0, stream, det, D.rows, stride, s0, ns,
-                         d->queue, d->counters, stats);
+      const int mt = std::max(mw, 1);
+      TMCS_LAUNCH("k_synd_transpose", k_synd_transpose, dim3((unsigned)nw, (unsigned)mt), dim3(64), 0, stream, det,
+                  D.rows, stride, s0, ns, mt, d->synd);
+    }
+    if (!full) {
+      const int64_t g = std::min<int64_t>((ns + 255) / 256, 4096);
+      TMCS_LAUNCH("k_compact", k_compact, dim3((unsigned)g), dim3(256), 0, stream, d->synd, std::max(mw, 1), ns,
+                  d->queue, d->counters);
     }
     BPArgs a;
     a.row_ptr = d->row_ptr; a.col_idx = d->col_idx; a.col_ptr = d->col_ptr; a.csc_row = d->csc_row;
     a.csc_edge = d->csc_edge; a.lam = d->lam; a.obs_mask = d->obs_mask;
     a.m = D.rows; a.n = D.cols; a.E = D.edges; a.T = cfg.max_iter; a.alpha = cfg.alpha; a.w = cfg.weights_dev;
-    a.det = det; a.stride = stride; a.shot0 = s0; a.nshots = ns; a.queue = full ? nullptr : d->queue;
+    a.synd = d->synd; a.mw = std::max(mw, 1); a.stride = stride; a.shot0 = s0; a.nshots = ns; a.queue = full ? nullptr : d->queue;
     a.counters = d->counters; a.use_osd = cfg.use_osd; a.osd_queue = d->osd_queue; a.osd_llr = d->osd_llr;
     a.pred = pred; a.nobs = D.nobs; a.stats = stats; a.ehat = cfg.ehat_dev; a.llr = cfg.llr_dev;
     a.iters = cfg.iters_dev; a.flags = cfg.flags_dev;
-    const int bp_grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(ns, 1));
-    TMCS_LAUNCH("k_bp", k_bp, dim3(bp_grid), dim3(bp_threads), bp_lds, stream, a);
+    const int bp_grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>((ns + slots - 1) / slots, 1));
+    if (use_msg)
+      TMCS_LAUNCH("k_bp", k_bp<true>, dim3(bp_grid), dim3(bp_threads), bp_lds, stream, a, (int32_t)slots);
+    else
+      TMCS_LAUNCH("k_bp", k_bp<false>, dim3(bp_grid), dim3(bp_threads), bp_lds, stream, a, (int32_t)slots);
     if ((st = hip_check(hipGetLastError(), "k_bp launch")) != TMCS_OK) return st;
     if (cfg.use_osd) {
       OSDArgs o;
