@@ -93,6 +93,7 @@ tmcs_status tmcs_build_dem(const tmcs_circuit* c, tmcs_dem** out) {
 void tmcs_free_dem(tmcs_dem* d) {
   if (!d) return;
   decode_release(d->d);
+  wbp_release(d->d);
   delete d;
 }
 

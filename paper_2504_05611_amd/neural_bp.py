@@ -1,0 +1,125 @@
+"""Learned per-edge, per-iteration BP weights (neural BP), trained on sampled syndromes.
+
+The forward and backward passes are the library's HIP kernels
+(tmcs_wbp_forward / tmcs_wbp_backward); torch provides device memory, the loss
+on the observables and the optimizer.
+
+Loss (the paper does not train decoders; this is the library's reading): for
+every iteration t and logical observable o, binary cross-entropy between the
+observable flip o and the probability the BP marginals assign to it,
+  P_t(o) = (1 - prod_{v in supp L_o} tanh(L_t(v) / 2)) / 2,
+summed over t so that early iterations are pushed towards the answer too.
+The product is evaluated in the log domain with sign tracking.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import tmcs
+
+
+class WeightedBP(torch.autograd.Function):
+    """L_all[T, S, n] = weighted min-sum posteriors after every iteration."""
+
+    @staticmethod
+    def forward(ctx, weights, det, dem, n_shots):
+        T = weights.shape[0]
+        n = dem.cols
+        ws = torch.empty(dem.wbp_workspace_size(T, n_shots), dtype=torch.uint8, device=weights.device)
+        llr = torch.empty((T, n_shots, n), dtype=torch.float32, device=weights.device)
+        w = weights.detach().contiguous()
+        dem.wbp_forward(w, T, det, n_shots, llr, ws)
+        ctx.save_for_backward(w)
+        ctx.dem, ctx.det, ctx.ws, ctx.n_shots = dem, det, ws, n_shots
+        return llr
+
+    @staticmethod
+    def backward(ctx, grad_llr):
+        (w,) = ctx.saved_tensors
+        T = w.shape[0]
+        gw = torch.zeros_like(w)
+        ctx.dem.wbp_backward(w, T, ctx.det, ctx.n_shots, grad_llr.contiguous(), gw, ctx.ws)
+        return gw, None, None, None
+
+
+def observable_support(dem) -> torch.Tensor:
+    """[k, n] 0/1 matrix of the columns that flip each observable."""
+    h = dem.export()
+    k = max(dem.info["obs"], 1)
+    L = np.zeros((k, dem.cols), dtype=np.float32)
+    for o in range(k):
+        L[o] = ((h.obs_mask >> np.uint64(o)) & np.uint64(1)).astype(np.float32)
+    return torch.from_numpy(L)
+
+
+def observable_loss(llr, obs_bits, supp):
+    """Sum over t and o of BCE(P_t(o), obs).  llr [T, S, n]; obs_bits [S, k] float; supp [k, n]."""
+    a = llr.abs().clamp_min(1e-6)
+    # log|tanh(L/2)|, kept finite so that columns outside supp(L_o) (weight 0) never give 0 * inf
+    logt = (torch.log1p(-torch.exp(-a)) - torch.log1p(torch.exp(-a))).clamp_min(-60.0)
+    neg = (llr < 0).to(llr.dtype)
+    S_log = torch.einsum("tsn,kn->tsk", logt, supp)                      # log|prod tanh|
+    parity = torch.remainder(torch.einsum("tsn,kn->tsk", neg, supp), 2.0)  # sign of the product
+    e = torch.exp(S_log)
+    # P(o = 1) = (1 - prod)/2, P(o = 0) = (1 + prod)/2, prod = (-1)^parity e^S_log
+    one_minus = torch.where(parity > 0.5, 1.0 + e, -torch.expm1(S_log))
+    one_plus = torch.where(parity > 0.5, -torch.expm1(S_log), 1.0 + e)
+    log_p1 = torch.log(one_minus.clamp_min(1e-30)) - math.log(2.0)
+    log_p0 = torch.log(one_plus.clamp_min(1e-30)) - math.log(2.0)
+    y = obs_bits[None]
+    return -(y * log_p1 + (1.0 - y) * log_p0).sum()
+
+
+@dataclass
+class TrainResult:
+    weights: torch.Tensor
+    losses: list
+
+
+def unpack_obs(obs_words, n_shots, k):
+    """[k, words] int64 bit planes -> [n_shots, k] float32 on the same device."""
+    sh = torch.arange(64, device=obs_words.device, dtype=torch.int64)
+    bits = (obs_words[:k, :, None] >> sh) & 1
+    return bits.reshape(k, -1)[:, :n_shots].T.to(torch.float32)
+
+
+def train(circuit, dem, T, *, steps=200, batch=256, lr=0.01, seed=2, init=1.0, log_every=0):
+    """Train weights [T, E] on fresh syndromes sampled by the library each step."""
+    dev = torch.device("cuda")
+    w = torch.full((T, dem.edges), float(init), dtype=torch.float32, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([w], lr=lr)
+    supp = observable_support(dem).to(dev)
+    k = max(circuit.num_observables, 1)
+    det, obs = circuit.alloc_outputs(batch)
+    losses = []
+    for step in range(steps):
+        circuit.sample(seed, 0, step * ((batch + 4095) // 4096) * 4096, batch, det, obs)
+        llr = WeightedBP.apply(w, det, dem, batch)
+        y = unpack_obs(obs, batch, k)
+        loss = observable_loss(llr, y, supp) / (batch * T)
+        opt.zero_grad()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            w.clamp_(0.0, 4.0)
+        losses.append(float(loss.detach()))
+        if log_every and step % log_every == 0:
+            print(f"step {step} loss {losses[-1]:.5f}", flush=True)
+    return TrainResult(w.detach(), losses)
+
+
+def evaluate(circuit, dem, *, n_shots, T, weights=None, alpha=1.0, use_osd=True, seed=11):
+    """LER and OSD rate of (weighted) BP-OSD on fresh shots."""
+    det, obs = circuit.alloc_outputs(n_shots)
+    circuit.sample(seed, 0, 0, n_shots, det, obs)
+    pred = torch.zeros_like(obs)
+    st = tmcs.new_stats()
+    dem.decode(det, n_shots, pred, max_iter=T, alpha=alpha, weights=weights, use_osd=use_osd, stats=st)
+    ne, ler, sig = tmcs.logical_error_rate(pred, obs, circuit.num_observables, n_shots)
+    s = tmcs.read_stats(st)
+    return dict(errors=ne, ler=ler, sigma=sig, osd_rate=s["osd"] / max(n_shots, 1),
+                converged=s["converged"] / max(n_shots, 1), bp_iters=s["bp_iters"] / max(n_shots, 1))

@@ -1,0 +1,98 @@
+"""GPU parity of the weighted-BP training kernels and a training gain test."""
+import numpy as np
+import pytest
+
+from oracle.circuits import build_circuit
+from oracle.dem import build_dem
+from oracle.frame import unpack_bits
+from oracle.wbp import backward as oracle_backward
+from oracle.wbp import forward as oracle_forward
+from workloads import NLCNOT, bb, sc
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(gpu_lib, spec, shots, T, seed=4):
+    import torch
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    det, obs = c.alloc_outputs(shots)
+    c.sample(seed, 0, 0, shots, det, obs)
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.6, 1.4, size=(T, dem.edges)).astype(np.float32)
+    wt = torch.from_numpy(w).cuda()
+    return c, dem, det, obs, w, wt
+
+
+@pytest.mark.parametrize("name,spec", [("sc3-nlcnot", sc(3, NLCNOT, 2, 2, 6e-3, 2e-2)),
+                                       ("bb18-nlcnot", bb("bb18", NLCNOT, 1, 1, 4e-3, 1e-2))],
+                         ids=["sc3-nlcnot", "bb18-nlcnot"])
+def test_forward_and_gradient(gpu_lib, name, spec):
+    import torch
+    T, shots = 6, 128
+    c, dem, det, obs, w, wt = _setup(gpu_lib, spec, shots, T)
+    ws = torch.empty(dem.wbp_workspace_size(T, shots), dtype=torch.uint8, device="cuda")
+    llr = torch.empty((T, shots, dem.cols), dtype=torch.float32, device="cuda")
+    dem.wbp_forward(wt, T, det, shots, llr, ws)
+    rng = np.random.default_rng(1)
+    G = rng.normal(size=(T, shots, dem.cols)).astype(np.float32)
+    gw = torch.zeros_like(wt)
+    dem.wbp_backward(wt, T, det, shots, torch.from_numpy(G).cuda(), gw, ws)
+    torch.cuda.synchronize()
+    od = build_dem(build_circuit(spec))
+    synd = unpack_bits(det.cpu().numpy().view(np.uint64), shots).T
+    f32 = oracle_forward(od.H(), od.priors(), synd, w, dtype=np.float32)
+    assert (llr.cpu().numpy() == f32["L"]).all()                    # FP32 forward, bit for bit
+    ref = oracle_backward(f32, G.astype(np.float64))                # FP64 arithmetic, same decisions
+    got = gw.cpu().numpy().astype(np.float64)
+    err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+    assert err < 1e-4, err
+    # and against the all-FP64 reference gradient
+    f64 = oracle_forward(od.H(), od.priors(), synd, w.astype(np.float64))
+    ref64 = oracle_backward(f64, G.astype(np.float64))
+    err64 = np.linalg.norm(got - ref64) / max(np.linalg.norm(ref64), 1e-30)
+    assert err64 < 1e-2, err64
+
+
+def test_unit_weights_match_plain_decoder(gpu_lib):
+    """With w = 1 the weighted forward is plain min-sum: same LLRs as the decoder without early stop."""
+    import torch
+    spec = sc(3, NLCNOT, 2, 2, 6e-3, 2e-2)
+    T, shots = 5, 200
+    c, dem, det, obs, _, _ = _setup(gpu_lib, spec, shots, T)
+    wt = torch.ones((T, dem.edges), dtype=torch.float32, device="cuda")
+    ws = torch.empty(dem.wbp_workspace_size(T, shots), dtype=torch.uint8, device="cuda")
+    llr = torch.empty((T, shots, dem.cols), dtype=torch.float32, device="cuda")
+    dem.wbp_forward(wt, T, det, shots, llr, ws)
+    it = torch.zeros(shots, dtype=torch.int32, device="cuda")
+    l2 = torch.zeros((shots, dem.cols), dtype=torch.float32, device="cuda")
+    pred = torch.zeros_like(obs)
+    dem.decode(det, shots, pred, max_iter=T, weights=wt, use_osd=False, llr=l2, iters=it)
+    torch.cuda.synchronize()
+    iters = it.cpu().numpy()
+    L = llr.cpu().numpy()
+    for s in range(shots):
+        if iters[s] > 0:
+            assert (L[iters[s] - 1, s] == l2.cpu().numpy()[s]).all()
+
+
+def test_training_lowers_the_loss_and_bp_failures(gpu_lib):
+    """Weights trained on sampled syndromes beat plain min-sum (alpha = 1) on fresh shots."""
+    import torch
+    from paper_2504_05611_amd import neural_bp
+    spec = sc(5, NLCNOT, 3, 3, 5e-3, 2e-2)
+    T = 12
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    res = neural_bp.train(c, dem, T, steps=150, batch=512, lr=0.02, seed=21)
+    first = float(np.mean(res.losses[:10]))
+    last = float(np.mean(res.losses[-10:]))
+    print(f"[train] loss {first:.4f} -> {last:.4f}", flush=True)
+    assert last < first
+    n = 200_000
+    plain = neural_bp.evaluate(c, dem, n_shots=n, T=T, use_osd=False, seed=99)
+    learned = neural_bp.evaluate(c, dem, n_shots=n, T=T, weights=res.weights, use_osd=False, seed=99)
+    print(f"[train] BP-only LER plain {plain['ler']:.4e} learned {learned['ler']:.4e}; "
+          f"non-converged plain {1 - plain['converged']:.4e} learned {1 - learned['converged']:.4e}", flush=True)
+    assert learned["ler"] < plain["ler"]
+    assert learned["converged"] > plain["converged"]
