@@ -198,6 +198,39 @@ tmcs_status tmcs_wbp_backward(const tmcs_dem* d, const float* weights_dev, int32
                               const void* workspace_dev, size_t workspace_bytes,
                               void* stream);
 
+/* Launch-shape autotuner: decodes the caller's syndromes (det_dev, n_shots
+ * shots, as for tmcs_decode) with each candidate launch shape - BP threads and
+ * workgroups per compute unit, OSD workgroups per compute unit - and writes the
+ * fastest into cfg's launch fields (the other fields are kept).  Decoder output
+ * never depends on these fields.  Synchronises the stream. */
+tmcs_status tmcs_autotune(const tmcs_dem* d, const uint64_t* det_dev, uint64_t n_shots,
+                          tmcs_decoder_cfg* cfg, void* stream);
+
+/* Batch plans.  A plan preallocates the whole sample -> decode -> count
+ * pipeline of one or more items (circuit, DEM, decoder settings, seed,
+ * instance id) for batches of batch_shots shots (a multiple of 4096), and with
+ * use_graph = 1 captures one batch of every item into a single HIP graph.
+ * Each tmcs_plan_run batch processes the next shot range of every item:
+ * shots [k B, (k+1) B) on the k-th batch, with the same bits as tmcs_sample /
+ * tmcs_decode on that range.  Counts accumulate on the device;
+ * tmcs_plan_result synchronises the stream and reads them for one item.
+ * Decoder settings must not request per-shot outputs.  Creation runs one
+ * untimed warm-up batch (which allocates all scratch) and resets the counts. */
+typedef struct tmcs_plan tmcs_plan;
+typedef struct {
+  const tmcs_circuit* circuit;
+  const tmcs_dem* dem;        /* built from circuit */
+  tmcs_decoder_cfg cfg;
+  uint64_t seed;
+  uint32_t instance;
+} tmcs_plan_item;
+tmcs_status tmcs_plan_create(const tmcs_plan_item* items, int32_t n_items, uint64_t batch_shots,
+                             int32_t use_graph, tmcs_plan** out);
+tmcs_status tmcs_plan_run(tmcs_plan* p, uint32_t n_batches, void* stream);
+tmcs_status tmcs_plan_result(tmcs_plan* p, int32_t item, uint64_t* shots, uint64_t* errors,
+                             tmcs_decode_stats* stats, void* stream);
+void tmcs_plan_free(tmcs_plan* p);
+
 /* Kernel timing (a tracing aid).  While enabled, every kernel the library
  * launches is bracketed by a pair of HIP events recorded on the stream it runs
  * on.  tmcs_timing_report synchronises on those events and writes a JSON object

@@ -10,16 +10,34 @@ namespace tmcs {
 tmcs_status hip_check(hipError_t e, const char* what);
 
 // sampler (sample.hip)
+// blk_off (device, nullable): added to every block index of the noise streams;
+// overflow_out (device, nullable): sticky event-buffer overflow flag owned by the
+// caller, in which case the call neither clears nor checks it and never waits.
 tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint64_t shot_begin,
-                       uint64_t n_shots, uint64_t* det, uint64_t* obs, hipStream_t stream);
+                       uint64_t n_shots, uint64_t* det, uint64_t* obs, hipStream_t stream,
+                       const uint64_t* blk_off = nullptr, uint32_t* overflow_out = nullptr,
+                       void* state = nullptr);
+// A private device state (program, tables, scratch) for callers whose launches
+// must keep pointing at the same buffers, e.g. a captured graph; state = nullptr
+// in sample_run uses the state cached on the circuit handle.
+void* sample_state_new(const Circuit& c, tmcs_status* st);
+void sample_state_free(void* state);
 void sample_release(Circuit& c);
 
 // decoder (decode.hip)
 tmcs_status decode_run(const Dem& d, const tmcs_decoder_cfg& cfg, const uint64_t* det,
                        uint64_t n_shots, uint64_t* pred_obs, tmcs_decode_stats* stats,
-                       hipStream_t stream);
+                       hipStream_t stream, void* state = nullptr);
+void* decode_state_new(const Dem& d, tmcs_status* st);
+void decode_state_free(void* state);
 tmcs_status ler_run(const uint64_t* pred, const uint64_t* obs, uint32_t k, uint64_t n_shots,
                     uint64_t* n_err, hipStream_t stream);
+// adds the failing-shot count to a device counter (no wait)
+tmcs_status count_errors_async(const uint64_t* pred, const uint64_t* obs, uint32_t k, uint64_t n_shots,
+                               unsigned long long* counter, hipStream_t stream);
+// launch-shape search for tmcs_autotune
+tmcs_status autotune_run(const Dem& d, const uint64_t* det, uint64_t n_shots, tmcs_decoder_cfg* cfg,
+                         hipStream_t stream);
 void decode_release(Dem& d);
 
 // weighted BP training kernels (wbp.hip)

@@ -741,14 +741,8 @@ void free_device(DecodeDevice* d) {
   *d = DecodeDevice();
 }
 
-tmcs_status ensure_device(const Dem& dc, DecodeDevice** out) {
-  Dem& D = const_cast<Dem&>(dc);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(TMCS_EDEVICE, "no HIP device");
-  DecodeDevice* d = (DecodeDevice*)D.device;
-  if (d && d->device == dev) { *out = d; return TMCS_OK; }
-  if (d) { free_device(d); delete d; D.device = nullptr; }
-  d = new DecodeDevice();
+tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
+  DecodeDevice* d = new DecodeDevice();
   d->device = dev;
   std::vector<int32_t> csc_row(D.row_idx.begin(), D.row_idx.end());
   std::vector<float> lam(D.cols);
@@ -767,6 +761,20 @@ tmcs_status ensure_device(const Dem& dc, DecodeDevice** out) {
     delete d;
     return fail(TMCS_ENOMEM, "hipMalloc failed (counters)");
   }
+  *out = d;
+  return TMCS_OK;
+}
+
+// The device state cached on the DEM handle (rebuilt when the device changes).
+tmcs_status ensure_device(const Dem& dc, DecodeDevice** out) {
+  Dem& D = const_cast<Dem&>(dc);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(TMCS_EDEVICE, "no HIP device");
+  DecodeDevice* d = (DecodeDevice*)D.device;
+  if (d && d->device == dev) { *out = d; return TMCS_OK; }
+  if (d) { free_device(d); delete d; D.device = nullptr; }
+  tmcs_status st = build_state(D, dev, &d);
+  if (st != TMCS_OK) return st;
   D.device = d;
   *out = d;
   return TMCS_OK;
@@ -821,14 +829,14 @@ constexpr int64_t DECODE_CHUNK_MIN = 4096;
 }  // namespace
 
 tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t* det, uint64_t n_shots,
-                       uint64_t* pred, tmcs_decode_stats* stats, hipStream_t stream) {
+                       uint64_t* pred, tmcs_decode_stats* stats, hipStream_t stream, void* state) {
   if (n_shots == 0) return TMCS_OK;
   if (!det && D.rows) return fail(TMCS_EINVAL, "null detector buffer");
   if (!pred && D.nobs) return fail(TMCS_EINVAL, "null prediction buffer");
   if (n_shots > (1ull << 40)) return fail(TMCS_EINVAL, "n_shots too large");
-  DecodeDevice* d = nullptr;
-  tmcs_status st = ensure_device(D, &d);
-  if (st != TMCS_OK) return st;
+  DecodeDevice* d = (DecodeDevice*)state;
+  tmcs_status st = TMCS_OK;
+  if (!d && (st = ensure_device(D, &d)) != TMCS_OK) return st;
   const int64_t stride = (int64_t)((n_shots + 63) / 64);
   const bool full = cfg.ehat_dev || cfg.llr_dev || cfg.iters_dev || cfg.flags_dev;
   const int mw = (D.rows + 63) / 64;
@@ -952,6 +960,76 @@ tmcs_status ler_run(const uint64_t* pred, const uint64_t* obs, uint32_t k, uint6
   if (st != TMCS_OK) return st;
   *n_err = h;
   return TMCS_OK;
+}
+
+tmcs_status count_errors_async(const uint64_t* pred, const uint64_t* obs, uint32_t k, uint64_t n_shots,
+                               unsigned long long* counter, hipStream_t stream) {
+  if (n_shots == 0 || k == 0) return TMCS_OK;
+  const int64_t stride = (int64_t)((n_shots + 63) / 64);
+  const int64_t g = std::min<int64_t>((stride + 255) / 256, 2048);
+  TMCS_LAUNCH("k_count_errors", k_count_errors, dim3((unsigned)g), dim3(256), 0, stream, pred, obs, k, stride, n_shots,
+              counter);
+  return hip_check(hipGetLastError(), "k_count_errors launch");
+}
+
+// Launch-shape search: decode the caller's syndromes with every candidate shape
+// and keep the fastest.  Results never depend on the launch shape, only time.
+tmcs_status autotune_run(const Dem& D, const uint64_t* det, uint64_t n_shots, tmcs_decoder_cfg* cfg,
+                         hipStream_t stream) {
+  if (n_shots == 0) return fail(TMCS_EINVAL, "autotune needs shots");
+  uint64_t* pred = nullptr;
+  const int64_t stride = (int64_t)((n_shots + 63) / 64);
+  if (hipMalloc((void**)&pred, (size_t)std::max(D.nobs, 1) * stride * 8) != hipSuccess)
+    return fail(TMCS_ENOMEM, "hipMalloc (autotune)");
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  tmcs_decoder_cfg base = *cfg;
+  base.ehat_dev = nullptr; base.llr_dev = nullptr; base.iters_dev = nullptr; base.flags_dev = nullptr;
+  tmcs_decoder_cfg best = base;
+  float best_ms = 1e30f;
+  const int threads[] = {128, 256, 512};
+  const int bp_cu[] = {4, 16};
+  const int osd_cu[] = {2, 4, 8};
+  tmcs_status st = TMCS_OK;
+  for (int th : threads)
+    for (int bc : bp_cu)
+      for (int oc : osd_cu) {
+        tmcs_decoder_cfg c = base;
+        c.bp_threads = th; c.bp_per_cu = bc; c.osd_per_cu = oc; c.bp_slots = 1;
+        if ((st = decode_run(D, c, det, n_shots, pred, nullptr, stream)) != TMCS_OK) break;   // warm
+        (void)hipEventRecord(e0, stream);
+        if ((st = decode_run(D, c, det, n_shots, pred, nullptr, stream)) != TMCS_OK) break;
+        (void)hipEventRecord(e1, stream);
+        if ((st = hip_check(hipEventSynchronize(e1), "autotune")) != TMCS_OK) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best = c; }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  hipFree(pred);
+  if (st != TMCS_OK) return st;
+  cfg->bp_threads = best.bp_threads;
+  cfg->bp_per_cu = best.bp_per_cu;
+  cfg->osd_per_cu = best.osd_per_cu;
+  cfg->bp_slots = best.bp_slots;
+  return TMCS_OK;
+}
+
+void* decode_state_new(const Dem& D, tmcs_status* st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { *st = fail(TMCS_EDEVICE, "no HIP device"); return nullptr; }
+  DecodeDevice* d = nullptr;
+  *st = build_state(D, dev, &d);
+  return d;
+}
+
+void decode_state_free(void* state) {
+  DecodeDevice* d = (DecodeDevice*)state;
+  if (!d) return;
+  free_device(d);
+  delete d;
 }
 
 void decode_release(Dem& D) {

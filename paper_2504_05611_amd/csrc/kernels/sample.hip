@@ -98,8 +98,9 @@ __device__ __forceinline__ void event_stream(uint32_t k0, uint32_t k1, uint32_t 
 __global__ void k_event_count(int64_t nsites, int64_t nblk, int64_t blk0, uint32_t k0, uint32_t k1,
                               uint32_t inst, const uint8_t* __restrict__ site_kind,
                               const uint16_t* __restrict__ site_tab, const uint64_t* __restrict__ tabs,
-                              uint32_t* __restrict__ counts) {
+                              uint32_t* __restrict__ counts, const uint64_t* __restrict__ blk_off) {
   const int64_t n = nsites * nblk;
+  if (blk_off) blk0 += (int64_t)*blk_off;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = i / nsites, s = i - b * nsites;
@@ -115,8 +116,10 @@ __global__ void k_event_write(int64_t nsites, int64_t nblk, int64_t blk0, uint32
                               uint32_t inst, const uint8_t* __restrict__ site_kind,
                               const uint16_t* __restrict__ site_tab, const uint64_t* __restrict__ tabs,
                               const uint32_t* __restrict__ offsets, uint16_t* __restrict__ events,
-                              uint32_t capacity, uint32_t* __restrict__ overflow) {
+                              uint32_t capacity, uint32_t* __restrict__ overflow,
+                              const uint64_t* __restrict__ blk_off) {
   const int64_t n = nsites * nblk;
+  if (blk_off) blk0 += (int64_t)*blk_off;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = i / nsites, s = i - b * nsites;
@@ -375,14 +378,8 @@ void free_device(SampleDevice* d) {
   *d = SampleDevice();
 }
 
-tmcs_status ensure_device(const Circuit& cc, SampleDevice** out) {
-  Circuit& c = const_cast<Circuit&>(cc);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(TMCS_EDEVICE, "no HIP device");
-  SampleDevice* d = (SampleDevice*)c.device;
-  if (d && d->device == dev) { *out = d; return TMCS_OK; }
-  if (d) { free_device(d); delete d; c.device = nullptr; }
-  d = new SampleDevice();
+tmcs_status build_state(const Circuit& c, int dev, SampleDevice** out) {
+  SampleDevice* d = new SampleDevice();
   d->device = dev;
   tmcs_status st = compile_program(c, &d->prog);
   if (st != TMCS_OK) { delete d; return st; }
@@ -411,6 +408,20 @@ tmcs_status ensure_device(const Circuit& cc, SampleDevice** out) {
     delete d;
     return fail(TMCS_ENOMEM, "hipMalloc failed (flag)");
   }
+  *out = d;
+  return TMCS_OK;
+}
+
+// The device state cached on the circuit handle (rebuilt when the device changes).
+tmcs_status ensure_device(const Circuit& cc, SampleDevice** out) {
+  Circuit& c = const_cast<Circuit&>(cc);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(TMCS_EDEVICE, "no HIP device");
+  SampleDevice* d = (SampleDevice*)c.device;
+  if (d && d->device == dev) { *out = d; return TMCS_OK; }
+  if (d) { free_device(d); delete d; c.device = nullptr; }
+  tmcs_status st = build_state(c, dev, &d);
+  if (st != TMCS_OK) return st;
   c.device = d;
   *out = d;
   return TMCS_OK;
@@ -449,14 +460,15 @@ tmcs_status launch_frame(const FrameArgs& a, int64_t nwg, size_t lds, hipStream_
 }  // namespace
 
 tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint64_t shot_begin,
-                       uint64_t n_shots, uint64_t* det, uint64_t* obs, hipStream_t stream) {
+                       uint64_t n_shots, uint64_t* det, uint64_t* obs, hipStream_t stream,
+                       const uint64_t* blk_off, uint32_t* overflow_out, void* state) {
   if (shot_begin % 64) return fail(TMCS_EINVAL, "shot_begin must be a multiple of 64");
   if (n_shots == 0) return TMCS_OK;
   if ((c.num_dets && !det) || (c.num_obs && !obs)) return fail(TMCS_EINVAL, "null output buffer");
   if ((shot_begin + n_shots) / SB >= (1ull << 32)) return fail(TMCS_EINVAL, "shot index beyond 2^44");
-  SampleDevice* d = nullptr;
-  tmcs_status st = ensure_device(c, &d);
-  if (st != TMCS_OK) return st;
+  SampleDevice* d = (SampleDevice*)state;
+  tmcs_status st = TMCS_OK;
+  if (!d && (st = ensure_device(c, &d)) != TMCS_OK) return st;
   const Program& P = d->prog;
   const int64_t nsites = (int64_t)P.site_kind.size();
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu), k1 = (uint32_t)(seed >> 32);
@@ -466,7 +478,9 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
   size_t lds = 0;
   const int F = frame_words_per_wg(P, c.num_qubits, &lds);
   if (lds > 160 * 1024) return fail(TMCS_EUNSUPPORTED, "circuit frame exceeds the 160 KB LDS of one workgroup");
-  TMCS_LAUNCH("k_zero_u32", k_zero_u32, dim3(1), dim3(64), 0, stream, d->flag, 1);
+  // the overflow flag: per call, or a caller-owned sticky flag (graph replays)
+  uint32_t* flag = overflow_out ? overflow_out : d->flag;
+  if (!overflow_out) TMCS_LAUNCH("k_zero_u32", k_zero_u32, dim3(1), dim3(64), 0, stream, flag, 1);
   // chunk of blocks: bound the per-(block, site) arrays to ~64M entries
   const int64_t blk_first = (int64_t)(shot_begin / SB);
   const int64_t blk_last = (int64_t)((shot_end - 1) / SB);
@@ -490,13 +504,13 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
       const int thr = 256;
       const int64_t grid = std::min<int64_t>((n + thr - 1) / thr, 1 << 20);
       TMCS_LAUNCH("k_event_count", k_event_count, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
-                         instance, d->site_kind, d->site_tab, d->tabs, d->counts);
+                         instance, d->site_kind, d->site_tab, d->tabs, d->counts, blk_off);
       TMCS_LAUNCH("k_scan_partials", k_scan_partials, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial);
       TMCS_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, stream, d->partial, ntiles);
       TMCS_LAUNCH("k_scan_final", k_scan_final, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial, d->offsets);
       TMCS_LAUNCH("k_event_write", k_event_write, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
                          instance, d->site_kind, d->site_tab, d->tabs, d->offsets, d->events,
-                         (uint32_t)d->cap_events, d->flag);
+                         (uint32_t)d->cap_events, flag, blk_off);
       if ((st = hip_check(hipGetLastError(), "event kernels")) != TMCS_OK) return st;
     }
     FrameArgs a;
@@ -522,12 +536,28 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
     }
     if (st != TMCS_OK) return st;
   }
-  uint32_t flag = 0;
-  if ((st = hip_check(hipMemcpyAsync(&flag, d->flag, sizeof(flag), hipMemcpyDeviceToHost, stream), "flag copy")) != TMCS_OK)
+  if (overflow_out) return TMCS_OK;   // checked by the owner of the flag
+  uint32_t hflag = 0;
+  if ((st = hip_check(hipMemcpyAsync(&hflag, d->flag, sizeof(hflag), hipMemcpyDeviceToHost, stream), "flag copy")) != TMCS_OK)
     return st;
   if ((st = hip_check(hipStreamSynchronize(stream), "sample synchronize")) != TMCS_OK) return st;
-  if (flag) return fail(TMCS_EDEVICE, "noise event buffer overflow");
+  if (hflag) return fail(TMCS_EDEVICE, "noise event buffer overflow");
   return TMCS_OK;
+}
+
+void* sample_state_new(const Circuit& c, tmcs_status* st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { *st = fail(TMCS_EDEVICE, "no HIP device"); return nullptr; }
+  SampleDevice* d = nullptr;
+  *st = build_state(c, dev, &d);
+  return d;
+}
+
+void sample_state_free(void* state) {
+  SampleDevice* d = (SampleDevice*)state;
+  if (!d) return;
+  free_device(d);
+  delete d;
 }
 
 void sample_release(Circuit& c) {

@@ -62,6 +62,11 @@ class DecodeStats(ctypes.Structure):
                 ("reserved", ctypes.c_uint64 * 2)]
 
 
+class PlanItem(ctypes.Structure):
+    _fields_ = [("circuit", ctypes.c_void_p), ("dem", ctypes.c_void_p), ("cfg", DecoderCfg),
+                ("seed", ctypes.c_uint64), ("instance", ctypes.c_uint32)]
+
+
 _vp, _u64, _u32, _i32, _sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_size_t
 _SIGS = {
     "tmcs_build_circuit": [ctypes.POINTER(_Spec), ctypes.POINTER(_vp)],
@@ -79,6 +84,11 @@ _SIGS = {
     "tmcs_wbp_workspace_size": [_vp, _i32, _u64, ctypes.POINTER(_sz)],
     "tmcs_wbp_forward": [_vp, _vp, _i32, _vp, _u64, _vp, _vp, _sz, _vp],
     "tmcs_wbp_backward": [_vp, _vp, _i32, _vp, _u64, _vp, _vp, _vp, _sz, _vp],
+    "tmcs_autotune": [_vp, _vp, _u64, ctypes.POINTER(DecoderCfg), _vp],
+    "tmcs_plan_create": [ctypes.POINTER(PlanItem), _i32, _u64, _i32, ctypes.POINTER(_vp)],
+    "tmcs_plan_run": [_vp, _u32, _vp],
+    "tmcs_plan_result": [_vp, _i32, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(DecodeStats), _vp],
+    "tmcs_plan_free": [_vp],
     "tmcs_timing_enable": [ctypes.c_int],
     "tmcs_timing_reset": [],
     "tmcs_timing_report": [_vp, ctypes.c_char_p, _sz, ctypes.POINTER(_sz)][1:],
@@ -91,6 +101,7 @@ for _name, _args in _SIGS.items():
 _lib.tmcs_last_error.restype = ctypes.c_char_p
 _lib.tmcs_free_circuit.restype = None
 _lib.tmcs_free_dem.restype = None
+_lib.tmcs_plan_free.restype = None
 
 EXPORTED = sorted(_SIGS)
 
@@ -145,7 +156,7 @@ class Circuit:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.tmcs_free_circuit(h)
             self._h = None
 
@@ -197,7 +208,7 @@ class DEM:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.tmcs_free_dem(h)
             self._h = None
 
@@ -252,6 +263,57 @@ class DEM:
         _check(_lib.tmcs_wbp_backward(self._h, _ptr(weights), T, _ptr(det), n_shots, _ptr(grad_llr),
                                       _ptr(grad_w), _ptr(workspace),
                                       workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def make_cfg(max_iter=30, alpha=1.0, weights=None, use_osd=True, bp_threads=0, bp_per_cu=0,
+             osd_per_cu=0, bp_slots=0):
+    return DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads, bp_per_cu,
+                      osd_per_cu, bp_slots, None, None, None, None)
+
+
+def autotune(dem, det, n_shots, cfg=None, stream=None) -> DecoderCfg:
+    """Fastest decoder launch shape for these syndromes (fields of DecoderCfg)."""
+    cfg = cfg or make_cfg()
+    _check(_lib.tmcs_autotune(dem._h, _ptr(det), n_shots, ctypes.byref(cfg), _stream(stream)))
+    return cfg
+
+
+class Plan:
+    """Preallocated (optionally graph-captured) sample -> decode -> count batches.
+
+    items: list of (circuit, dem, DecoderCfg, seed, instance)."""
+
+    def __init__(self, items, batch_shots, use_graph=True):
+        self._keep = items
+        arr = (PlanItem * len(items))()
+        for i, (c, d, cfg, seed, inst) in enumerate(items):
+            arr[i].circuit = c._h
+            arr[i].dem = d._h
+            arr[i].cfg = cfg
+            arr[i].seed = seed
+            arr[i].instance = inst
+        h = ctypes.c_void_p()
+        _check(_lib.tmcs_plan_create(arr, len(items), batch_shots, 1 if use_graph else 0, ctypes.byref(h)))
+        self._h = h
+        self.batch = batch_shots
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.tmcs_plan_free(h)
+            self._h = None
+
+    def run(self, n_batches, stream=None):
+        _check(_lib.tmcs_plan_run(self._h, n_batches, _stream(stream)))
+
+    def result(self, item=0, stream=None):
+        shots = ctypes.c_uint64()
+        errs = ctypes.c_uint64()
+        st = DecodeStats()
+        _check(_lib.tmcs_plan_result(self._h, item, ctypes.byref(shots), ctypes.byref(errs), ctypes.byref(st),
+                                     _stream(stream)))
+        return dict(shots=shots.value, errors=errs.value, nontrivial=st.nontrivial, converged=st.converged,
+                    osd=st.osd, not_in_span=st.not_in_span, bp_iters=st.bp_iters, stat_shots=st.shots)
 
 
 def logical_error_rate(pred, obs, k, n_shots, stream=None):

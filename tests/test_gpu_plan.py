@@ -1,0 +1,61 @@
+"""Graph-captured batch plans and the autotuner against eager calls."""
+import numpy as np
+import pytest
+
+from workloads import MEMORY, NLCNOT, bb, sc
+
+pytestmark = pytest.mark.gpu
+
+
+def _eager(tmcs, c, dem, seed, inst, begin, n, T):
+    import torch
+    det, obs = c.alloc_outputs(n)
+    c.sample(seed, inst, begin, n, det, obs)
+    pred = torch.zeros_like(obs)
+    st = tmcs.new_stats()
+    dem.decode(det, n, pred, max_iter=T, stats=st)
+    ne, _, _ = tmcs.logical_error_rate(pred, obs, c.num_observables, n)
+    return ne, tmcs.read_stats(st)
+
+
+@pytest.mark.parametrize("use_graph", [True, False], ids=["graph", "eager-plan"])
+def test_plan_matches_eager(gpu_lib, use_graph):
+    import torch
+    specs = [sc(5, NLCNOT, 3, 3, 3e-3, 2e-2), sc(5, NLCNOT, 3, 3, 6e-3, 2e-2), bb("bb18", MEMORY, 3, 0, 4e-3)]
+    B, T = 8192, 30
+    circuits = [gpu_lib.Circuit(s) for s in specs]
+    dems = [gpu_lib.DEM(c) for c in circuits]
+    items = [(c, d, gpu_lib.make_cfg(max_iter=T), 9, i) for i, (c, d) in enumerate(zip(circuits, dems))]
+    plan = gpu_lib.Plan(items, B, use_graph=use_graph)
+    plan.run(1)
+    torch.cuda.synchronize()
+    # eager work between replays
+    ref = [_eager(gpu_lib, c, d, 9, i, 0, 3 * B, T) for i, (c, d) in enumerate(zip(circuits, dems))]
+    plan.run(2)
+    for i in range(len(items)):
+        r = plan.result(i)
+        print(f"[plan] item {i} {r} eager {ref[i]}", flush=True)
+        assert r["shots"] == 3 * B
+        assert r["errors"] == ref[i][0]
+        assert r["stat_shots"] == 3 * B
+        assert r["osd"] == ref[i][1]["osd"] and r["converged"] == ref[i][1]["converged"]
+        assert r["bp_iters"] == ref[i][1]["bp_iters"]
+
+
+def test_autotune_keeps_results(gpu_lib):
+    import torch
+    spec = sc(5, NLCNOT, 3, 3, 4e-3, 2e-2)
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    n = 20000
+    det, obs = c.alloc_outputs(n)
+    c.sample(1, 0, 0, n, det, obs)
+    cfg = gpu_lib.autotune(dem, det, n, gpu_lib.make_cfg(max_iter=30))
+    assert cfg.bp_threads in (128, 256, 512) and cfg.osd_per_cu in (2, 4, 8)
+    p1 = torch.zeros_like(obs)
+    p2 = torch.zeros_like(obs)
+    dem.decode(det, n, p1, max_iter=30)
+    dem.decode(det, n, p2, max_iter=30, bp_threads=cfg.bp_threads, bp_per_cu=cfg.bp_per_cu,
+               osd_per_cu=cfg.osd_per_cu)
+    torch.cuda.synchronize()
+    assert (p1.cpu().numpy() == p2.cpu().numpy()).all()
