@@ -21,7 +21,7 @@ accumulated left to right), which is the precision in which the GPU decoder
 takes its hard decisions and OSD orderings.
 
 Parity: pinned against exact min-marginals on tree-shaped (repetition-code)
-graphs by brute force (tests/test_oracle_bp.py).
+graphs by brute force (tests/test_oracle_decoder.py).
 """
 from __future__ import annotations
 

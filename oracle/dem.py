@@ -23,7 +23,7 @@ sorted by (sorted detector list, observable mask) lexicographically.
 
 Parity: pinned by brute-force circuit distance of the d=3 surface-code
 operations (Table I) and by the detector marginals of sampled shots
-(tests/test_oracle_dem.py).
+(tests/test_oracle_circuits.py, tests/test_oracle_sampler.py).
 """
 from __future__ import annotations
 

@@ -24,7 +24,7 @@ draws its events per 4096-shot block.  Components: DEPOLARIZE1 0->X, 1->Y,
 Parity: pinned against the stabilizer tableau on small circuits (noiseless
 all-zero detectors; identical detector bits under injected Paulis) and, for
 the noise statistics, against detector marginals predicted by the detector
-error model (tests/test_oracle_frame.py).
+error model (tests/test_oracle_circuits.py, tests/test_oracle_sampler.py).
 """
 from __future__ import annotations
 

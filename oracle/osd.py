@@ -21,7 +21,7 @@ otherwise OSD-0 runs on BP's final posterior LLRs.
 
 Parity: H e = s is checked on every call; the solution is cross-checked with
 a dense Gauss-Jordan solve on the same column set, and on tiny codes with
-exhaustive search (tests/test_oracle_osd.py).
+exhaustive search (tests/test_oracle_decoder.py).
 """
 from __future__ import annotations
 
