@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <type_traits>
 #include <vector>
 
@@ -47,6 +48,13 @@ struct DecodeDevice {
   int32_t *row_ptr = nullptr, *col_idx = nullptr, *col_ptr = nullptr, *csc_row = nullptr, *csc_edge = nullptr;
   float* lam = nullptr;
   uint64_t* obs_mask = nullptr;
+  int4* init = nullptr;            // [m] BP check state of iteration 1
+  uint32_t* sign0 = nullptr;       // [E4 / 4] sign bytes of iteration 1
+  int32_t E4 = 0;
+  int32_t max_row_deg = 0;
+  // per-lane BP schedules, one per team size used so far
+  struct Sched { int P = 0; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr; };
+  std::vector<Sched> scheds;
   // scratch
   int32_t* counters = nullptr;     // [0] queue len, [1] bp next, [2] osd len, [3] osd next
   int32_t* queue = nullptr;
@@ -57,16 +65,27 @@ struct DecodeDevice {
   size_t cap_queue = 0, cap_osd = 0, cap_llr = 0, cap_basis = 0, cap_synd = 0;
 };
 
+// Per-lane schedule records of the BP passes (int4 = {x, y, z, w}).
+//   check pass: x = v | flags, y = CSR edge e, z = check c (edges of a check are
+//               consecutive in one lane, in CSR order)
+//   var pass:   x = v | flags, y = CSR edge e, z = check c (entries of a column
+//               are consecutive in one lane, in CSC order)
+constexpr int32_t R_FIRST = 1 << 30;    // first edge of its check / column
+constexpr int32_t R_LAST = (int32_t)(1u << 31);
+constexpr int32_t R_IDX = (1 << 30) - 1;
+
 struct BPArgs {
-  const int32_t* row_ptr;
-  const int32_t* col_idx;
-  const int32_t* col_ptr;
-  const int32_t* csc_row;
-  const int32_t* csc_edge;
+  const int4* csched;        // [Kc][P] check-pass records
+  const int4* vsched;        // [Kv][P] variable-pass records
+  int32_t Kc, Kv;
+  const int4* init;          // [m] check state of iteration 1 (n1, n2 bits, argmin edge, sign parity)
+  const uint32_t* sign0;     // [E4 / 4] sign bytes of q at iteration 1
   const float* lam;
   const uint64_t* obs_mask;
   int32_t m, n;
   int64_t E;
+  int32_t E32;               // E as int32
+  int32_t E4;                // E rounded up to a multiple of 4
   int32_t T;
   float alpha;
   const float* w;            // nullable [T][E]
@@ -149,252 +168,187 @@ __global__ void k_compact(const uint64_t* __restrict__ synd, int32_t mw, int64_t
   }
 }
 
-// Slot states of the BP kernel.
-enum : int32_t { SLOT_EMPTY = 0, SLOT_NEW = 1, SLOT_ACTIVE = 2, SLOT_DONE = 3 };
-
-// BP over a persistent workgroup that carries S shots ("slots") at once, each at
-// its own iteration; a slot whose shot has converged (or used its T iterations)
-// is finalised and refilled from the queue independently of the others.
+// BP over persistent teams: one workgroup (a "team" of P = blockDim.x lanes)
+// decodes one shot at a time, with the whole per-shot state in LDS.  Work is
+// split over the lanes by static schedules built once per DEM and team size
+// (longest-processing-time assignment of whole checks, and of whole columns,
+// to lanes), so every step of a pass is one edge per lane with no intra-pass
+// synchronisation; a pass ends with one barrier.
 //
-// MSG = true keeps every check-to-variable message m_{c->v} in LDS (CSR edge
-// order); the check pass first turns m_old into q = L_v - m_old in place, then
-// writes the new messages, and the variable pass is a plain sum.  MSG = false
-// keeps the compressed check state instead - (min1, min2, argmin edge, sign
-// parity) per check and one sign bit per edge - and rebuilds messages from it;
-// it needs ~4 bytes per column + 13 per check instead of 4 per edge, for DEMs
-// whose messages do not fit.
-template <bool MSG>
-__global__ void k_bp(BPArgs a, int32_t S) {
-  extern __shared__ __align__(8) unsigned char sm[];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int m = a.m, n = a.n;
-  const int64_t E = a.E;
-  const int64_t nwords = (E + 31) / 32;
-  // per-slot arrays (slot-major)
-  float* Lf = (float*)sm;                                             // [S][n]
-  float* msg = Lf + (size_t)S * n;                                    // MSG:  [S][E]
-  float* min1 = msg;                                                  // !MSG: [S][m]
-  float* min2 = min1 + (size_t)S * m;                                 // !MSG: [S][m]
-  int32_t* arg = (int32_t*)(min2 + (size_t)S * m);                    // !MSG: [S][m]
-  uint32_t* esign = (uint32_t*)(arg + (size_t)S * m);                 // !MSG: [S][nwords]
-  uint8_t* cflag = MSG ? (uint8_t*)(msg + (size_t)S * E) : (uint8_t*)(esign + (size_t)S * nwords);  // [S][m]
-  __shared__ int32_t st[16], tt[16], ls_of[16], flag[16], osdpos[16], itr[16];
-  __shared__ unsigned long long pmask[16];
-  __shared__ int s_exit;
+// Per-shot LDS state (compressed): for every check (n1, n2) = the two smallest
+// |q_{v->c}|, the argmin edge, the sign parity of the q's and the syndrome bit;
+// one sign byte per edge (sign of q_{v->c}); L_v per column.  Messages are
+// rebuilt from it: m_{c->v} = (-1)^{s_c + parity + sgn q_e} alpha_t(e) *
+// (e == argmin ? n2 : n1).
+//
+// Iteration 1 needs no check pass: with q_{v->c} = lambda_v its state depends
+// on the DEM alone (precomputed, plus the syndrome bit).  Iteration t is then a
+// variable pass (L^t) followed by a check pass that tests H [L^t < 0] = s and,
+// if t < T, builds the state of iteration t + 1.
+template <bool WEIGHTED>
+__global__ void __launch_bounds__(1024) k_bp(BPArgs a) {
+  extern __shared__ __align__(16) unsigned char sm[];
+  float4* state = (float4*)sm;                        // [m + 1] (slot m: padding records)
+  float* L = (float*)(state + a.m + 1);               // [n]
+  uint8_t* sgn = (uint8_t*)(L + a.n);                 // [E4 + 4] (byte E4: padding records)
+  __shared__ int s_job, s_flag, s_pos;
+  __shared__ int s_unsat[2];
+  __shared__ unsigned long long s_pm;
+  const int tid = threadIdx.x, P = blockDim.x;
   const int32_t total = a.queue ? a.counters[0] : (int32_t)a.nshots;
-  if (tid < S) {
-    const int job = atomicAdd(&a.counters[1], 1);
-    st[tid] = job < total ? SLOT_NEW : SLOT_EMPTY;
-    ls_of[tid] = job < total ? (a.queue ? a.queue[job] : job) : 0;
-    flag[tid] = 0;
-  }
-  __syncthreads();
+  unsigned long long c_nontriv = 0, c_conv = 0, c_osd = 0, c_iters = 0;   // thread 0
   while (true) {
-    // 1. initialise new slots: syndrome bits, zero messages / check state, L = lambda
-    for (int sl = 0; sl < S; ++sl) {
-      if (st[sl] != SLOT_NEW) continue;
-      const uint64_t* sy = a.synd + (int64_t)ls_of[sl] * a.mw;
-      uint8_t* cf = cflag + sl * m;
-      for (int c = tid; c < m; c += nt) {
+    if (tid == 0) {
+      s_job = atomicAdd(&a.counters[1], 1);
+      s_flag = 0;
+      s_unsat[0] = 0;
+      s_unsat[1] = 0;
+      s_pm = 0ull;
+    }
+    __syncthreads();
+    const int job = s_job;
+    if (job >= total) break;
+    const int64_t ls = a.queue ? a.queue[job] : job;
+    const int64_t shot = a.shot0 + ls;
+    // state of iteration 1, L = lambda, initial signs
+    {
+      const uint64_t* sy = a.synd + ls * a.mw;
+      int fl = 0;
+      for (int c = tid; c < a.m; c += P) {
+        int4 s0 = a.init[c];
         const int sb = (int)((sy[c >> 6] >> (c & 63)) & 1ull);
-        cf[c] = (uint8_t)(sb << 1);
-        if (!MSG) {
-          min1[sl * m + c] = 0.0f;
-          min2[sl * m + c] = 0.0f;
-          arg[sl * m + c] = -1;
+        fl |= sb | ((s0.z < 0 && sb) ? 2 : 0);   // bit 1: a check without edges can never be satisfied
+        s0.w |= sb << 1;
+        state[c] = make_float4(__int_as_float(s0.x), __int_as_float(s0.y), __int_as_float(s0.z),
+                               __int_as_float(s0.w));
+      }
+      for (int v = tid; v < a.n; v += P) L[v] = a.lam[v];
+      for (int i = tid; i < (a.E4 >> 2); i += P) ((uint32_t*)sgn)[i] = a.sign0[i];
+      if (fl) atomicOr(&s_flag, fl);
+    }
+    __syncthreads();
+    const int f0 = s_flag;
+    int itr = 0;
+    bool conv = true;
+    if (f0 & 1) {
+      conv = false;
+      for (int t = 1;; ++t) {
+        // variable pass: L^t from the state of iteration t
+        {
+          const float* wt = WEIGHTED ? a.w + (int64_t)(t - 1) * a.E : nullptr;
+          float acc = 0.0f;
+          auto vstep = [&](const int4 r) {
+            const int v = r.x & R_IDX, e = r.y, c = r.z;
+            const float4 s = state[c];
+            const int se = sgn[e];
+            const float at = WEIGHTED ? wt[e < a.E32 ? e : 0] : a.alpha;
+            const float mag = __fmul_rn(at, e == __float_as_int(s.z) ? s.y : s.x);
+            const int fl = __float_as_int(s.w);
+            const float base = (r.x & R_FIRST) ? __int_as_float(r.w) : acc;   // lambda_v on a column's first edge
+            acc = __fadd_rn(base, (((fl >> 1) ^ fl ^ se) & 1) ? -mag : mag);
+            if (r.x & R_LAST) L[v] = acc;
+          };
+          // records are read two steps ahead; the schedule holds two rows of
+          // padding past its (even) length, so every read is in bounds
+          const int4* rp = a.vsched + tid;
+          int4 ra = rp[0], rb = rp[P];
+          for (int k = 0; k < a.Kv; k += 2) {
+            vstep(ra);
+            ra = rp[(size_t)(k + 2) * P];
+            vstep(rb);
+            rb = rp[(size_t)(k + 3) * P];
+          }
         }
-        if (sb) flag[sl] = 1;                              // benign race: every writer stores 1
-      }
-      float* L = Lf + (size_t)sl * n;
-      for (int v = tid; v < n; v += nt) L[v] = a.lam[v];
-      if (MSG) {
-        float* ms = msg + (size_t)sl * E;
-        for (int64_t e = tid; e < E; e += nt) ms[e] = 0.0f;
-      } else {
-        uint32_t* es = esign + (size_t)sl * nwords;
-        for (int64_t i = tid; i < nwords; i += nt) es[i] = 0u;
-      }
-    }
-    __syncthreads();
-    if (tid < S && st[tid] == SLOT_NEW) {
-      if (flag[tid]) { st[tid] = SLOT_ACTIVE; tt[tid] = 1; flag[tid] = 0; }
-      else { st[tid] = SLOT_DONE; itr[tid] = 0; osdpos[tid] = -1; flag[tid] = 1; pmask[tid] = 0ull; }
-    }
-    __syncthreads();
-    // 2. check pass: convergence of L^{(t-1)} and the messages of iteration t
-    for (int sl = 0; sl < S; ++sl) {
-      if (st[sl] != SLOT_ACTIVE) continue;
-      const int t = tt[sl];
-      const bool update = t <= a.T;
-      const float* L = Lf + (size_t)sl * n;
-      const uint8_t* cf = cflag + sl * m;
-      int unsat = 0;
-      for (int c = tid; c < m; c += nt) {
-        const int32_t r0 = a.row_ptr[c], r1 = a.row_ptr[c + 1];
-        const int sc = (cf[c] >> 1) & 1;
-        int hard = 0, npar = 0;
-        float n1 = BP_BIG, n2 = BP_BIG;
-        int32_t nag = -1;
-        if (MSG) {
-          float* ms = msg + (size_t)sl * E;
-          for (int32_t e = r0; e < r1; ++e) {
-            const float Lv = L[a.col_idx[e]];
-            hard ^= Lv < 0.0f ? 1 : 0;
-            const float q = __fsub_rn(Lv, ms[e]);           // q_{v->c} = L_v - m_old
-            ms[e] = q;
-            const float aq = fabsf(q);
-            if (aq < n1) { n2 = n1; n1 = aq; nag = e; }
-            else if (aq < n2) { n2 = aq; }
-            npar ^= q < 0.0f ? 1 : 0;
-          }
-          if (update) {
-            const float* wt = a.w ? a.w + (int64_t)(t - 1) * E : nullptr;
-            for (int32_t e = r0; e < r1; ++e) {
-              const float q = ms[e];
-              const float at = wt ? wt[e] : a.alpha;
-              const float mag = __fmul_rn(at, e == nag ? n2 : n1);
-              ms[e] = (sc ^ npar ^ (q < 0.0f ? 1 : 0)) ? -mag : mag;
-            }
-          }
-        } else {
-          uint32_t* es = esign + (size_t)sl * nwords;
-          const float m1 = min1[sl * m + c], m2 = min2[sl * m + c];
-          const int32_t ag = arg[sl * m + c];
-          const int sp = cf[c] & 1;
-          for (int32_t e0 = r0; e0 < r1; e0 += 4) {
-            int32_t vv[4];
-            float Lv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) vv[u] = e0 + u < r1 ? a.col_idx[e0 + u] : 0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) Lv[u] = L[vv[u]];
-            const int32_t elast = e0 + 3 < r1 ? e0 + 3 : r1 - 1;   // a batch spans <= 2 sign words
-            const uint32_t sw0 = es[e0 >> 5], sw1 = es[elast >> 5];
-            uint32_t flip0 = 0u, flip1 = 0u;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int32_t e = e0 + u;
-              if (e >= r1) break;
-              hard ^= Lv[u] < 0.0f ? 1 : 0;
-              if (!update) continue;
-              const bool hi = (e >> 5) != (e0 >> 5);
-              const int se = (int)(((hi ? sw1 : sw0) >> (e & 31)) & 1u);
-              const float aold = (t == 1) ? 1.0f : (a.w ? a.w[(int64_t)(t - 2) * E + e] : a.alpha);
-              const float mag = __fmul_rn(aold, e == ag ? m2 : m1);
-              const float mo = (sc ^ sp ^ se) ? -mag : mag;
-              const float q = __fsub_rn(Lv[u], mo);
+        __syncthreads();
+        // check pass: H [L^t < 0] = s ?  and, if t < T, the state of iteration t + 1
+        const bool update = t < a.T;
+        int unsat = (f0 >> 1) & 1;
+        {
+          const float* wo = WEIGHTED ? a.w + (int64_t)(t - 1) * a.E : nullptr;   // weights of the messages m^t
+          float n1o = 0.0f, n2o = 0.0f, n1 = BP_BIG, n2 = BP_BIG;
+          int nago = -1, nag = -1, sc = 0, spo = 0, npar = 0, hard = 0;
+          auto cstep = [&](const int4 r) {
+            const int v = r.x & R_IDX, e = r.y, c = r.z;
+            const bool first = (r.x & R_FIRST) != 0;
+            const float4 s = state[c];
+            const float Lv = L[v];
+            const int se = sgn[e];
+            const int fl = __float_as_int(s.w);
+            n1o = first ? s.x : n1o;
+            n2o = first ? s.y : n2o;
+            nago = first ? __float_as_int(s.z) : nago;
+            sc = first ? (fl >> 1) & 1 : sc;
+            spo = first ? fl & 1 : spo;
+            n1 = first ? BP_BIG : n1;
+            n2 = first ? BP_BIG : n2;
+            nag = first ? -1 : nag;
+            npar = first ? 0 : npar;
+            hard = (first ? 0 : hard) ^ (Lv < 0.0f ? 1 : 0);
+            if (update) {
+              const float ao = WEIGHTED ? wo[e < a.E32 ? e : 0] : a.alpha;
+              const float mag = __fmul_rn(ao, e == nago ? n2o : n1o);
+              const float q = __fsub_rn(Lv, (sc ^ spo ^ se) ? -mag : mag);   // q = L_v - m_old
               const float aq = fabsf(q);
               const int ng = q < 0.0f ? 1 : 0;
-              if (aq < n1) { n2 = n1; n1 = aq; nag = e; }
-              else if (aq < n2) { n2 = aq; }
+              const bool lt1 = aq < n1, lt2 = aq < n2;
+              n2 = lt1 ? n1 : (lt2 ? aq : n2);
+              n1 = lt1 ? aq : n1;
+              nag = lt1 ? e : nag;
               npar ^= ng;
-              if (ng != se) {
-                if (hi) flip1 |= 1u << (e & 31); else flip0 |= 1u << (e & 31);
-              }
+              sgn[e] = (uint8_t)ng;
             }
-            if (flip0) atomicXor(&es[e0 >> 5], flip0);
-            if (flip1) atomicXor(&es[elast >> 5], flip1);
-          }
-          if (update) {
-            min1[sl * m + c] = n1;
-            min2[sl * m + c] = n2;
-            arg[sl * m + c] = nag;
-            cflag[sl * m + c] = (uint8_t)((sc << 1) | npar);
-          }
-        }
-        unsat |= hard != sc;
-      }
-      if (unsat) flag[sl] = 1;                               // benign race: every writer stores 1
-    }
-    __syncthreads();
-    // 3. per-slot decision: converged, out of iterations, or one more iteration
-    if (tid < S && st[tid] == SLOT_ACTIVE) {
-      const int t = tt[tid];
-      const bool conv = flag[tid] == 0;
-      if (conv || t > a.T) {
-        st[tid] = SLOT_DONE;
-        itr[tid] = conv ? t - 1 : a.T;
-        flag[tid] = conv ? 1 : 0;                           // flag now = converged
-        pmask[tid] = 0ull;
-        osdpos[tid] = (!conv && a.use_osd) ? atomicAdd(&a.counters[2], 1) : -1;
-      } else {
-        flag[tid] = 0;
-      }
-    }
-    __syncthreads();
-    // 4. variable pass for active slots, finalisation for finished ones
-    for (int sl = 0; sl < S; ++sl) {
-      const int state = st[sl];
-      float* L = Lf + (size_t)sl * n;
-      if (state == SLOT_ACTIVE) {
-        if (MSG) {
-          const float* ms = msg + (size_t)sl * E;
-          for (int v = tid; v < n; v += nt) {
-            float acc = a.lam[v];
-            const int32_t k0 = a.col_ptr[v], k1 = a.col_ptr[v + 1];
-            for (int32_t k = k0; k < k1; ++k) acc = __fadd_rn(acc, ms[a.csc_edge[k]]);
-            L[v] = acc;
-          }
-        } else {
-          const int t = tt[sl];
-          const uint32_t* es = esign + (size_t)sl * nwords;
-          for (int v = tid; v < n; v += nt) {
-            float acc = a.lam[v];
-            const int32_t k0 = a.col_ptr[v], k1 = a.col_ptr[v + 1];
-            for (int32_t k = k0; k < k1; ++k) {
-              const int32_t c = sl * m + a.csc_row[k], e = a.csc_edge[k];
-              const uint8_t fl = cflag[c];
-              const int se = (int)((es[e >> 5] >> (e & 31)) & 1u);
-              const float at = a.w ? a.w[(int64_t)(t - 1) * E + e] : a.alpha;
-              const float mag = __fmul_rn(at, e == arg[c] ? min2[c] : min1[c]);
-              const int neg = ((fl >> 1) ^ fl ^ se) & 1;
-              acc = __fadd_rn(acc, neg ? -mag : mag);
+            if (r.x & R_LAST) {
+              unsat |= hard != sc;
+              if (update)
+                state[c] = make_float4(n1, n2, __int_as_float(nag), __int_as_float((sc << 1) | npar));
             }
-            L[v] = acc;
+          };
+          const int4* rp = a.csched + tid;
+          int4 ra = rp[0], rb = rp[P];
+          for (int k = 0; k < a.Kc; k += 2) {
+            cstep(ra);
+            ra = rp[(size_t)(k + 2) * P];
+            cstep(rb);
+            rb = rp[(size_t)(k + 3) * P];
           }
         }
-      } else if (state == SLOT_DONE) {
-        const int64_t shot = a.shot0 + ls_of[sl];
-        const int pos = osdpos[sl];
-        for (int v = tid; v < n; v += nt) {
-          const float Lv = L[v];
-          if (pos < 0 && Lv < 0.0f && a.obs_mask[v]) atomicXor(&pmask[sl], (unsigned long long)a.obs_mask[v]);
-          if (pos >= 0) a.osd_llr[(int64_t)pos * n + v] = Lv;
-          if (a.llr) a.llr[shot * n + v] = Lv;
-          if (a.ehat && pos < 0) a.ehat[shot * n + v] = Lv < 0.0f ? 1 : 0;
-        }
+        if (unsat) s_unsat[t & 1] = 1;                     // benign race: every writer stores 1
+        if (tid == 0) s_unsat[(t + 1) & 1] = 0;            // read by every lane before the last barrier
+        __syncthreads();
+        if (!s_unsat[t & 1]) { itr = t; conv = true; break; }
+        if (t >= a.T) { itr = a.T; break; }
       }
     }
+    // finalise: prediction from the hard decision, or hand the posteriors to OSD
+    if (tid == 0) s_pos = (!conv && a.use_osd) ? atomicAdd(&a.counters[2], 1) : -1;
     __syncthreads();
-    // 5. finished slots: predictions, statistics, refill
-    if (tid < S) {
-      if (st[tid] == SLOT_ACTIVE) {
-        tt[tid] += 1;
-      } else if (st[tid] == SLOT_DONE) {
-        const int64_t shot = a.shot0 + ls_of[tid];
-        const bool conv = flag[tid] != 0;
-        const int pos = osdpos[tid];
-        if (pos < 0) write_pred(a.pred, a.stride, a.nobs, shot, pmask[tid]);
-        else a.osd_queue[pos] = ls_of[tid];
-        if (a.iters) a.iters[shot] = itr[tid];
-        if (a.flags) a.flags[shot] = (uint8_t)((conv ? 1 : 0) | (pos >= 0 ? 2 : 0));
-        if (a.stats) {
-          if (itr[tid] > 0 || !conv) atomicAdd((unsigned long long*)&a.stats->nontrivial, 1ull);
-          if (conv) atomicAdd((unsigned long long*)&a.stats->converged, 1ull);
-          if (pos >= 0) atomicAdd((unsigned long long*)&a.stats->osd, 1ull);
-          atomicAdd((unsigned long long*)&a.stats->bp_iters, (unsigned long long)itr[tid]);
-        }
-        const int job = atomicAdd(&a.counters[1], 1);
-        st[tid] = job < total ? SLOT_NEW : SLOT_EMPTY;
-        ls_of[tid] = job < total ? (a.queue ? a.queue[job] : job) : 0;
-        flag[tid] = 0;
-      }
+    const int pos = s_pos;
+    uint64_t pm = 0ull;
+    for (int v = tid; v < a.n; v += P) {
+      const float Lv = L[v];
+      if (pos < 0 && Lv < 0.0f) pm ^= a.obs_mask[v];
+      if (pos >= 0) a.osd_llr[(int64_t)pos * a.n + v] = Lv;
+      if (a.llr) a.llr[shot * a.n + v] = Lv;
+      if (a.ehat && pos < 0) a.ehat[shot * a.n + v] = Lv < 0.0f ? 1 : 0;
     }
-    if (tid == 0) s_exit = 1;
+    if (pm) atomicXor(&s_pm, (unsigned long long)pm);
     __syncthreads();
-    if (tid < S && st[tid] != SLOT_EMPTY) s_exit = 0;     // benign race: every writer stores 0
-    __syncthreads();
-    if (s_exit) break;
+    if (tid == 0) {
+      if (pos < 0) write_pred(a.pred, a.stride, a.nobs, shot, s_pm);
+      else a.osd_queue[pos] = (int32_t)ls;
+      if (a.iters) a.iters[shot] = itr;
+      if (a.flags) a.flags[shot] = (uint8_t)((conv ? 1 : 0) | (pos >= 0 ? 2 : 0));
+      c_nontriv += (itr > 0 || !conv) ? 1 : 0;
+      c_conv += conv ? 1 : 0;
+      c_osd += pos >= 0 ? 1 : 0;
+      c_iters += (unsigned long long)itr;
+    }
+  }
+  if (tid == 0 && a.stats) {
+    if (c_nontriv) atomicAdd((unsigned long long*)&a.stats->nontrivial, c_nontriv);
+    if (c_conv) atomicAdd((unsigned long long*)&a.stats->converged, c_conv);
+    if (c_osd) atomicAdd((unsigned long long*)&a.stats->osd, c_osd);
+    if (c_iters) atomicAdd((unsigned long long*)&a.stats->bp_iters, c_iters);
   }
 }
 
@@ -737,7 +691,8 @@ tmcs_status grow(T** p, size_t* cap, size_t need) {
 void free_device(DecodeDevice* d) {
   hipFree(d->row_ptr); hipFree(d->col_idx); hipFree(d->col_ptr); hipFree(d->csc_row); hipFree(d->csc_edge);
   hipFree(d->lam); hipFree(d->obs_mask); hipFree(d->counters); hipFree(d->queue); hipFree(d->osd_queue);
-  hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd);
+  hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd); hipFree(d->init); hipFree(d->sign0);
+  for (auto& q : d->scheds) { hipFree(q.c); hipFree(q.v); }
   *d = DecodeDevice();
 }
 
@@ -756,12 +711,120 @@ tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
     delete d;
     return st;
   }
+  // iteration 1 of BP has q_{v->c} = lambda_v: its check state and edge signs
+  // follow from the DEM alone (same FP32 comparisons as the check pass)
+  std::vector<int4> init(std::max(D.rows, 0));
+  d->E4 = (int32_t)((D.edges + 3) & ~3ll);
+  std::vector<uint8_t> sg((size_t)d->E4, 0);
+  for (int c = 0; c < D.rows; ++c) {
+    float n1 = BP_BIG, n2 = BP_BIG;
+    int nag = -1, npar = 0;
+    for (int32_t e = D.row_ptr[c]; e < D.row_ptr[c + 1]; ++e) {
+      const float q = lam[D.col_idx[e]];
+      const float aq = std::fabs(q);
+      const int ng = q < 0.0f ? 1 : 0;
+      if (aq < n1) { n2 = n1; n1 = aq; nag = e; }
+      else if (aq < n2) { n2 = aq; }
+      npar ^= ng;
+      sg[e] = (uint8_t)ng;
+    }
+    int4 r;
+    std::memcpy(&r.x, &n1, 4);
+    std::memcpy(&r.y, &n2, 4);
+    r.z = nag;
+    r.w = npar;
+    init[c] = r;
+    d->max_row_deg = std::max(d->max_row_deg, D.row_ptr[c + 1] - D.row_ptr[c]);
+  }
+  std::vector<uint32_t> sg32((size_t)d->E4 / 4);
+  if (!sg32.empty()) std::memcpy(sg32.data(), sg.data(), sg.size());
+  if ((st = upload(&d->init, init)) != TMCS_OK || (st = upload(&d->sign0, sg32)) != TMCS_OK) {
+    free_device(d);
+    delete d;
+    return st;
+  }
   if (hipMalloc((void**)&d->counters, 8 * sizeof(int32_t)) != hipSuccess) {
     free_device(d);
     delete d;
     return fail(TMCS_ENOMEM, "hipMalloc failed (counters)");
   }
   *out = d;
+  return TMCS_OK;
+}
+
+// Longest-processing-time assignment of items (checks or columns) of given
+// sizes to P lanes; returns per-lane item lists (ascending) and the max load.
+int lpt_assign(const std::vector<int>& size, int P, std::vector<std::vector<int>>* lanes) {
+  std::vector<int> order(size.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return size[a] > size[b]; });
+  lanes->assign(P, {});
+  std::vector<std::pair<long, int>> heap;   // (load, lane), min-heap
+  for (int l = 0; l < P; ++l) heap.push_back({0, l});
+  auto cmp = [](const std::pair<long, int>& a, const std::pair<long, int>& b) { return a > b; };
+  std::make_heap(heap.begin(), heap.end(), cmp);
+  for (int it : order) {
+    if (size[it] == 0) continue;
+    std::pop_heap(heap.begin(), heap.end(), cmp);
+    auto& top = heap.back();
+    (*lanes)[top.second].push_back(it);
+    top.first += size[it];
+    std::push_heap(heap.begin(), heap.end(), cmp);
+  }
+  long kmax = 0;
+  for (auto& h : heap) kmax = std::max(kmax, h.first);
+  for (auto& l : *lanes) std::sort(l.begin(), l.end());
+  return (int)kmax;
+}
+
+// Schedules of the check and variable passes for team size P (cached per P).
+tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, DecodeDevice::Sched* out) {
+  for (const auto& q : d->scheds)
+    if (q.P == P) { *out = q; return TMCS_OK; }
+  DecodeDevice::Sched q;
+  q.P = P;
+  std::vector<std::vector<int>> lanes;
+  std::vector<int> rdeg(std::max(D.rows, 0)), cdeg(std::max(D.cols, 0));
+  for (int c = 0; c < D.rows; ++c) rdeg[c] = D.row_ptr[c + 1] - D.row_ptr[c];
+  for (int v = 0; v < D.cols; ++v) cdeg[v] = D.col_ptr[v + 1] - D.col_ptr[v];
+  // padding steps touch only spare LDS slots (edge E4, check m) and never
+  // carry FIRST/LAST, so their results are never stored
+  const int4 pad = make_int4(0, d->E4, D.rows, 0);
+  // K is rounded up to even, plus two rows of padding read by the prefetch
+  q.Kc = lpt_assign(rdeg, P, &lanes);
+  q.Kc += q.Kc & 1;
+  std::vector<int4> cs((size_t)(q.Kc + 2) * P, pad);
+  for (int l = 0; l < P; ++l) {
+    int k = 0;
+    for (int c : lanes[l])
+      for (int32_t e = D.row_ptr[c]; e < D.row_ptr[c + 1]; ++e, ++k) {
+        int32_t x = D.col_idx[e];
+        if (e == D.row_ptr[c]) x |= R_FIRST;
+        if (e == D.row_ptr[c + 1] - 1) x |= R_LAST;
+        cs[(size_t)k * P + l] = make_int4(x, e, c, 0);
+      }
+  }
+  q.Kv = lpt_assign(cdeg, P, &lanes);
+  q.Kv += q.Kv & 1;
+  std::vector<int4> vs((size_t)(q.Kv + 2) * P, pad);
+  for (int l = 0; l < P; ++l) {
+    int k = 0;
+    for (int v : lanes[l])
+      for (int32_t j = D.col_ptr[v]; j < D.col_ptr[v + 1]; ++j, ++k) {
+        int32_t x = v;
+        if (j == D.col_ptr[v]) x |= R_FIRST;
+        if (j == D.col_ptr[v + 1] - 1) x |= R_LAST;
+        float lv = (float)std::log((1.0 - D.priors[v]) / D.priors[v]);
+        int32_t lbits;
+        std::memcpy(&lbits, &lv, 4);
+        vs[(size_t)k * P + l] = make_int4(x, D.csc_edge[j], D.row_idx[j], lbits);
+      }
+  }
+  tmcs_status st;
+  if ((st = upload(&q.c, cs)) != TMCS_OK) return st;
+  if ((st = upload(&q.v, vs)) != TMCS_OK) { hipFree(q.c); return st; }
+  d->scheds.push_back(q);
+  *out = q;
   return TMCS_OK;
 }
 
@@ -845,24 +908,29 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   if (cfg.use_osd && (npad > OSD_MAX_KEYS || mw > 32))
     return fail(TMCS_EUNSUPPORTED, "OSD-0 supports up to 16384 columns and 2048 detectors in this build");
   const int cus = device_cus();
-  // BP launch shape: explicit messages when they fit, S shots per workgroup
-  int bp_threads = cfg.bp_threads > 0 ? cfg.bp_threads : (D.cols > 4096 ? 512 : 256);
-  bp_threads = std::min(1024, std::max(64, (bp_threads + 63) / 64 * 64));
-  const size_t per_shot_msg = (size_t)D.cols * 4 + (size_t)D.edges * 4 + (size_t)D.rows;
-  const size_t per_shot_cmp = (size_t)D.cols * 4 + (size_t)D.rows * 13 + (size_t)((D.edges + 31) / 32) * 4;
-  const bool use_msg = per_shot_msg + 16 <= 64 * 1024;
-  const size_t per_shot = use_msg ? per_shot_msg : per_shot_cmp;
-  if (per_shot + 16 > 160 * 1024) return fail(TMCS_EUNSUPPORTED, "BP state exceeds the 160 KB LDS of one workgroup");
-  int slots = cfg.bp_slots > 0 ? cfg.bp_slots : 1;
-  slots = std::max(1, std::min(16, slots));
-  while (slots > 1 && per_shot * slots + 16 > 160 * 1024) --slots;
-  const size_t bp_lds = per_shot * slots + 16;
-  const void* bp_fn = use_msg ? (const void*)k_bp<true> : (const void*)k_bp<false>;
+  // BP launch shape: one team (workgroup) per shot in flight, state in LDS
+  const size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (size_t)d->E4 + 4;
+  if (bp_lds > 160 * 1024)
+    return fail(TMCS_EUNSUPPORTED, "BP state of one shot exceeds the 160 KB LDS of a compute unit");
+  const int team_fit = std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));   // teams per CU by LDS
+  int P;
+  if (cfg.bp_threads > 0) {
+    P = cfg.bp_threads;
+  } else {
+    // about 8 waves per CU, but no lane should carry much more than its share of edges
+    int G = std::max(1, std::min(16, (8 + team_fit - 1) / team_fit));
+    P = 64 * G;
+    const int64_t cap = std::max<int64_t>(64, (3 * D.edges / std::max(2 * d->max_row_deg, 1)) / 64 * 64);
+    while (P > 64 && P > cap) P -= 64;
+  }
+  P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
+  DecodeDevice::Sched sch;
+  if ((st = get_sched(D, d, P, &sch)) != TMCS_OK) return st;
   if (bp_lds > 64 * 1024 &&
-      hipFuncSetAttribute(bp_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess)
+      (hipFuncSetAttribute((const void*)k_bp<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
+       hipFuncSetAttribute((const void*)k_bp<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess))
     return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
-  const int per_cu_fit = std::max<int>(1, (int)((160 * 1024) / (bp_lds + 512)));
-  const int per_cu = std::min(per_cu_fit, cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 16);
+  const int per_cu = std::max(1, std::min({team_fit, 32 / (P / 64), cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 32}));
   // shots per internal pass: bounded so the OSD LLR staging stays <= 1 GiB
   const int64_t chunk = std::min<int64_t>((int64_t)n_shots,
                                           std::max<int64_t>(DECODE_CHUNK_MIN, ((1ll << 28) / std::max(D.cols, 1)) & ~63ll));
@@ -902,18 +970,17 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
                   d->queue, d->counters);
     }
     BPArgs a;
-    a.row_ptr = d->row_ptr; a.col_idx = d->col_idx; a.col_ptr = d->col_ptr; a.csc_row = d->csc_row;
-    a.csc_edge = d->csc_edge; a.lam = d->lam; a.obs_mask = d->obs_mask;
-    a.m = D.rows; a.n = D.cols; a.E = D.edges; a.T = cfg.max_iter; a.alpha = cfg.alpha; a.w = cfg.weights_dev;
+    a.csched = sch.c; a.vsched = sch.v; a.Kc = sch.Kc; a.Kv = sch.Kv; a.init = d->init; a.sign0 = d->sign0;
+    a.lam = d->lam; a.obs_mask = d->obs_mask;
+    a.m = D.rows; a.n = D.cols; a.E = D.edges; a.E32 = (int32_t)D.edges; a.E4 = d->E4; a.T = cfg.max_iter; a.alpha = cfg.alpha;
+    a.w = cfg.weights_dev;
     a.synd = d->synd; a.mw = std::max(mw, 1); a.stride = stride; a.shot0 = s0; a.nshots = ns; a.queue = full ? nullptr : d->queue;
     a.counters = d->counters; a.use_osd = cfg.use_osd; a.osd_queue = d->osd_queue; a.osd_llr = d->osd_llr;
     a.pred = pred; a.nobs = D.nobs; a.stats = stats; a.ehat = cfg.ehat_dev; a.llr = cfg.llr_dev;
     a.iters = cfg.iters_dev; a.flags = cfg.flags_dev;
-    const int bp_grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>((ns + slots - 1) / slots, 1));
-    if (use_msg)
-      TMCS_LAUNCH("k_bp", k_bp<true>, dim3(bp_grid), dim3(bp_threads), bp_lds, stream, a, (int32_t)slots);
-    else
-      TMCS_LAUNCH("k_bp", k_bp<false>, dim3(bp_grid), dim3(bp_threads), bp_lds, stream, a, (int32_t)slots);
+    const int bp_grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(ns, 1));
+    if (cfg.weights_dev) TMCS_LAUNCH("k_bp", k_bp<true>, dim3(bp_grid), dim3(P), bp_lds, stream, a);
+    else TMCS_LAUNCH("k_bp", k_bp<false>, dim3(bp_grid), dim3(P), bp_lds, stream, a);
     if ((st = hip_check(hipGetLastError(), "k_bp launch")) != TMCS_OK) return st;
     if (cfg.use_osd) {
       OSDArgs o;
@@ -988,8 +1055,8 @@ tmcs_status autotune_run(const Dem& D, const uint64_t* det, uint64_t n_shots, tm
   base.ehat_dev = nullptr; base.llr_dev = nullptr; base.iters_dev = nullptr; base.flags_dev = nullptr;
   tmcs_decoder_cfg best = base;
   float best_ms = 1e30f;
-  const int threads[] = {128, 256, 512};
-  const int bp_cu[] = {4, 16};
+  const int threads[] = {64, 128, 256, 512};
+  const int bp_cu[] = {0, 4};
   const int osd_cu[] = {2, 4, 8};
   tmcs_status st = TMCS_OK;
   for (int th : threads)
