@@ -463,20 +463,48 @@ __device__ __forceinline__ uint64_t bit_of(const uint64_t (&v)[W], int p) {
 // column degree), and a syndrome s by those whose pivot rows lie in supp(s).
 // New basis vectors are created 64 at a time by one wave, made fully reduced
 // among themselves, and the older vectors are then reduced against them.
-template <int MW, int RW, int KPT>
-__global__ void __launch_bounds__(OSD_THREADS) k_osd(OSDArgs a) {
+// BL: the basis lives in LDS (after the sort keys) instead of HBM.
+// NT: threads per workgroup (64: one wave decodes a shot on its own).
+template <int MW, int RW, int KPT, bool BL, int NT>
+__global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
   constexpr int W = MW + RW;
   extern __shared__ __align__(8) unsigned char sm[];
   uint64_t* keys = (uint64_t*)sm;                                  // [npad]
-  int32_t* pivot = (int32_t*)(keys + a.npad);                      // [rank] pivot row of basis i
+  uint64_t* lbasis = keys + a.npad;                                // BL: [rank][W]
+  int32_t* pivot = (int32_t*)(BL ? lbasis + (size_t)a.rank * W : keys + a.npad);   // [rank] pivot row of basis i
   int32_t* kept = pivot + a.rank;                                  // [rank] column of basis i
   int32_t* prow = kept + a.rank;                                   // [m] basis index of a pivot row, or -1
-  uint64_t* acc = (uint64_t*)(((uintptr_t)(prow + a.m) + 7) & ~(uintptr_t)7);  // [W] solve accumulator
-  __shared__ int s_job, s_r;
+  int32_t* srow = prow + a.m;                                      // [m] rows with a syndrome bit
+  uint64_t* acc = (uint64_t*)(((uintptr_t)(srow + a.m) + 7) & ~(uintptr_t)7);  // [W] solve accumulator
+  __shared__ int s_job, s_r, s_ns;
   __shared__ uint64_t s_red;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  uint64_t* B = a.basis + (int64_t)blockIdx.x * a.rank * W;
+  uint64_t* B = BL ? lbasis : a.basis + (int64_t)blockIdx.x * a.rank * W;
+  // acc = s + sum of the basis vectors pivoted on rows of s.  With a fully
+  // reduced basis this is zero on every pivot row; its syndrome part is zero iff
+  // s lies in the span of the kept columns, and its combination part then names
+  // the kept columns whose sum is s.  Returns nonzero iff the syndrome part is.
+  auto reduce_syndrome = [&]() {
+    __syncthreads();
+    if (tid < W) acc[tid] = 0ull;
+    __syncthreads();
+    for (int i = tid; i < s_ns; i += NT) {
+      const int row = srow[i];
+      atomicXor((unsigned long long*)&acc[row >> 6], (unsigned long long)(1ull << (row & 63)));
+      const int pi = prow[row];
+      if (pi >= 0) {
+        const uint64_t* b = B + (int64_t)pi * W;
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+          if (b[w]) atomicXor((unsigned long long*)&acc[w], (unsigned long long)b[w]);
+      }
+    }
+    __syncthreads();
+    int nz = 0;
+    for (int w = tid; w < MW; w += NT) nz |= acc[w] != 0ull;
+    return __syncthreads_or(nz);
+  };
   while (true) {
     if (tid == 0) s_job = atomicAdd(&a.counters[3], 1);
     __syncthreads();
@@ -486,10 +514,13 @@ __global__ void __launch_bounds__(OSD_THREADS) k_osd(OSDArgs a) {
     const int64_t ls = a.osd_queue[job];
     const int64_t shot = a.shot0 + ls;
     const float* L = a.osd_llr + (int64_t)job * a.n;
-    // 1. sort columns by (L_v, v)
-    for (int r = tid; r < a.m; r += OSD_THREADS) prow[r] = -1;
-    if (tid < W) acc[tid] = 0ull;
-    if (tid == 0) s_r = 0;
+    // 1. sort columns by (L_v, v); list the syndrome's rows
+    if (tid == 0) { s_r = 0; s_ns = 0; }
+    __syncthreads();
+    for (int r = tid; r < a.m; r += NT) {
+      prow[r] = -1;
+      if ((a.det[(int64_t)r * a.stride + (shot >> 6)] >> (shot & 63)) & 1ull) srow[atomicAdd(&s_ns, 1)] = r;
+    }
     {
       uint64_t x[KPT];
 #pragma unroll
@@ -500,7 +531,7 @@ __global__ void __launch_bounds__(OSD_THREADS) k_osd(OSDArgs a) {
       bitonic_sort_regs<KPT>(x, keys, a.npad);
     }
     // 2. information set, 256 sorted candidates per pass (one per thread)
-    for (int base = 0; base < a.n; base += OSD_THREADS) {
+    for (int base = 0; base < a.n; base += NT) {
       const int r_start = s_r;
       __syncthreads();           // every wave has read s_r before wave 0 advances it
       if (r_start >= a.rank) break;
@@ -529,7 +560,7 @@ __global__ void __launch_bounds__(OSD_THREADS) k_osd(OSDArgs a) {
       }
       __syncthreads();           // phase 1 everywhere before any wave publishes new pivots
       int r_done = r_start;
-      for (int q = 0; q < OSD_THREADS / 64; ++q) {
+      for (int q = 0; q < NT / 64; ++q) {
         if (wave == q) {
           // phase 2: in-order pass over this wave's candidates whose syndrome
           // part is still nonzero (zero ones depend on earlier columns)
@@ -592,7 +623,7 @@ __global__ void __launch_bounds__(OSD_THREADS) k_osd(OSDArgs a) {
         const int r_new = s_r;
         if (r_new > r_done) {
           // older basis vectors: clear their bits at the new pivots
-          for (int i = tid; i < r_done; i += OSD_THREADS) {
+          for (int i = tid; i < r_done; i += NT) {
             uint64_t bi[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) bi[w] = B[(int64_t)i * W + w];
@@ -628,30 +659,20 @@ __global__ void __launch_bounds__(OSD_THREADS) k_osd(OSDArgs a) {
         r_done = r_new;
         __syncthreads();
       }
+      // Stop as soon as s lies in the span of the kept columns.  Columns of the
+      // full information set are independent, so s has exactly one
+      // representation over them; the one found here (zero on the columns not
+      // yet kept) is it, and the rest of the scan could only add zeros.
+      if (!reduce_syndrome()) break;
     }
     // 3. solve: s reduced by the basis vectors pivoted on rows of s
     const int r = s_r;
-    int bad = 0;
-    for (int row = tid; row < a.m; row += OSD_THREADS) {
-      if ((a.det[(int64_t)row * a.stride + (shot >> 6)] >> (shot & 63)) & 1ull) {
-        atomicXor((unsigned long long*)&acc[row >> 6], (unsigned long long)(1ull << (row & 63)));
-        const int i = prow[row];
-        if (i >= 0) {
-          const uint64_t* b = B + (int64_t)i * W;
-#pragma unroll
-          for (int w = 0; w < W; ++w)
-            if (b[w]) atomicXor((unsigned long long*)&acc[w], (unsigned long long)b[w]);
-        }
-      }
-    }
-    __syncthreads();
-    for (int w = tid; w < MW; w += OSD_THREADS) bad |= acc[w] != 0ull;
-    const int not_in_span = __syncthreads_or(bad);
+    const int not_in_span = reduce_syndrome();
     uint64_t pm = 0;
     if (a.ehat)
-      for (int v = tid; v < a.n; v += OSD_THREADS) a.ehat[shot * a.n + v] = 0;
+      for (int v = tid; v < a.n; v += NT) a.ehat[shot * a.n + v] = 0;
     __syncthreads();
-    for (int i = tid; i < r; i += OSD_THREADS) {
+    for (int i = tid; i < r; i += NT) {
       if ((acc[MW + (i >> 6)] >> (i & 63)) & 1ull) {
         const int col = kept[i];
         pm ^= a.obs_mask[col];
@@ -850,30 +871,54 @@ int device_cus() {
   return cus > 0 ? cus : 256;
 }
 
-template <int MW, int RW, int KPT>
+template <int MW, int RW, int KPT, bool BL>
 tmcs_status launch_osd(const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
+  constexpr int NT = BL ? 64 : OSD_THREADS;
   if (lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_osd<MW, RW, KPT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      hipFuncSetAttribute((const void*)k_osd<MW, RW, KPT, BL, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "OSD workspace does not fit in LDS");
-  TMCS_LAUNCH("k_osd", (k_osd<MW, RW, KPT>), dim3(grid), dim3(OSD_THREADS), lds, s, a);
+  TMCS_LAUNCH("k_osd", (k_osd<MW, RW, KPT, BL, NT>), dim3(grid), dim3(NT), lds, s, a);
   return hip_check(hipGetLastError(), "k_osd launch");
 }
 
 template <int MW>
 tmcs_status dispatch_kpt(int kpt, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
   switch (kpt) {
-    case 1: return launch_osd<MW, MW, 1>(a, grid, lds, s);
-    case 2: return launch_osd<MW, MW, 2>(a, grid, lds, s);
-    case 4: return launch_osd<MW, MW, 4>(a, grid, lds, s);
-    case 8: return launch_osd<MW, MW, 8>(a, grid, lds, s);
-    case 16: return launch_osd<MW, MW, 16>(a, grid, lds, s);
-    case 32: return launch_osd<MW, MW, 32>(a, grid, lds, s);
-    case 64: return launch_osd<MW, MW, 64>(a, grid, lds, s);
+    case 1: return launch_osd<MW, MW, 1, false>(a, grid, lds, s);
+    case 2: return launch_osd<MW, MW, 2, false>(a, grid, lds, s);
+    case 4: return launch_osd<MW, MW, 4, false>(a, grid, lds, s);
+    case 8: return launch_osd<MW, MW, 8, false>(a, grid, lds, s);
+    case 16: return launch_osd<MW, MW, 16, false>(a, grid, lds, s);
+    case 32: return launch_osd<MW, MW, 32, false>(a, grid, lds, s);
+    case 64: return launch_osd<MW, MW, 64, false>(a, grid, lds, s);
     default: return fail(TMCS_EUNSUPPORTED, "OSD sort size");
   }
 }
 
-tmcs_status dispatch_osd(int mw, int kpt, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
+// basis in LDS, one wave per shot: small DEMs only (m <= 512, sort length <= 4096)
+template <int MW>
+tmcs_status dispatch_kpt_lds(int kpt, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
+  switch (kpt) {
+    case 4: return launch_osd<MW, MW, 4, true>(a, grid, lds, s);
+    case 8: return launch_osd<MW, MW, 8, true>(a, grid, lds, s);
+    case 16: return launch_osd<MW, MW, 16, true>(a, grid, lds, s);
+    case 32: return launch_osd<MW, MW, 32, true>(a, grid, lds, s);
+    case 64: return launch_osd<MW, MW, 64, true>(a, grid, lds, s);
+    default: return fail(TMCS_EUNSUPPORTED, "OSD sort size");
+  }
+}
+
+bool osd_lds_basis_ok(int mw, int npad) { return mw <= 8 && npad <= 4096; }
+
+tmcs_status dispatch_osd(int mw, int kpt, bool bl, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (bl) {
+    if (mw <= 1) return dispatch_kpt_lds<1>(kpt, a, grid, lds, s);
+    if (mw <= 2) return dispatch_kpt_lds<2>(kpt, a, grid, lds, s);
+    if (mw <= 4) return dispatch_kpt_lds<4>(kpt, a, grid, lds, s);
+    if (mw <= 5) return dispatch_kpt_lds<5>(kpt, a, grid, lds, s);
+    if (mw <= 8) return dispatch_kpt_lds<8>(kpt, a, grid, lds, s);
+    return fail(TMCS_EUNSUPPORTED, "OSD basis in LDS: too many detectors");
+  }
   if (mw <= 1) return dispatch_kpt<1>(kpt, a, grid, lds, s);
   if (mw <= 2) return dispatch_kpt<2>(kpt, a, grid, lds, s);
   if (mw <= 4) return dispatch_kpt<4>(kpt, a, grid, lds, s);
@@ -937,16 +982,20 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   // OSD launch shape
   const int W = 2 * (mw <= 1 ? 1 : mw <= 2 ? 2 : mw <= 4 ? 4 : mw <= 5 ? 5 : mw <= 8 ? 8 : mw <= 12 ? 12
                    : mw <= 15 ? 15 : mw <= 18 ? 18 : mw <= 24 ? 24 : 32);
-  const size_t osd_lds = (size_t)npad * 8 + (size_t)D.rank * 8 + (size_t)D.rows * 4 + (size_t)W * 8 + 64;
+  size_t osd_lds = (size_t)npad * 8 + (size_t)D.rank * 8 + (size_t)D.rows * 8 + (size_t)W * 8 + 64;
+  // small DEMs keep the elimination basis in LDS as well (at least two workgroups per CU)
+  const size_t basis_bytes = (size_t)std::max(D.rank, 1) * W * 8;
+  const bool osd_bl = osd_lds_basis_ok(mw, npad) && osd_lds + basis_bytes <= 80 * 1024;
+  if (osd_bl) osd_lds += basis_bytes;
   const int osd_fit = std::max<int>(1, (int)((160 * 1024) / (osd_lds + 512)));
-  const int osd_per_cu = std::min(osd_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 4);
+  const int osd_per_cu = std::min(osd_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : (osd_bl ? 16 : 4));
   const int osd_grid = std::max(1, cus * osd_per_cu);
   if ((st = grow(&d->queue, &d->cap_queue, (size_t)chunk)) != TMCS_OK) return st;
   if ((st = grow(&d->synd, &d->cap_synd, (size_t)chunk * (size_t)std::max(mw, 1))) != TMCS_OK) return st;
   if (cfg.use_osd) {
     if ((st = grow(&d->osd_queue, &d->cap_osd, (size_t)chunk)) != TMCS_OK ||
         (st = grow(&d->osd_llr, &d->cap_llr, (size_t)chunk * (size_t)D.cols)) != TMCS_OK ||
-        (st = grow(&d->basis, &d->cap_basis, (size_t)osd_grid * (size_t)std::max(D.rank, 1) * W)) != TMCS_OK)
+        (!osd_bl && (st = grow(&d->basis, &d->cap_basis, (size_t)osd_grid * (size_t)std::max(D.rank, 1) * W)) != TMCS_OK))
       return st;
   }
   const int64_t total_words = (int64_t)D.nobs * stride;
@@ -989,7 +1038,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
       o.counters = d->counters; o.osd_queue = d->osd_queue; o.osd_llr = d->osd_llr; o.basis = d->basis;
       o.pred = pred; o.nobs = D.nobs; o.stats = stats; o.ehat = cfg.ehat_dev; o.flags = cfg.flags_dev;
       o.npad = npad;
-      if ((st = dispatch_osd(mw, npad / OSD_THREADS, o, osd_grid, osd_lds, stream)) != TMCS_OK) return st;
+      if ((st = dispatch_osd(mw, npad / (osd_bl ? 64 : OSD_THREADS), osd_bl, o, osd_grid, osd_lds, stream)) != TMCS_OK) return st;
     }
   }
   return TMCS_OK;
