@@ -28,6 +28,36 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 BP_OPS_PER_EDGE_ITER = 10      # |q|, two min compares, sign XORs, message rebuild, add
 FRAME_OPS_PER_CX_WORD = 4      # two 64-bit XORs per CX per 64-shot word
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch,
+# averaged over the dispatches of a --steps 1 --warmup 1 run of this workload),
+# scaled by what the counters read for a plain 1 GiB device copy.  Valid only for
+# the kernel source they were taken on: the SHA-256 of that source file must match.
+# Commands and raw figures: profiles/hbm_traffic_sc5_nlcnot.md
+TRAFFIC = {
+    "sc5_nlcnot": {
+        "k_bp": {"src": "paper_2504_05611_amd/csrc/kernels/decode.hip",
+                 "sha256": "2c12f2c22a378aba40978f4cf50a3e9a15b894315df168e2b12f8bd125e1b3de",
+                 "fetch_kib": 14850.6, "write_kib": 27062.5},
+        "k_frame": {"src": "paper_2504_05611_amd/csrc/kernels/sample.hip",
+                    "sha256": "06e7ff6878bc7c6c7893c53fbdb252ee01427c5b9956d8d578b7295f5e34c8d0",
+                    "fetch_kib": 20892.5, "write_kib": 38552.6},
+    },
+}
+FETCH_SCALE = 1048576.0 / 524302.5   # copy-kernel calibration (1 GiB read per launch)
+WRITE_SCALE = 1048576.0 / 1048576.0
+
+
+def traffic_bytes(workload, kernel):
+    """Scaled HBM bytes per launch, or None when no counters match the current source."""
+    import hashlib
+    t = TRAFFIC.get(workload, {}).get(kernel)
+    if t is None:
+        return None
+    with open(os.path.join(ROOT, t["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
+            return None
+    return (t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -146,8 +176,20 @@ def main():
         model = "no model"
     achieved = ops / avg_s / 1e12
     roofline = dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS, unit="TOP/s",
-                    frac=achieved / VALU_PEAK_TOPS, traffic=None, kernel=dominant,
+                    frac=achieved / VALU_PEAK_TOPS, traffic=traffic_bytes(w.name, dominant), kernel=dominant,
                     avg_launch_ms=avg_s * 1e3, model=model)
+    # the sampler's frame kernel against the same VALU peak (frame bit-operations only)
+    sample_roofline = None
+    if "k_frame" in kern:
+        fl, fms = kern["k_frame"]
+        words = math.ceil(shots / 64)
+        f_ops = FRAME_OPS_PER_CX_WORD * info["gates_2q"] * words * args.steps / fl
+        f_ach = f_ops / (fms / fl / 1e3) / 1e12
+        sample_roofline = dict(bound="alu", kernel="k_frame", achieved=f_ach, peak=VALU_PEAK_TOPS, unit="TOP/s",
+                               frac=f_ach / VALU_PEAK_TOPS, traffic=traffic_bytes(w.name, "k_frame"),
+                               avg_launch_ms=fms / fl,
+                               model=f"{FRAME_OPS_PER_CX_WORD} lane-ops per CX per 64-shot word x "
+                                     f"{info['gates_2q']} CX x {words} words")
     ler = errors / total
     out = {
         "metric": "shots/sec (sample+BP-OSD decode) on 1 MI355X at matched logical error rate",
@@ -163,6 +205,7 @@ def main():
         "osd_rate": st["osd"] / max(st["shots"], 1), "bp_iters_mean": st["bp_iters"] / max(st["shots"], 1),
         "kernels_ms": {n: round(v[1] / v[0], 4) for n, v in sorted(kern.items())},
         "roofline": roofline,
+        "sample_roofline": sample_roofline,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, spec, 8192)
