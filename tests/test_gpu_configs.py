@@ -1,0 +1,145 @@
+"""Parity at the shapes of the other benchmark workloads.
+
+* BB [[144,12,12]] memory, 12 rounds, three noise strengths decoded as three
+  instances of one graph-captured plan (the batched launch);
+* BB [[144,12,12]] teleportation through 144 ebits (plain BP-OSD and the
+  weighted-BP kernels, T = 20);
+* the surface-code non-local CNOT of the mixed batch at d = 11 (BP, whose
+  detector count is beyond this build's OSD-0), and the sizes this build
+  refuses.
+
+The oracle checks sampled bits bit for bit and decodes sampled 64-shot words
+in FP32 (the decoder's precision) in the same operation order.
+"""
+import numpy as np
+import pytest
+
+from oracle.circuits import build_circuit
+from oracle.dem import build_dem
+from oracle.frame import pack_bits, sample as oracle_sample, unpack_bits
+from oracle.bp import decode_bp
+from oracle.osd import Decoder
+from oracle.wbp import backward as oracle_backward
+from oracle.wbp import forward as oracle_forward
+from workloads import WORKLOADS
+
+pytestmark = pytest.mark.gpu
+
+
+def _check_sampler(tmcs, c, spec, seed, inst, begin, n):
+    import torch
+    det, obs = c.alloc_outputs(n)
+    c.sample(seed, inst, begin, n, det, obs)
+    torch.cuda.synchronize()
+    d_or, o_or = oracle_sample(build_circuit(spec), seed, inst, begin, n)
+    assert (det.cpu().numpy().view(np.uint64) == pack_bits(d_or)).all()
+    assert (obs.cpu().numpy().view(np.uint64)[: c.num_observables] == pack_bits(o_or)).all()
+
+
+def test_bb144_memory_three_instances_in_one_plan(gpu_lib):
+    import torch
+    w = WORKLOADS["bb144_memory"]
+    circuits = [gpu_lib.Circuit(s) for s in w.specs]
+    dems = [gpu_lib.DEM(c) for c in circuits]
+    B, nb = 8192, 2
+    plan = gpu_lib.Plan([(c, d, gpu_lib.make_cfg(max_iter=w.bp_iters), w.seed, i)
+                         for i, (c, d) in enumerate(zip(circuits, dems))], B, use_graph=True)
+    plan.run(nb)
+    torch.cuda.synchronize()
+    preds = []
+    for i, (c, d) in enumerate(zip(circuits, dems)):
+        n = nb * B
+        det, obs = c.alloc_outputs(n)
+        c.sample(w.seed, i, 0, n, det, obs)
+        pred = torch.zeros_like(obs)
+        st = gpu_lib.new_stats()
+        d.decode(det, n, pred, max_iter=w.bp_iters, stats=st)
+        ne, _, _ = gpu_lib.logical_error_rate(pred, obs, c.num_observables, n)
+        s = gpu_lib.read_stats(st)
+        r = plan.result(i)
+        print(f"[bb144-memory] p={w.specs[i].p} plan {r} eager errors {ne} {s}", flush=True)
+        assert r["shots"] == n and r["errors"] == ne
+        assert r["osd"] == s["osd"] and r["converged"] == s["converged"] and r["bp_iters"] == s["bp_iters"]
+        preds.append((det.cpu().numpy().view(np.uint64), pred.cpu().numpy().view(np.uint64)))
+    # bits of instance 2 on a stretch that crosses a noise block, and one decoded word of instance 1
+    _check_sampler(gpu_lib, circuits[2], w.specs[2], w.seed, 2, 4096 - 64, 128)
+    od = build_dem(build_circuit(w.specs[1]))
+    dec = Decoder(od.H(), od.priors(), od.L(), max_iter=w.bp_iters, dtype=np.float32)
+    d1, p1 = preds[1]
+    wd = 37
+    o = dec.decode(unpack_bits(d1[:, wd:wd + 1], 64).T)
+    assert (unpack_bits(p1[:, wd:wd + 1], 64).T[:, : od.num_obs] == o["pred_obs"]).all()
+
+
+def test_bb144_teleport_decoder_and_weighted_bp(gpu_lib):
+    import torch
+    w = WORKLOADS["bb144_teleport"]
+    spec = w.specs[0]
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    _check_sampler(gpu_lib, c, spec, w.seed, 0, 2 * 4096 - 64, 128)
+    n = 4096
+    det, obs = c.alloc_outputs(n)
+    c.sample(w.seed, 0, 0, n, det, obs)
+    pred = torch.zeros_like(obs)
+    dem.decode(det, n, pred, max_iter=w.bp_iters)
+    torch.cuda.synchronize()
+    d = det.cpu().numpy().view(np.uint64)
+    p = pred.cpu().numpy().view(np.uint64)
+    od = build_dem(build_circuit(spec))
+    dec = Decoder(od.H(), od.priors(), od.L(), max_iter=w.bp_iters, dtype=np.float32)
+    wd = 5
+    o = dec.decode(unpack_bits(d[:, wd:wd + 1], 64).T)
+    assert (unpack_bits(p[:, wd:wd + 1], 64).T[:, : od.num_obs] == o["pred_obs"]).all()
+    # weighted BP at this shape: FP32 forward bit for bit, gradient against the FP64-arithmetic reference
+    T, shots = 4, 2
+    rng = np.random.default_rng(3)
+    wts = rng.uniform(0.6, 1.4, size=(T, dem.edges)).astype(np.float32)
+    wt = torch.from_numpy(wts).cuda()
+    ws = torch.empty(dem.wbp_workspace_size(T, shots), dtype=torch.uint8, device="cuda")
+    llr = torch.empty((T, shots, dem.cols), dtype=torch.float32, device="cuda")
+    det2, _ = c.alloc_outputs(shots)
+    c.sample(w.seed, 0, 0, shots, det2, _)
+    dem.wbp_forward(wt, T, det2, shots, llr, ws)
+    G = rng.normal(size=(T, shots, dem.cols)).astype(np.float32)
+    gw = torch.zeros_like(wt)
+    dem.wbp_backward(wt, T, det2, shots, torch.from_numpy(G).cuda(), gw, ws)
+    torch.cuda.synchronize()
+    synd = unpack_bits(det2.cpu().numpy().view(np.uint64), shots).T
+    f32 = oracle_forward(od.H(), od.priors(), synd, wts, dtype=np.float32)
+    assert (llr.cpu().numpy() == f32["L"]).all()
+    ref = oracle_backward(f32, G.astype(np.float64))
+    got = gw.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-4 * max(np.linalg.norm(ref), 1e-30)
+
+
+def test_sc11_nlcnot_bp_and_size_limits(gpu_lib):
+    import torch
+    w = WORKLOADS["sc_nlcnot_mixed"]
+    spec = next(s for s in w.specs if s.d == 11 and s.p == 1e-3)
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    _check_sampler(gpu_lib, c, spec, w.seed, 1, 4096 - 64, 128)
+    n = 64
+    det, obs = c.alloc_outputs(n)
+    c.sample(w.seed, 1, 0, n, det, obs)
+    pred = torch.zeros_like(obs)
+    llr = torch.zeros((n, dem.cols), dtype=torch.float32, device="cuda")
+    iters = torch.zeros(n, dtype=torch.int32, device="cuda")
+    dem.decode(det, n, pred, max_iter=w.bp_iters, use_osd=False, llr=llr, iters=iters)
+    torch.cuda.synchronize()
+    od = build_dem(build_circuit(spec))
+    synd = unpack_bits(det.cpu().numpy().view(np.uint64), n).T[:16]
+    r = decode_bp(od.H(), od.priors(), synd, w.bp_iters, dtype=np.float32)
+    assert (iters.cpu().numpy()[:16] == r["iters"]).all()
+    assert (llr.cpu().numpy()[:16] == r["llr"].astype(np.float32)).all()
+    # OSD-0 beyond 2048 detectors and BP state beyond one CU's LDS are refused, not approximated
+    with pytest.raises(gpu_lib.TmcsError):
+        dem.decode(det, n, pred, max_iter=w.bp_iters, use_osd=True)
+    c15 = gpu_lib.Circuit(next(s for s in w.specs if s.d == 15))
+    big = gpu_lib.DEM(c15)
+    det15, obs15 = c15.alloc_outputs(n)
+    pred15 = torch.zeros_like(obs15)
+    with pytest.raises(gpu_lib.TmcsError):
+        big.decode(det15, n, pred15, max_iter=w.bp_iters, use_osd=False)
+    torch.cuda.synchronize()
