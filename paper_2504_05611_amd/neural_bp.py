@@ -87,8 +87,11 @@ def unpack_obs(obs_words, n_shots, k):
     return bits.reshape(k, -1)[:, :n_shots].T.to(torch.float32)
 
 
-def train(circuit, dem, T, *, steps=200, batch=256, lr=0.01, seed=2, init=1.0, log_every=0):
-    """Train weights [T, E] on fresh syndromes sampled by the library each step."""
+def train(circuit, dem, T, *, steps=200, batch=256, lr=0.01, seed=2, init=1.0, log_every=0, last=0):
+    """Train weights [T, E] on fresh syndromes sampled by the library each step.
+
+    last > 0 restricts the loss to the last `last` iterations (all T otherwise).
+    """
     dev = torch.device("cuda")
     w = torch.full((T, dem.edges), float(init), dtype=torch.float32, device=dev, requires_grad=True)
     opt = torch.optim.Adam([w], lr=lr)
@@ -100,7 +103,8 @@ def train(circuit, dem, T, *, steps=200, batch=256, lr=0.01, seed=2, init=1.0, l
         circuit.sample(seed, 0, step * ((batch + 4095) // 4096) * 4096, batch, det, obs)
         llr = WeightedBP.apply(w, det, dem, batch)
         y = unpack_obs(obs, batch, k)
-        loss = observable_loss(llr, y, supp) / (batch * T)
+        tl = llr[T - last:] if 0 < last < T else llr
+        loss = observable_loss(tl, y, supp) / (batch * tl.shape[0])
         opt.zero_grad()
         loss.backward()
         opt.step()
@@ -123,3 +127,59 @@ def evaluate(circuit, dem, *, n_shots, T, weights=None, alpha=1.0, use_osd=True,
     s = tmcs.read_stats(st)
     return dict(errors=ne, ler=ler, sigma=sig, osd_rate=s["osd"] / max(n_shots, 1),
                 converged=s["converged"] / max(n_shots, 1), bp_iters=s["bp_iters"] / max(n_shots, 1))
+
+
+def main(argv=None):
+    """Train weights on one workload's syndromes and compare learned with plain BP-OSD.
+
+    Prints one JSON line: training throughput, loss trace summary, and for plain
+    (alpha = 1) and learned weights the LER, OSD rate and BP convergence rate on
+    the same fresh shots.
+    """
+    import argparse
+    import json
+    import time
+
+    from workloads import WORKLOADS
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--workload", default="bb144_teleport")
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--lr", type=float, default=0.01)
+    ap.add_argument("--last", type=int, default=0, help="loss over the last N iterations only (0: all)")
+    ap.add_argument("--eval-shots", type=int, default=1 << 20)
+    ap.add_argument("--out", default="", help="save the trained weights (torch .pt)")
+    ap.add_argument("--log-every", type=int, default=20)
+    args = ap.parse_args(argv)
+    w = WORKLOADS[args.workload]
+    spec = w.specs[0]
+    T = w.bp_iters
+    circuit = tmcs.Circuit(spec)
+    dem = tmcs.DEM(circuit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = train(circuit, dem, T, steps=args.steps, batch=args.batch, lr=args.lr, seed=w.seed + 1,
+                log_every=args.log_every, last=args.last)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    if args.out:
+        torch.save(res.weights.cpu(), args.out)
+    out = dict(workload=w.name, T=T, edges=dem.edges, train_steps=args.steps, batch=args.batch, lr=args.lr,
+               loss_iterations=args.last or T,
+               train_syndromes=args.steps * args.batch, train_s=t_train,
+               train_syndromes_per_s=args.steps * args.batch / t_train,
+               loss_first=float(np.mean(res.losses[: max(1, len(res.losses) // 10)])),
+               loss_last=float(np.mean(res.losses[-max(1, len(res.losses) // 10):])))
+    for name, wts in (("plain", None), ("learned", res.weights)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = evaluate(circuit, dem, n_shots=args.eval_shots, T=T, weights=wts, seed=w.seed)
+        torch.cuda.synchronize()
+        r["decode_s"] = time.perf_counter() - t1
+        out[name] = r
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
