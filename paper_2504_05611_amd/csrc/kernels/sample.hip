@@ -15,7 +15,8 @@
 // Pipeline per chunk of blocks:
 //   k_event_count  one thread per (block, site): length of its event stream
 //   k_scan_*       exclusive prefix sum of the counts (block-major, site-minor)
-//   k_event_write  one thread per (block, site): events as u16 (pos | comp << 12)
+//   k_event_write  one thread per (block, site): 64-bit events (position,
+//                  component, channel kind, qubits)
 //   k_frame        one workgroup per F consecutive 64-shot words of one block:
 //                  X/Z frame words of every qubit live in LDS ([qubit][word],
 //                  bit = shot), the layered program is executed with a barrier
@@ -112,11 +113,13 @@ __global__ void k_event_count(int64_t nsites, int64_t nblk, int64_t blk0, uint32
   }
 }
 
+// Event word (64 bits): shot position in the block (12 bits), channel component
+// (4), channel kind (2), first qubit (23) and second qubit + 1 (23; 0 = none).
 __global__ void k_event_write(int64_t nsites, int64_t nblk, int64_t blk0, uint32_t k0, uint32_t k1,
                               uint32_t inst, const uint8_t* __restrict__ site_kind,
                               const uint16_t* __restrict__ site_tab, const uint64_t* __restrict__ tabs,
-                              const uint32_t* __restrict__ offsets, uint16_t* __restrict__ events,
-                              uint32_t capacity, uint32_t* __restrict__ overflow,
+                              const int2* __restrict__ site_q, const uint32_t* __restrict__ offsets,
+                              uint64_t* __restrict__ events, uint32_t capacity, uint32_t* __restrict__ overflow,
                               const uint64_t* __restrict__ blk_off) {
   const int64_t n = nsites * nblk;
   if (blk_off) blk0 += (int64_t)*blk_off;
@@ -124,10 +127,12 @@ __global__ void k_event_write(int64_t nsites, int64_t nblk, int64_t blk0, uint32
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = i / nsites, s = i - b * nsites;
     const uint8_t kind = site_kind[s];
+    const int2 q = site_q[s];
+    const uint64_t hi = ((uint64_t)kind << 16) | ((uint64_t)(uint32_t)q.x << 18) | ((uint64_t)(uint32_t)(q.y + 1) << 41);
     uint32_t o = offsets[i];
     event_stream(k0, k1, (uint32_t)(blk0 + b), (uint32_t)s, inst, tabs + (int64_t)site_tab[s] * SB,
                  channel_k(kind), [&](int pos, int comp) {
-                   if (o < capacity) events[o] = (uint16_t)(pos | (comp << 12));
+                   if (o < capacity) events[o] = hi | (uint64_t)(pos | (comp << 12));
                    else atomicOr(overflow, 1u);
                    ++o;
                  });
@@ -212,15 +217,18 @@ __global__ void k_zero_u32(uint32_t* p, int n) {
 }
 
 struct FrameArgs {
-  const int32_t* layers;
+  const int32_t* layers;     // [nlayers][3] kind, count, data offset (noise layers: noise ordinal)
   const int32_t* data;
   const int32_t* mslots;
   int32_t nlayers;
   int32_t Q;
   int32_t nslots;
   int32_t nsites;
+  int32_t nnoise;            // noise layers
+  const int32_t* noise_s0;   // [nnoise] first site of each noise layer (sites of a layer are consecutive)
+  const int32_t* noise_cnt;  // [nnoise] sites in it
   const uint32_t* offsets;   // [chunk blocks * nsites + 1]
-  const uint16_t* events;
+  const uint64_t* events;
   uint32_t capacity;
   int64_t blk0;              // first block of the chunk
   int64_t wg_word0;          // global word of workgroup 0's first word
@@ -232,12 +240,157 @@ struct FrameArgs {
   int64_t stride;            // words per output row
 };
 
+__device__ __forceinline__ int item_width(int32_t kind) {
+  return (kind == L_RESET || kind == L_H || kind == L_CLEAR) ? 1 : (kind == L_CX || kind == L_EMIT) ? 2
+         : kind == L_FEED ? 3 : 4;
+}
+
+// Operands of a thread's first PF items of one layer, loaded while the
+// previous layer runs.
+constexpr int PF = 4;
+struct FramePrefetch {
+  int32_t v[PF][4];          // gate layers: the item's integers
+  uint64_t ev[PF];           // noise layers: event words
+};
+
+template <int F>
+__device__ __forceinline__ void frame_prefetch(FramePrefetch& p, const FrameArgs& a, int L, const uint32_t* nl, int tid) {
+  if (L >= a.nlayers) return;
+  const int kind = a.layers[3 * L], cnt = a.layers[3 * L + 1], off = a.layers[3 * L + 2];
+  if (kind == L_NOISE) {
+    const uint32_t e0 = nl[2 * off], e1 = nl[2 * off + 1];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const uint32_t e = e0 + tid + j * FRAME_THREADS;
+      if (e < e1) p.ev[j] = a.events[e];
+    }
+    return;
+  }
+  const int w = item_width(kind);
+  const int32_t* it = a.data + off;
+#pragma unroll
+  for (int j = 0; j < PF; ++j) {
+    const int g = (tid + j * FRAME_THREADS) / F;
+    if (g < cnt) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        if (x < w) p.v[j][x] = it[w * g + x];
+    }
+  }
+}
+
+// One layer of the program on the F words of this workgroup.  Items of a layer
+// touch distinct frame words (noise events of one site may share a word, hence
+// the atomic XORs there; measurement records XOR into accumulator slots).
+template <int F>
+__device__ __forceinline__ void frame_layer(const FrameArgs& a, int L, const FramePrefetch& p, const uint32_t* nl,
+                                            uint64_t* fx, uint64_t* fz, uint64_t* slot, int64_t gw0, int64_t blk,
+                                            int wib0, int tid) {
+  const int kind = a.layers[3 * L], cnt = a.layers[3 * L + 1], off = a.layers[3 * L + 2];
+  if (kind == L_NOISE) {
+    auto apply = [&](const uint64_t ev) {
+      const int pos = (int)(ev & 4095u), comp = (int)((ev >> 12) & 15u), nk = (int)((ev >> 16) & 3u);
+      const int q1 = (int)((ev >> 18) & 0x7FFFFFu), q2 = (int)((ev >> 41) & 0x7FFFFFu) - 1;
+      const int f = (pos >> 6) - wib0;
+      if (f < 0 || f >= F) return;
+      const int64_t gw = gw0 + f;
+      if (gw < a.word_lo || gw >= a.word_hi) return;
+      if ((uint64_t)(blk * SB + pos) >= a.shot_end) return;
+      const unsigned long long bit = 1ull << (pos & 63);
+      int pa, pb = 0;
+      if (nk == NK_XERR) pa = 1;
+      else if (nk == NK_ZERR) pa = 3;
+      else if (nk == NK_DEP1) pa = comp + 1;
+      else { pa = (comp + 1) >> 2; pb = (comp + 1) & 3; }
+      if (pa == 1 || pa == 2) atomicXor((unsigned long long*)&fx[q1 * F + f], bit);
+      if (pa == 2 || pa == 3) atomicXor((unsigned long long*)&fz[q1 * F + f], bit);
+      if (q2 >= 0) {
+        if (pb == 1 || pb == 2) atomicXor((unsigned long long*)&fx[q2 * F + f], bit);
+        if (pb == 2 || pb == 3) atomicXor((unsigned long long*)&fz[q2 * F + f], bit);
+      }
+    };
+    const uint32_t e0 = nl[2 * off], e1 = nl[2 * off + 1];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) {
+      const uint32_t e = e0 + tid + j * FRAME_THREADS;
+      if (e < e1) apply(p.ev[j]);
+    }
+    for (uint32_t e = e0 + tid + PF * FRAME_THREADS; e < e1; e += FRAME_THREADS) apply(a.events[e]);
+    return;
+  }
+  const int w = item_width(kind);
+  const int32_t* it = a.data + off;
+  auto item = [&](const int g, const int f, const int32_t* v) {
+    switch (kind) {
+      case L_RESET:
+        fx[v[0] * F + f] = 0ull;
+        fz[v[0] * F + f] = 0ull;
+        break;
+      case L_H: {
+        const uint64_t x = fx[v[0] * F + f];
+        fx[v[0] * F + f] = fz[v[0] * F + f];
+        fz[v[0] * F + f] = x;
+        break;
+      }
+      case L_CX:
+        fx[v[1] * F + f] ^= fx[v[0] * F + f];
+        fz[v[0] * F + f] ^= fz[v[1] * F + f];
+        break;
+      case L_MEAS: {
+        const uint64_t bit = v[1] ? fz[v[0] * F + f] : fx[v[0] * F + f];
+        if (bit)
+          for (int s2 = v[2]; s2 < v[3]; ++s2)
+            atomicXor((unsigned long long*)&slot[a.mslots[s2] * F + f], (unsigned long long)bit);
+        break;
+      }
+      case L_FEED: {
+        const uint64_t x = slot[v[0] * F + f];
+        if (v[2] == 1) fx[v[1] * F + f] ^= x;
+        else fz[v[1] * F + f] ^= x;
+        break;
+      }
+      case L_CLEAR:
+        slot[v[0] * F + f] = 0ull;
+        break;
+      case L_EMIT: {
+        const int64_t gw = gw0 + f;
+        const uint64_t x = slot[v[0] * F + f];
+        slot[v[0] * F + f] = 0ull;
+        if (gw >= a.word_lo && gw < a.word_hi) {
+          const int64_t col = gw - a.word_begin;
+          if (v[1] >= 0) a.det_out[(int64_t)v[1] * a.stride + col] = x;
+          else a.obs_out[(int64_t)(-v[1] - 1) * a.stride + col] = x;
+        }
+        break;
+      }
+      default:
+        break;
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < PF; ++j) {
+    const int i = tid + j * FRAME_THREADS;
+    if (i < cnt * F) item(i / F, i % F, p.v[j]);
+  }
+  for (int i = tid + PF * FRAME_THREADS; i < cnt * F; i += FRAME_THREADS) {
+    const int g = i / F;
+    int32_t v[4] = {0, 0, 0, 0};
+    for (int x = 0; x < w; ++x) v[x] = it[w * g + x];
+    item(g, i % F, v);
+  }
+}
+
+// One workgroup per F consecutive 64-shot words of one noise block.  The layer
+// program runs with a barrier between layers; the next layer's operands are
+// loaded into registers while the current one runs (two register sets that
+// swap roles every layer).
 template <int F>
 __global__ void __launch_bounds__(FRAME_THREADS) k_frame(FrameArgs a) {
   extern __shared__ uint64_t smem[];
   uint64_t* fx = smem;
   uint64_t* fz = smem + (size_t)a.Q * F;
   uint64_t* slot = smem + (size_t)2 * a.Q * F;
+  uint32_t* nl = (uint32_t*)(slot + (size_t)a.nslots * F);      // [nnoise][2] event range of each noise layer
   const int tid = threadIdx.x;
   const int64_t gw0 = a.wg_word0 + (int64_t)blockIdx.x * F;   // first global word of this WG
   const int64_t blk = gw0 / WPB;
@@ -245,101 +398,24 @@ __global__ void __launch_bounds__(FRAME_THREADS) k_frame(FrameArgs a) {
   const int64_t ebase = (blk - a.blk0) * a.nsites;
   const int total = (2 * a.Q + a.nslots) * F;
   for (int i = tid; i < total; i += FRAME_THREADS) smem[i] = 0ull;
+  for (int j = tid; j < a.nnoise; j += FRAME_THREADS) {
+    const int s0 = a.noise_s0[j], c = a.noise_cnt[j];
+    uint32_t e0 = a.offsets[ebase + s0], e1 = a.offsets[ebase + s0 + c];
+    e0 = e0 < a.capacity ? e0 : a.capacity;
+    e1 = e1 < a.capacity ? e1 : a.capacity;
+    nl[2 * j] = e0;
+    nl[2 * j + 1] = e1;
+  }
   __syncthreads();
-  for (int L = 0; L < a.nlayers; ++L) {
-    const int kind = a.layers[3 * L];
-    const int cnt = a.layers[3 * L + 1];
-    const int32_t* it = a.data + a.layers[3 * L + 2];
-    switch (kind) {
-      case L_RESET:
-        for (int i = tid; i < cnt * F; i += FRAME_THREADS) {
-          const int q = it[i / F], f = i % F;
-          fx[q * F + f] = 0ull;
-          fz[q * F + f] = 0ull;
-        }
-        break;
-      case L_H:
-        for (int i = tid; i < cnt * F; i += FRAME_THREADS) {
-          const int q = it[i / F], f = i % F;
-          const uint64_t x = fx[q * F + f];
-          fx[q * F + f] = fz[q * F + f];
-          fz[q * F + f] = x;
-        }
-        break;
-      case L_CX:
-        for (int i = tid; i < cnt * F; i += FRAME_THREADS) {
-          const int g = i / F, f = i % F;
-          const int c = it[2 * g], t = it[2 * g + 1];
-          fx[t * F + f] ^= fx[c * F + f];
-          fz[c * F + f] ^= fz[t * F + f];
-        }
-        break;
-      case L_MEAS:
-        for (int i = tid; i < cnt * F; i += FRAME_THREADS) {
-          const int g = i / F, f = i % F;
-          const int q = it[4 * g], basis = it[4 * g + 1], s0 = it[4 * g + 2], s1 = it[4 * g + 3];
-          const uint64_t bit = basis ? fz[q * F + f] : fx[q * F + f];
-          if (bit)
-            for (int s = s0; s < s1; ++s) atomicXor((unsigned long long*)&slot[a.mslots[s] * F + f], (unsigned long long)bit);
-        }
-        break;
-      case L_FEED:
-        for (int i = tid; i < cnt * F; i += FRAME_THREADS) {
-          const int g = i / F, f = i % F;
-          const int s = it[3 * g], q = it[3 * g + 1], pa = it[3 * g + 2];
-          const uint64_t v = slot[s * F + f];
-          if (pa == 1) fx[q * F + f] ^= v; else fz[q * F + f] ^= v;
-        }
-        break;
-      case L_CLEAR:
-        for (int i = tid; i < cnt * F; i += FRAME_THREADS) {
-          const int s = it[i / F], f = i % F;
-          slot[s * F + f] = 0ull;
-        }
-        break;
-      case L_EMIT:
-        for (int i = tid; i < cnt * F; i += FRAME_THREADS) {
-          const int g = i / F, f = i % F;
-          const int s = it[2 * g], o = it[2 * g + 1];
-          const int64_t gw = gw0 + f;
-          const uint64_t v = slot[s * F + f];
-          slot[s * F + f] = 0ull;
-          if (gw >= a.word_lo && gw < a.word_hi) {
-            const int64_t col = gw - a.word_begin;
-            if (o >= 0) a.det_out[(int64_t)o * a.stride + col] = v;
-            else a.obs_out[(int64_t)(-o - 1) * a.stride + col] = v;
-          }
-        }
-        break;
-      case L_NOISE:
-        for (int g = tid; g < cnt; g += FRAME_THREADS) {
-          const int site = it[4 * g], nk = it[4 * g + 1], q1 = it[4 * g + 2], q2 = it[4 * g + 3];
-          uint32_t e0 = a.offsets[ebase + site], e1 = a.offsets[ebase + site + 1];
-          e1 = e1 < a.capacity ? e1 : a.capacity;
-          for (uint32_t e = e0; e < e1; ++e) {
-            const uint32_t code = a.events[e];
-            const int pos = (int)(code & 4095u), comp = (int)(code >> 12);
-            const int f = (pos >> 6) - wib0;
-            if (f < 0 || f >= F) continue;
-            const int64_t gw = gw0 + f;
-            if (gw < a.word_lo || gw >= a.word_hi) continue;
-            if ((uint64_t)(blk * SB + pos) >= a.shot_end) continue;
-            const uint64_t bit = 1ull << (pos & 63);
-            int pa, pb = 0;
-            if (nk == NK_XERR) pa = 1;
-            else if (nk == NK_ZERR) pa = 3;
-            else if (nk == NK_DEP1) pa = comp + 1;
-            else { pa = (comp + 1) >> 2; pb = (comp + 1) & 3; }
-            if (pa == 1 || pa == 2) fx[q1 * F + f] ^= bit;
-            if (pa == 2 || pa == 3) fz[q1 * F + f] ^= bit;
-            if (pb == 1 || pb == 2) fx[q2 * F + f] ^= bit;
-            if (pb == 2 || pb == 3) fz[q2 * F + f] ^= bit;
-          }
-        }
-        break;
-      default:
-        break;
-    }
+  FramePrefetch pa, pb;
+  frame_prefetch<F>(pa, a, 0, nl, tid);
+  for (int L = 0; L < a.nlayers; L += 2) {
+    frame_prefetch<F>(pb, a, L + 1, nl, tid);
+    frame_layer<F>(a, L, pa, nl, fx, fz, slot, gw0, blk, wib0, tid);
+    __syncthreads();
+    if (L + 1 >= a.nlayers) break;
+    frame_prefetch<F>(pa, a, L + 2, nl, tid);
+    frame_layer<F>(a, L + 1, pb, nl, fx, fz, slot, gw0, blk, wib0, tid);
     __syncthreads();
   }
 }
@@ -353,11 +429,15 @@ struct SampleDevice {
   uint8_t* site_kind = nullptr;
   uint16_t* site_tab = nullptr;
   uint64_t* tabs = nullptr;
+  int2* site_q = nullptr;          // per site: qubit(s) (second -1 for 1-qubit channels)
+  int32_t* noise_s0 = nullptr;     // per noise layer: first site, number of sites
+  int32_t* noise_cnt = nullptr;
+  int32_t nnoise = 0;
   // scratch
   uint32_t* counts = nullptr;
   uint32_t* offsets = nullptr;
   uint32_t* partial = nullptr;
-  uint16_t* events = nullptr;
+  uint64_t* events = nullptr;
   uint32_t* flag = nullptr;
   size_t cap_counts = 0, cap_offsets = 0, cap_partial = 0, cap_events = 0;
 };
@@ -374,6 +454,7 @@ tmcs_status upload(T** dst, const std::vector<T>& v) {
 void free_device(SampleDevice* d) {
   hipFree(d->layers); hipFree(d->data); hipFree(d->mslots); hipFree(d->site_kind);
   hipFree(d->site_tab); hipFree(d->tabs); hipFree(d->counts); hipFree(d->offsets);
+  hipFree(d->site_q); hipFree(d->noise_s0); hipFree(d->noise_cnt);
   hipFree(d->partial); hipFree(d->events); hipFree(d->flag);
   *d = SampleDevice();
 }
@@ -393,7 +474,34 @@ tmcs_status build_state(const Circuit& c, int dev, SampleDevice** out) {
       tabs[i * SB + (k - 1)] = (uint64_t)std::ceil(t * 4294967296.0);
     }
   }
-  if ((st = upload(&d->layers, d->prog.layers)) != TMCS_OK ||
+  // noise layers: their site ranges; the device copy of the layer table holds
+  // the noise-layer ordinal in place of the data offset
+  std::vector<int32_t> dlayers = d->prog.layers, ns0, ncnt;
+  std::vector<int2> site_q(d->prog.site_kind.size(), make_int2(0, -1));
+  for (int L = 0; L < d->prog.num_layers; ++L) {
+    if (dlayers[3 * L] != L_NOISE) continue;
+    const int cnt = dlayers[3 * L + 1], off = dlayers[3 * L + 2];
+    const int32_t* it = d->prog.data.data() + off;
+    for (int g = 0; g < cnt; ++g) {
+      if (it[4 * g] != it[0] + g) { free_device(d); delete d; return fail(TMCS_EINVAL, "noise layer sites not consecutive"); }
+      site_q[it[4 * g]] = make_int2(it[4 * g + 2], it[4 * g + 3]);
+      if (it[4 * g + 2] >= (1 << 23) - 1 || it[4 * g + 3] >= (1 << 23) - 1) {
+        free_device(d); delete d;
+        return fail(TMCS_EUNSUPPORTED, "more than 2^23 - 1 qubits");
+      }
+    }
+    dlayers[3 * L + 2] = (int32_t)ns0.size();
+    ns0.push_back(it[0]);
+    ncnt.push_back(cnt);
+  }
+  d->nnoise = (int32_t)ns0.size();
+  if ((st = upload(&d->site_q, site_q)) != TMCS_OK || (st = upload(&d->noise_s0, ns0)) != TMCS_OK ||
+      (st = upload(&d->noise_cnt, ncnt)) != TMCS_OK) {
+    free_device(d);
+    delete d;
+    return st;
+  }
+  if ((st = upload(&d->layers, dlayers)) != TMCS_OK ||
       (st = upload(&d->data, d->prog.data)) != TMCS_OK ||
       (st = upload(&d->mslots, d->prog.mslots)) != TMCS_OK ||
       (st = upload(&d->site_kind, d->prog.site_kind)) != TMCS_OK ||
@@ -439,11 +547,12 @@ tmcs_status grow(T** p, size_t* cap, size_t need) {
   return TMCS_OK;
 }
 
-int frame_words_per_wg(const Program& P, int Q, size_t* lds_bytes) {
+int frame_words_per_wg(const Program& P, int Q, int nnoise, size_t* lds_bytes) {
   const size_t per_word = (size_t)(2 * Q + P.nslots) * sizeof(uint64_t);
+  const size_t fixed = (size_t)nnoise * 8;
   int F = 64;
-  while (F > 1 && per_word * F > 64 * 1024) F >>= 1;
-  *lds_bytes = per_word * F;
+  while (F > 1 && per_word * F + fixed > 64 * 1024) F >>= 1;
+  *lds_bytes = per_word * F + fixed;
   return F;
 }
 
@@ -476,7 +585,7 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
   const int64_t stride = (int64_t)((n_shots + 63) / 64);
   const int64_t word_begin = (int64_t)(shot_begin / 64);
   size_t lds = 0;
-  const int F = frame_words_per_wg(P, c.num_qubits, &lds);
+  const int F = frame_words_per_wg(P, c.num_qubits, d->nnoise, &lds);
   if (lds > 160 * 1024) return fail(TMCS_EUNSUPPORTED, "circuit frame exceeds the 160 KB LDS of one workgroup");
   // the overflow flag: per call, or a caller-owned sticky flag (graph replays)
   uint32_t* flag = overflow_out ? overflow_out : d->flag;
@@ -509,13 +618,14 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
       TMCS_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, stream, d->partial, ntiles);
       TMCS_LAUNCH("k_scan_final", k_scan_final, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial, d->offsets);
       TMCS_LAUNCH("k_event_write", k_event_write, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
-                         instance, d->site_kind, d->site_tab, d->tabs, d->offsets, d->events,
+                         instance, d->site_kind, d->site_tab, d->tabs, d->site_q, d->offsets, d->events,
                          (uint32_t)d->cap_events, flag, blk_off);
       if ((st = hip_check(hipGetLastError(), "event kernels")) != TMCS_OK) return st;
     }
     FrameArgs a;
     a.layers = d->layers; a.data = d->data; a.mslots = d->mslots;
     a.nlayers = P.num_layers; a.Q = c.num_qubits; a.nslots = P.nslots; a.nsites = (int32_t)nsites;
+    a.nnoise = d->nnoise; a.noise_s0 = d->noise_s0; a.noise_cnt = d->noise_cnt;
     a.offsets = d->offsets; a.events = d->events; a.capacity = (uint32_t)d->cap_events;
     a.blk0 = b0;
     a.word_lo = (int64_t)(s_lo / 64);
