@@ -55,17 +55,17 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 }
 
 // g = #{k in 1..4096 : u < T[k]} with T non-increasing (tab[k-1] = T[k]).
-__device__ __forceinline__ int geometric_gap(const uint64_t* __restrict__ tab, uint32_t u) {
-  int lo = 0, hi = SB;
+// Since T[k] ~ (1-p)^k 2^32, g is close to log(u / 2^32) / log(1 - p); that
+// value (inv = 1 / log(1 - p)) only picks where to start, and the table walk
+// from there gives the exact count: T[g] > u >= T[g + 1].
+__device__ __forceinline__ int geometric_gap(const uint64_t* __restrict__ tab, uint32_t u, double inv) {
   const uint64_t uu = u;
-#pragma unroll
-  for (int it = 0; it < 13; ++it) {
-    if (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (__ldg(tab + mid) > uu) lo = mid + 1; else hi = mid;
-    }
-  }
-  return lo;
+  if (inv == 0.0) return SB;                       // p = 0: T[k] = 2^32 > u for every k
+  const double x = log(((double)u + 0.5) * (1.0 / 4294967296.0)) * inv;
+  int k = x < 0.0 ? 0 : (x > (double)SB ? SB : (int)x);
+  while (k < SB && __ldg(tab + k) > uu) ++k;
+  while (k > 0 && __ldg(tab + k - 1) <= uu) --k;
+  return k;
 }
 
 __device__ __forceinline__ int channel_k(uint8_t kind) {
@@ -75,7 +75,7 @@ __device__ __forceinline__ int channel_k(uint8_t kind) {
 // Walk the event stream of (block, site); call emit(pos, comp) per event.
 template <typename Emit>
 __device__ __forceinline__ void event_stream(uint32_t k0, uint32_t k1, uint32_t block, uint32_t site,
-                                             uint32_t inst, const uint64_t* __restrict__ tab, int K,
+                                             uint32_t inst, const uint64_t* __restrict__ tab, double inv, int K,
                                              Emit emit) {
   uint32_t w[4];
   uint32_t call = 0;
@@ -84,7 +84,7 @@ __device__ __forceinline__ void event_stream(uint32_t k0, uint32_t k1, uint32_t 
   while (true) {
     if (have == 0) { philox4x32_10(block, site, inst, call++, k0, k1, w); have = 4; }
     const uint32_t u = w[4 - have--];
-    pos += geometric_gap(tab, u) + 1;
+    pos += geometric_gap(tab, u, inv) + 1;
     if (pos >= SB) break;
     int comp = 0;
     if (K > 1) {
@@ -99,7 +99,8 @@ __device__ __forceinline__ void event_stream(uint32_t k0, uint32_t k1, uint32_t 
 __global__ void k_event_count(int64_t nsites, int64_t nblk, int64_t blk0, uint32_t k0, uint32_t k1,
                               uint32_t inst, const uint8_t* __restrict__ site_kind,
                               const uint16_t* __restrict__ site_tab, const uint64_t* __restrict__ tabs,
-                              uint32_t* __restrict__ counts, const uint64_t* __restrict__ blk_off) {
+                              const double* __restrict__ tab_inv, uint32_t* __restrict__ counts,
+                              const uint64_t* __restrict__ blk_off) {
   const int64_t n = nsites * nblk;
   if (blk_off) blk0 += (int64_t)*blk_off;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -107,7 +108,8 @@ __global__ void k_event_count(int64_t nsites, int64_t nblk, int64_t blk0, uint32
     const int64_t b = i / nsites, s = i - b * nsites;
     const uint8_t kind = site_kind[s];
     uint32_t cnt = 0;
-    event_stream(k0, k1, (uint32_t)(blk0 + b), (uint32_t)s, inst, tabs + (int64_t)site_tab[s] * SB,
+    const int ti = site_tab[s];
+    event_stream(k0, k1, (uint32_t)(blk0 + b), (uint32_t)s, inst, tabs + (int64_t)ti * SB, tab_inv[ti],
                  channel_k(kind), [&](int, int) { ++cnt; });
     counts[i] = cnt;
   }
@@ -118,7 +120,8 @@ __global__ void k_event_count(int64_t nsites, int64_t nblk, int64_t blk0, uint32
 __global__ void k_event_write(int64_t nsites, int64_t nblk, int64_t blk0, uint32_t k0, uint32_t k1,
                               uint32_t inst, const uint8_t* __restrict__ site_kind,
                               const uint16_t* __restrict__ site_tab, const uint64_t* __restrict__ tabs,
-                              const int2* __restrict__ site_q, const uint32_t* __restrict__ offsets,
+                              const double* __restrict__ tab_inv, const int2* __restrict__ site_q,
+                              const uint32_t* __restrict__ offsets,
                               uint64_t* __restrict__ events, uint32_t capacity, uint32_t* __restrict__ overflow,
                               const uint64_t* __restrict__ blk_off) {
   const int64_t n = nsites * nblk;
@@ -130,7 +133,8 @@ __global__ void k_event_write(int64_t nsites, int64_t nblk, int64_t blk0, uint32
     const int2 q = site_q[s];
     const uint64_t hi = ((uint64_t)kind << 16) | ((uint64_t)(uint32_t)q.x << 18) | ((uint64_t)(uint32_t)(q.y + 1) << 41);
     uint32_t o = offsets[i];
-    event_stream(k0, k1, (uint32_t)(blk0 + b), (uint32_t)s, inst, tabs + (int64_t)site_tab[s] * SB,
+    const int ti = site_tab[s];
+    event_stream(k0, k1, (uint32_t)(blk0 + b), (uint32_t)s, inst, tabs + (int64_t)ti * SB, tab_inv[ti],
                  channel_k(kind), [&](int pos, int comp) {
                    if (o < capacity) events[o] = hi | (uint64_t)(pos | (comp << 12));
                    else atomicOr(overflow, 1u);
@@ -429,6 +433,7 @@ struct SampleDevice {
   uint8_t* site_kind = nullptr;
   uint16_t* site_tab = nullptr;
   uint64_t* tabs = nullptr;
+  double* tab_inv = nullptr;       // per table: 1 / log(1 - p) (search start only)
   int2* site_q = nullptr;          // per site: qubit(s) (second -1 for 1-qubit channels)
   int32_t* noise_s0 = nullptr;     // per noise layer: first site, number of sites
   int32_t* noise_cnt = nullptr;
@@ -454,7 +459,7 @@ tmcs_status upload(T** dst, const std::vector<T>& v) {
 void free_device(SampleDevice* d) {
   hipFree(d->layers); hipFree(d->data); hipFree(d->mslots); hipFree(d->site_kind);
   hipFree(d->site_tab); hipFree(d->tabs); hipFree(d->counts); hipFree(d->offsets);
-  hipFree(d->site_q); hipFree(d->noise_s0); hipFree(d->noise_cnt);
+  hipFree(d->site_q); hipFree(d->noise_s0); hipFree(d->noise_cnt); hipFree(d->tab_inv);
   hipFree(d->partial); hipFree(d->events); hipFree(d->flag);
   *d = SampleDevice();
 }
@@ -465,7 +470,10 @@ tmcs_status build_state(const Circuit& c, int dev, SampleDevice** out) {
   tmcs_status st = compile_program(c, &d->prog);
   if (st != TMCS_OK) { delete d; return st; }
   std::vector<uint64_t> tabs(d->prog.tab_p.size() * SB);
+  std::vector<double> tab_inv(d->prog.tab_p.size());
   for (size_t i = 0; i < d->prog.tab_p.size(); ++i) {
+    const double lq = std::log1p(-d->prog.tab_p[i]);
+    tab_inv[i] = lq < 0.0 ? 1.0 / lq : 0.0;
     // T[k] = ceil(t_k 2^32), t_0 = 1, t_k = t_{k-1} (1 - p), FP64
     double t = 1.0;
     const double q = 1.0 - d->prog.tab_p[i];
@@ -506,7 +514,7 @@ tmcs_status build_state(const Circuit& c, int dev, SampleDevice** out) {
       (st = upload(&d->mslots, d->prog.mslots)) != TMCS_OK ||
       (st = upload(&d->site_kind, d->prog.site_kind)) != TMCS_OK ||
       (st = upload(&d->site_tab, d->prog.site_tab)) != TMCS_OK ||
-      (st = upload(&d->tabs, tabs)) != TMCS_OK) {
+      (st = upload(&d->tabs, tabs)) != TMCS_OK || (st = upload(&d->tab_inv, tab_inv)) != TMCS_OK) {
     free_device(d);
     delete d;
     return st;
@@ -613,12 +621,12 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
       const int thr = 256;
       const int64_t grid = std::min<int64_t>((n + thr - 1) / thr, 1 << 20);
       TMCS_LAUNCH("k_event_count", k_event_count, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
-                         instance, d->site_kind, d->site_tab, d->tabs, d->counts, blk_off);
+                         instance, d->site_kind, d->site_tab, d->tabs, d->tab_inv, d->counts, blk_off);
       TMCS_LAUNCH("k_scan_partials", k_scan_partials, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial);
       TMCS_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, stream, d->partial, ntiles);
       TMCS_LAUNCH("k_scan_final", k_scan_final, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial, d->offsets);
       TMCS_LAUNCH("k_event_write", k_event_write, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
-                         instance, d->site_kind, d->site_tab, d->tabs, d->site_q, d->offsets, d->events,
+                         instance, d->site_kind, d->site_tab, d->tabs, d->tab_inv, d->site_q, d->offsets, d->events,
                          (uint32_t)d->cap_events, flag, blk_off);
       if ((st = hip_check(hipGetLastError(), "event kernels")) != TMCS_OK) return st;
     }
