@@ -110,7 +110,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: only one GPU is used in this build (asked for --gpus {args.gpus}); "
-              "the path shards by shot blocks with one all-reduce of counts, see the design notes.",
+              "the path would shard by 4096-shot noise blocks with one all-reduce of the counts.",
               file=sys.stderr)
         sys.exit(2)
     import torch

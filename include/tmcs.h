@@ -121,9 +121,11 @@ tmcs_status tmcs_dem_export(const tmcs_dem* d, int32_t* col_ptr, int32_t* row_id
                             double* priors, uint64_t* obs_mask);
 
 /* Sample n_shots shots [shot_begin, shot_begin + n_shots) of circuit c.
- * Noise: Philox4x32-10 keyed by (seed) with counter (block, site, instance, call),
- * 4096-shot blocks with geometric gaps between events (the bit definition is in
- * the design notes of the library).  shot_begin must be a multiple of 64.
+ * Noise: Philox4x32-10 with key (seed lo, seed hi) and counter (block, site,
+ * instance, call) draws the events of each noise site per 4096-shot block; a draw
+ * u gives g = #{k in 1..4096 : u < ceil((1-p)^k 2^32)} event-free shots before
+ * the next event, and a K-component channel picks component (v K) >> 32 from the
+ * next draw v.  shot_begin must be a multiple of 64.
  * det_dev: [detectors][ceil(n/64)] uint64; obs_dev: [observables][ceil(n/64)].
  * Scratch device memory is cached on the circuit handle and grows on demand;
  * the call synchronises the stream once to check the event-buffer capacity. */
@@ -132,8 +134,11 @@ tmcs_status tmcs_sample(const tmcs_circuit* c, uint64_t seed, uint32_t instance,
                         uint64_t* obs_dev, void* stream);
 
 /* Decoder configuration: flooding min-sum BP over the DEM with an OSD-0 fallback
- * (Supplementary Note 7 names BP-OSD; the update rules are stated in the
- * library's design notes). */
+ * (Supplementary Note 7 names BP-OSD).  With priors lambda_v = ln((1-p_v)/p_v):
+ *   m_{c->v} = (-1)^{s_c} prod_{v' != v} sgn(q_{v'->c}) * alpha * min_{v' != v} |q_{v'->c}|,
+ *   L_v = lambda_v + sum_c m_{c->v} (c ascending), q_{v->c} = L_v - m_{c->v},
+ * stopping when H [L < 0] = s; OSD-0 orders columns by (L_v, v), keeps the first
+ * GF(2)-independent ones and solves H_S e_S = s on them.  All in FP32. */
 typedef struct {
   int32_t max_iter;         /* BP iterations T (>= 1) */
   float alpha;              /* scalar scaling of check messages (plain BP) */
@@ -141,10 +146,12 @@ typedef struct {
                                weights (edges in row-major order of H) replacing alpha */
   int32_t use_osd;          /* 1: OSD-0 on shots where BP did not converge */
   /* launch shape (0 = library default; results never depend on these): */
-  int32_t bp_threads;       /* threads per BP workgroup (multiple of 64, <= 1024) */
-  int32_t bp_per_cu;        /* resident BP workgroups per compute unit */
+  int32_t bp_threads;       /* threads of a BP team, the workgroup that decodes one shot
+                               at a time (multiple of 64, <= 1024) */
+  int32_t bp_per_cu;        /* resident BP teams per compute unit */
   int32_t osd_per_cu;       /* resident OSD workgroups per compute unit */
-  int32_t bp_slots;         /* shots a BP workgroup carries at once (<= 16) */
+  int32_t bp_global_state;  /* 1: keep each shot's BP state in device memory instead of LDS
+                               (automatic when it exceeds the 160 KB LDS of a compute unit) */
   /* optional per-shot outputs (NULL to skip), each indexed by shot of the call: */
   uint8_t* ehat_dev;        /* [n_shots][cols] final correction (0/1 bytes) */
   float* llr_dev;           /* [n_shots][cols] final BP posterior LLRs */

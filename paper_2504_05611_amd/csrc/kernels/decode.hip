@@ -62,7 +62,8 @@ struct DecodeDevice {
   float* osd_llr = nullptr;
   uint64_t* basis = nullptr;
   uint64_t* synd = nullptr;
-  size_t cap_queue = 0, cap_osd = 0, cap_llr = 0, cap_basis = 0, cap_synd = 0;
+  unsigned char* gstate = nullptr;  // BP state in device memory, one slab per team
+  size_t cap_queue = 0, cap_osd = 0, cap_llr = 0, cap_basis = 0, cap_synd = 0, cap_gstate = 0;
 };
 
 // Per-lane schedule records of the BP passes (int4 = {x, y, z, w}).
@@ -106,6 +107,8 @@ struct BPArgs {
   float* llr;
   int32_t* iters;
   uint8_t* flags;
+  unsigned char* gstate;     // GSTATE: [grid][team_bytes]
+  size_t team_bytes;
 };
 
 __device__ __forceinline__ void write_pred(uint64_t* pred, int64_t stride, int nobs, int64_t shot, uint64_t mask) {
@@ -185,10 +188,14 @@ __global__ void k_compact(const uint64_t* __restrict__ synd, int32_t mw, int64_t
 // on the DEM alone (precomputed, plus the syndrome bit).  Iteration t is then a
 // variable pass (L^t) followed by a check pass that tests H [L^t < 0] = s and,
 // if t < T, builds the state of iteration t + 1.
-template <bool WEIGHTED>
+// GSTATE: the per-shot state lives in this team's slab of device memory
+// (a.gstate + blockIdx.x * a.team_bytes) instead of LDS, for DEMs whose state
+// does not fit; the code is otherwise the same.
+template <bool WEIGHTED, bool GSTATE>
 __global__ void __launch_bounds__(1024) k_bp(BPArgs a) {
   extern __shared__ __align__(16) unsigned char sm[];
-  float4* state = (float4*)sm;                        // [m + 1] (slot m: padding records)
+  unsigned char* base = GSTATE ? a.gstate + (size_t)blockIdx.x * a.team_bytes : sm;
+  float4* state = (float4*)base;                      // [m + 1] (slot m: padding records)
   float* L = (float*)(state + a.m + 1);               // [n]
   uint8_t* sgn = (uint8_t*)(L + a.n);                 // [E4 + 4] (byte E4: padding records)
   __shared__ int s_job, s_flag, s_pos;
@@ -358,7 +365,8 @@ struct OSDArgs {
   const int32_t* csc_row;
   const uint64_t* obs_mask;
   int32_t m, n, rank;
-  const uint64_t* det;
+  const uint64_t* synd;      // [chunk shots][mw] shot-major syndrome words
+  int32_t mw;
   int64_t stride;
   int64_t shot0;
   int32_t* counters;
@@ -517,9 +525,13 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
     // 1. sort columns by (L_v, v); list the syndrome's rows
     if (tid == 0) { s_r = 0; s_ns = 0; }
     __syncthreads();
-    for (int r = tid; r < a.m; r += NT) {
-      prow[r] = -1;
-      if ((a.det[(int64_t)r * a.stride + (shot >> 6)] >> (shot & 63)) & 1ull) srow[atomicAdd(&s_ns, 1)] = r;
+    for (int r = tid; r < a.m; r += NT) prow[r] = -1;
+    for (int wd = tid; wd < a.mw; wd += NT) {
+      uint64_t x = a.synd[ls * a.mw + wd];
+      if (x) {
+        const int base = atomicAdd(&s_ns, __popcll(x));
+        for (int k = 0; x; ++k, x &= x - 1) srow[base + k] = wd * 64 + (__ffsll((unsigned long long)x) - 1);
+      }
     }
     {
       uint64_t x[KPT];
@@ -712,7 +724,7 @@ tmcs_status grow(T** p, size_t* cap, size_t need) {
 void free_device(DecodeDevice* d) {
   hipFree(d->row_ptr); hipFree(d->col_idx); hipFree(d->col_ptr); hipFree(d->csc_row); hipFree(d->csc_edge);
   hipFree(d->lam); hipFree(d->obs_mask); hipFree(d->counters); hipFree(d->queue); hipFree(d->osd_queue);
-  hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd); hipFree(d->init); hipFree(d->sign0);
+  hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd); hipFree(d->gstate); hipFree(d->init); hipFree(d->sign0);
   for (auto& q : d->scheds) { hipFree(q.c); hipFree(q.v); }
   *d = DecodeDevice();
 }
@@ -955,15 +967,16 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int cus = device_cus();
   // BP launch shape: one team (workgroup) per shot in flight, state in LDS
   const size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (size_t)d->E4 + 4;
-  if (bp_lds > 160 * 1024)
-    return fail(TMCS_EUNSUPPORTED, "BP state of one shot exceeds the 160 KB LDS of a compute unit");
-  const int team_fit = std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));   // teams per CU by LDS
+  const bool gstate = cfg.bp_global_state != 0 || bp_lds > 160 * 1024;
+  const size_t team_bytes = (bp_lds + 255) & ~(size_t)255;
+  // teams per CU: as many as fit in LDS, or 4 teams of 8 waves with the state in device memory
+  const int team_fit = gstate ? 4 : std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));
   int P;
   if (cfg.bp_threads > 0) {
     P = cfg.bp_threads;
   } else {
     // about 8 waves per CU, but no lane should carry much more than its share of edges
-    int G = std::max(1, std::min(16, (8 + team_fit - 1) / team_fit));
+    int G = gstate ? 8 : std::max(1, std::min(16, (8 + team_fit - 1) / team_fit));
     P = 64 * G;
     const int64_t cap = std::max<int64_t>(64, (3 * D.edges / std::max(2 * d->max_row_deg, 1)) / 64 * 64);
     while (P > 64 && P > cap) P -= 64;
@@ -971,9 +984,9 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
   DecodeDevice::Sched sch;
   if ((st = get_sched(D, d, P, &sch)) != TMCS_OK) return st;
-  if (bp_lds > 64 * 1024 &&
-      (hipFuncSetAttribute((const void*)k_bp<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
-       hipFuncSetAttribute((const void*)k_bp<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess))
+  if (!gstate && bp_lds > 64 * 1024 &&
+      (hipFuncSetAttribute((const void*)k_bp<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
+       hipFuncSetAttribute((const void*)k_bp<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess))
     return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
   const int per_cu = std::max(1, std::min({team_fit, 32 / (P / 64), cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 32}));
   // shots per internal pass: bounded so the OSD LLR staging stays <= 1 GiB
@@ -992,6 +1005,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int osd_grid = std::max(1, cus * osd_per_cu);
   if ((st = grow(&d->queue, &d->cap_queue, (size_t)chunk)) != TMCS_OK) return st;
   if ((st = grow(&d->synd, &d->cap_synd, (size_t)chunk * (size_t)std::max(mw, 1))) != TMCS_OK) return st;
+  if (gstate && (st = grow(&d->gstate, &d->cap_gstate, (size_t)cus * per_cu * team_bytes)) != TMCS_OK) return st;
   if (cfg.use_osd) {
     if ((st = grow(&d->osd_queue, &d->cap_osd, (size_t)chunk)) != TMCS_OK ||
         (st = grow(&d->osd_llr, &d->cap_llr, (size_t)chunk * (size_t)D.cols)) != TMCS_OK ||
@@ -1028,13 +1042,20 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
     a.pred = pred; a.nobs = D.nobs; a.stats = stats; a.ehat = cfg.ehat_dev; a.llr = cfg.llr_dev;
     a.iters = cfg.iters_dev; a.flags = cfg.flags_dev;
     const int bp_grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(ns, 1));
-    if (cfg.weights_dev) TMCS_LAUNCH("k_bp", k_bp<true>, dim3(bp_grid), dim3(P), bp_lds, stream, a);
-    else TMCS_LAUNCH("k_bp", k_bp<false>, dim3(bp_grid), dim3(P), bp_lds, stream, a);
+    a.gstate = d->gstate; a.team_bytes = team_bytes;
+    if (gstate) {
+      if (cfg.weights_dev) TMCS_LAUNCH("k_bp", (k_bp<true, true>), dim3(bp_grid), dim3(P), 0, stream, a);
+      else TMCS_LAUNCH("k_bp", (k_bp<false, true>), dim3(bp_grid), dim3(P), 0, stream, a);
+    } else {
+      if (cfg.weights_dev) TMCS_LAUNCH("k_bp", (k_bp<true, false>), dim3(bp_grid), dim3(P), bp_lds, stream, a);
+      else TMCS_LAUNCH("k_bp", (k_bp<false, false>), dim3(bp_grid), dim3(P), bp_lds, stream, a);
+    }
     if ((st = hip_check(hipGetLastError(), "k_bp launch")) != TMCS_OK) return st;
     if (cfg.use_osd) {
       OSDArgs o;
       o.col_ptr = d->col_ptr; o.csc_row = d->csc_row; o.obs_mask = d->obs_mask;
-      o.m = D.rows; o.n = D.cols; o.rank = D.rank; o.det = det; o.stride = stride; o.shot0 = s0;
+      o.m = D.rows; o.n = D.cols; o.rank = D.rank; o.synd = d->synd; o.mw = std::max(mw, 1); o.stride = stride;
+      o.shot0 = s0;
       o.counters = d->counters; o.osd_queue = d->osd_queue; o.osd_llr = d->osd_llr; o.basis = d->basis;
       o.pred = pred; o.nobs = D.nobs; o.stats = stats; o.ehat = cfg.ehat_dev; o.flags = cfg.flags_dev;
       o.npad = npad;
@@ -1112,7 +1133,7 @@ tmcs_status autotune_run(const Dem& D, const uint64_t* det, uint64_t n_shots, tm
     for (int bc : bp_cu)
       for (int oc : osd_cu) {
         tmcs_decoder_cfg c = base;
-        c.bp_threads = th; c.bp_per_cu = bc; c.osd_per_cu = oc; c.bp_slots = 1;
+        c.bp_threads = th; c.bp_per_cu = bc; c.osd_per_cu = oc;
         if ((st = decode_run(D, c, det, n_shots, pred, nullptr, stream)) != TMCS_OK) break;   // warm
         (void)hipEventRecord(e0, stream);
         if ((st = decode_run(D, c, det, n_shots, pred, nullptr, stream)) != TMCS_OK) break;
@@ -1129,7 +1150,6 @@ tmcs_status autotune_run(const Dem& D, const uint64_t* det, uint64_t n_shots, tm
   cfg->bp_threads = best.bp_threads;
   cfg->bp_per_cu = best.bp_per_cu;
   cfg->osd_per_cu = best.osd_per_cu;
-  cfg->bp_slots = best.bp_slots;
   return TMCS_OK;
 }
 

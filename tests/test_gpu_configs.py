@@ -4,9 +4,9 @@
   instances of one graph-captured plan (the batched launch);
 * BB [[144,12,12]] teleportation through 144 ebits (plain BP-OSD and the
   weighted-BP kernels, T = 20);
-* the surface-code non-local CNOT of the mixed batch at d = 11 (BP, whose
-  detector count is beyond this build's OSD-0), and the sizes this build
-  refuses.
+* the surface-code non-local CNOT of the mixed batch at d = 11 (BP with its
+  state in LDS and in device memory; the detector count is beyond this
+  build's OSD-0) and d = 15 (BP state in device memory only).
 
 The oracle checks sampled bits bit for bit and decodes sampled 64-shot words
 in FP32 (the decoder's precision) in the same operation order.
@@ -63,11 +63,13 @@ def test_bb144_memory_three_instances_in_one_plan(gpu_lib):
         preds.append((det.cpu().numpy().view(np.uint64), pred.cpu().numpy().view(np.uint64)))
     # bits of instance 2 on a stretch that crosses a noise block, and one decoded word of instance 1
     _check_sampler(gpu_lib, circuits[2], w.specs[2], w.seed, 2, 4096 - 64, 128)
-    od = build_dem(build_circuit(w.specs[1]))
+    oc1 = build_circuit(w.specs[1])
+    od = build_dem(oc1)
     dec = Decoder(od.H(), od.priors(), od.L(), max_iter=w.bp_iters, dtype=np.float32)
-    d1, p1 = preds[1]
+    _, p1 = preds[1]
     wd = 37
-    o = dec.decode(unpack_bits(d1[:, wd:wd + 1], 64).T)
+    synd, _ = oracle_sample(oc1, w.seed, 1, wd * 64, 64)
+    o = dec.decode(synd.T)
     assert (unpack_bits(p1[:, wd:wd + 1], 64).T[:, : od.num_obs] == o["pred_obs"]).all()
 
 
@@ -84,12 +86,13 @@ def test_bb144_teleport_decoder_and_weighted_bp(gpu_lib):
     pred = torch.zeros_like(obs)
     dem.decode(det, n, pred, max_iter=w.bp_iters)
     torch.cuda.synchronize()
-    d = det.cpu().numpy().view(np.uint64)
     p = pred.cpu().numpy().view(np.uint64)
-    od = build_dem(build_circuit(spec))
+    oc = build_circuit(spec)
+    od = build_dem(oc)
     dec = Decoder(od.H(), od.priors(), od.L(), max_iter=w.bp_iters, dtype=np.float32)
     wd = 5
-    o = dec.decode(unpack_bits(d[:, wd:wd + 1], 64).T)
+    synd, _ = oracle_sample(oc, w.seed, 0, wd * 64, 64)
+    o = dec.decode(synd.T)
     assert (unpack_bits(p[:, wd:wd + 1], 64).T[:, : od.num_obs] == o["pred_obs"]).all()
     # weighted BP at this shape: FP32 forward bit for bit, gradient against the FP64-arithmetic reference
     T, shots = 4, 2
@@ -98,14 +101,14 @@ def test_bb144_teleport_decoder_and_weighted_bp(gpu_lib):
     wt = torch.from_numpy(wts).cuda()
     ws = torch.empty(dem.wbp_workspace_size(T, shots), dtype=torch.uint8, device="cuda")
     llr = torch.empty((T, shots, dem.cols), dtype=torch.float32, device="cuda")
-    det2, _ = c.alloc_outputs(shots)
-    c.sample(w.seed, 0, 0, shots, det2, _)
+    d2, _ = oracle_sample(oc, w.seed, 0, 0, shots)
+    det2 = torch.from_numpy(pack_bits(d2).view(np.int64)).cuda()
     dem.wbp_forward(wt, T, det2, shots, llr, ws)
     G = rng.normal(size=(T, shots, dem.cols)).astype(np.float32)
     gw = torch.zeros_like(wt)
     dem.wbp_backward(wt, T, det2, shots, torch.from_numpy(G).cuda(), gw, ws)
     torch.cuda.synchronize()
-    synd = unpack_bits(det2.cpu().numpy().view(np.uint64), shots).T
+    synd = d2.T
     f32 = oracle_forward(od.H(), od.priors(), synd, wts, dtype=np.float32)
     assert (llr.cpu().numpy() == f32["L"]).all()
     ref = oracle_backward(f32, G.astype(np.float64))
@@ -121,25 +124,58 @@ def test_sc11_nlcnot_bp_and_size_limits(gpu_lib):
     dem = gpu_lib.DEM(c)
     _check_sampler(gpu_lib, c, spec, w.seed, 1, 4096 - 64, 128)
     n = 64
-    det, obs = c.alloc_outputs(n)
-    c.sample(w.seed, 1, 0, n, det, obs)
-    pred = torch.zeros_like(obs)
+    oc = build_circuit(spec)
+    d_or, o_or = oracle_sample(oc, w.seed, 1, 0, n)
+    det = torch.from_numpy(pack_bits(d_or).view(np.int64)).cuda()
+    pred = torch.zeros((c.num_observables, 1), dtype=torch.int64, device="cuda")
     llr = torch.zeros((n, dem.cols), dtype=torch.float32, device="cuda")
     iters = torch.zeros(n, dtype=torch.int32, device="cuda")
     dem.decode(det, n, pred, max_iter=w.bp_iters, use_osd=False, llr=llr, iters=iters)
     torch.cuda.synchronize()
-    od = build_dem(build_circuit(spec))
-    synd = unpack_bits(det.cpu().numpy().view(np.uint64), n).T[:16]
+    od = build_dem(oc)
+    synd = d_or.T[:16]
     r = decode_bp(od.H(), od.priors(), synd, w.bp_iters, dtype=np.float32)
     assert (iters.cpu().numpy()[:16] == r["iters"]).all()
     assert (llr.cpu().numpy()[:16] == r["llr"].astype(np.float32)).all()
-    # OSD-0 beyond 2048 detectors and BP state beyond one CU's LDS are refused, not approximated
+    # the same shots with the BP state in device memory instead of LDS
+    llr_g = torch.zeros_like(llr)
+    dem.decode(det, n, pred, max_iter=w.bp_iters, use_osd=False, llr=llr_g, bp_global_state=1)
+    torch.cuda.synchronize()
+    assert (llr_g.cpu().numpy() == llr.cpu().numpy()).all()
+    # OSD-0 beyond 2048 detectors is refused, not approximated
     with pytest.raises(gpu_lib.TmcsError):
         dem.decode(det, n, pred, max_iter=w.bp_iters, use_osd=True)
-    c15 = gpu_lib.Circuit(next(s for s in w.specs if s.d == 15))
-    big = gpu_lib.DEM(c15)
-    det15, obs15 = c15.alloc_outputs(n)
-    pred15 = torch.zeros_like(obs15)
-    with pytest.raises(gpu_lib.TmcsError):
-        big.decode(det15, n, pred15, max_iter=w.bp_iters, use_osd=False)
     torch.cuda.synchronize()
+
+
+def test_sc15_nlcnot_bp_state_in_device_memory(gpu_lib):
+    """d = 15: the per-shot BP state (~336 KB) exceeds LDS and lives in device memory.
+
+    The oracle's DEM of this circuit takes minutes to build, so it is read from
+    tests/golden/dem_sc15_nlcnot_p1e-3.npz (written by make_dem_sc15_nlcnot.py
+    from oracle/ code only)."""
+    import os
+    import torch
+    w = WORKLOADS["sc_nlcnot_mixed"]
+    inst, spec = next((i, s) for i, s in enumerate(w.specs) if s.d == 15 and s.p == 1e-3)
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "dem_sc15_nlcnot_p1e-3.npz"))
+    m, ncol = int(g["num_dets"]), len(g["priors"])
+    H = np.zeros((m, ncol), dtype=np.uint8)
+    cp = g["col_ptr"]
+    for j in range(ncol):
+        H[g["rows"][cp[j]:cp[j + 1]], j] = 1
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    assert dem.rows == m and dem.cols == ncol
+    n = 64
+    d_or, _ = oracle_sample(build_circuit(spec), w.seed, inst, 0, n)
+    det = torch.from_numpy(pack_bits(d_or).view(np.int64)).cuda()
+    pred = torch.zeros((c.num_observables, 1), dtype=torch.int64, device="cuda")
+    llr = torch.zeros((n, dem.cols), dtype=torch.float32, device="cuda")
+    iters = torch.zeros(n, dtype=torch.int32, device="cuda")
+    dem.decode(det, n, pred, max_iter=w.bp_iters, use_osd=False, llr=llr, iters=iters)
+    torch.cuda.synchronize()
+    r = decode_bp(H, g["priors"], d_or.T[:4], w.bp_iters, dtype=np.float32)
+    print(f"[sc15] iters {iters.cpu().numpy()[:4]} oracle {r['iters']}", flush=True)
+    assert (iters.cpu().numpy()[:4] == r["iters"]).all()
+    assert (llr.cpu().numpy()[:4] == r["llr"].astype(np.float32)).all()

@@ -10,7 +10,7 @@ import pytest
 
 from oracle.circuits import build_circuit
 from oracle.dem import build_dem
-from oracle.frame import unpack_bits
+from oracle.frame import pack_bits, sample as oracle_sample, unpack_bits
 from oracle.osd import Decoder, logical_errors
 from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc
 
@@ -25,12 +25,20 @@ CASES = [
 ]
 
 
+def _oracle_det(spec, shots, seed=3):
+    """Detector and observable bit planes from the oracle's own sampler (device tensors)."""
+    import torch
+    d, o = oracle_sample(build_circuit(spec), seed, 0, 0, shots)
+    det = torch.from_numpy(pack_bits(d).view(np.int64)).cuda()
+    obs = torch.from_numpy(pack_bits(o).view(np.int64)).cuda()
+    return det, obs
+
+
 def _run_lib(tmcs, spec, shots, T, seed=3, alpha=1.0):
     import torch
     c = tmcs.Circuit(spec)
     dem = tmcs.DEM(c)
-    det, obs = c.alloc_outputs(shots)
-    c.sample(seed, 0, 0, shots, det, obs)
+    det, obs = _oracle_det(spec, shots, seed)
     N = dem.cols
     k = max(c.num_observables, 1)
     w = (shots + 63) // 64
@@ -126,15 +134,15 @@ def test_decoder_full_size_sampled(gpu_lib):
     st = gpu_lib.read_stats(stats)
     print(f"[decoder-full] errors={ne} ler={ler:.3e} stats={st}", flush=True)
     assert st["shots"] == N and st["not_in_span"] == 0
-    d = det.cpu().numpy().view(np.uint64)
     p = pred.cpu().numpy().view(np.uint64)
-    od = build_dem(build_circuit(spec))
+    oc = build_circuit(spec)
+    od = build_dem(oc)
     dec = Decoder(od.H(), od.priors(), od.L(), max_iter=w.bp_iters, dtype=np.float32)
     rng = np.random.default_rng(0)
     words = np.sort(rng.choice(N // 64, size=12, replace=False))
     for wd in words:
-        synd = unpack_bits(d[:, wd:wd + 1], 64).T
-        o = dec.decode(synd)
+        synd, _ = oracle_sample(oc, w.seed, 0, int(wd) * 64, 64)     # the oracle's own bits of these shots
+        o = dec.decode(synd.T)
         got = unpack_bits(p[:, wd:wd + 1], 64).T[:, : od.num_obs]
         assert (got == o["pred_obs"]).all()
 
@@ -152,7 +160,8 @@ def test_decoder_launch_shape_invariance(gpu_lib, name, spec, shots):
     c.sample(5, 0, 0, shots, det, obs)
     ref = None
     for kw in (dict(), dict(bp_threads=64, bp_per_cu=2, osd_per_cu=1),
-               dict(bp_threads=256, bp_per_cu=16, osd_per_cu=8), dict(bp_threads=1024, osd_per_cu=3)):
+               dict(bp_threads=256, bp_per_cu=16, osd_per_cu=8), dict(bp_threads=1024, osd_per_cu=3),
+               dict(bp_global_state=1), dict(bp_global_state=1, bp_threads=128, bp_per_cu=3)):
         for full in (True, False):
             pred = torch.zeros_like(obs)
             ehat = torch.zeros((shots, dem.cols), dtype=torch.uint8, device="cuda") if full else None

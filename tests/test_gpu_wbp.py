@@ -4,7 +4,7 @@ import pytest
 
 from oracle.circuits import build_circuit
 from oracle.dem import build_dem
-from oracle.frame import unpack_bits
+from oracle.frame import pack_bits, sample as oracle_sample, unpack_bits
 from oracle.wbp import backward as oracle_backward
 from oracle.wbp import forward as oracle_forward
 from workloads import NLCNOT, bb, sc
@@ -16,8 +16,9 @@ def _setup(gpu_lib, spec, shots, T, seed=4):
     import torch
     c = gpu_lib.Circuit(spec)
     dem = gpu_lib.DEM(c)
-    det, obs = c.alloc_outputs(shots)
-    c.sample(seed, 0, 0, shots, det, obs)
+    d, o = oracle_sample(build_circuit(spec), seed, 0, 0, shots)     # inputs from the oracle's sampler
+    det = torch.from_numpy(pack_bits(d).view(np.int64)).cuda()
+    obs = torch.from_numpy(pack_bits(o).view(np.int64)).cuda()
     rng = np.random.default_rng(seed)
     w = rng.uniform(0.6, 1.4, size=(T, dem.edges)).astype(np.float32)
     wt = torch.from_numpy(w).cuda()
