@@ -36,11 +36,11 @@ FRAME_OPS_PER_CX_WORD = 4      # two 64-bit XORs per CX per 64-shot word
 TRAFFIC = {
     "sc5_nlcnot": {
         "k_bp": {"src": "paper_2504_05611_amd/csrc/kernels/decode.hip",
-                 "sha256": "2c12f2c22a378aba40978f4cf50a3e9a15b894315df168e2b12f8bd125e1b3de",
-                 "fetch_kib": 14850.6, "write_kib": 27062.5},
+                 "sha256": "62512bd0277d9268ad3b57259b19850d05cb605e965a0c6d137a74361fb3a218",
+                 "fetch_kib": 14825.3, "write_kib": 27062.8},
         "k_frame": {"src": "paper_2504_05611_amd/csrc/kernels/sample.hip",
-                    "sha256": "06e7ff6878bc7c6c7893c53fbdb252ee01427c5b9956d8d578b7295f5e34c8d0",
-                    "fetch_kib": 20892.5, "write_kib": 38552.6},
+                    "sha256": "aac13a06933cea5d844bbee436525c35d3f385c1dc3acc17043a360968da0597",
+                    "fetch_kib": 61133.1, "write_kib": 38549.8},
     },
 }
 FETCH_SCALE = 1048576.0 / 524302.5   # copy-kernel calibration (1 GiB read per launch)
