@@ -975,10 +975,11 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   if (cfg.bp_threads > 0) {
     P = cfg.bp_threads;
   } else {
-    // about 8 waves per CU, but no lane should carry much more than its share of edges
-    int G = gstate ? 8 : std::max(1, std::min(16, (8 + team_fit - 1) / team_fit));
+    // about 24 waves per CU (the passes are latency-bound: more waves, more
+    // overlap), but no lane should carry much more than its share of edges
+    int G = gstate ? 8 : std::max(1, std::min(16, (24 + team_fit - 1) / team_fit));
     P = 64 * G;
-    const int64_t cap = std::max<int64_t>(64, (3 * D.edges / std::max(2 * d->max_row_deg, 1)) / 64 * 64);
+    const int64_t cap = std::max<int64_t>(64, (2 * D.edges / std::max(d->max_row_deg, 1)) / 64 * 64);
     while (P > 64 && P > cap) P -= 64;
   }
   P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
@@ -1125,7 +1126,7 @@ tmcs_status autotune_run(const Dem& D, const uint64_t* det, uint64_t n_shots, tm
   base.ehat_dev = nullptr; base.llr_dev = nullptr; base.iters_dev = nullptr; base.flags_dev = nullptr;
   tmcs_decoder_cfg best = base;
   float best_ms = 1e30f;
-  const int threads[] = {64, 128, 256, 512};
+  const int threads[] = {64, 128, 256, 512, 1024};
   const int bp_cu[] = {0, 4};
   const int osd_cu[] = {2, 4, 8};
   tmcs_status st = TMCS_OK;

@@ -51,7 +51,7 @@ def test_autotune_keeps_results(gpu_lib):
     det, obs = c.alloc_outputs(n)
     c.sample(1, 0, 0, n, det, obs)
     cfg = gpu_lib.autotune(dem, det, n, gpu_lib.make_cfg(max_iter=30))
-    assert cfg.bp_threads in (64, 128, 256, 512) and cfg.osd_per_cu in (2, 4, 8)
+    assert cfg.bp_threads in (64, 128, 256, 512, 1024) and cfg.osd_per_cu in (2, 4, 8)
     p1 = torch.zeros_like(obs)
     p2 = torch.zeros_like(obs)
     dem.decode(det, n, p1, max_iter=30)
