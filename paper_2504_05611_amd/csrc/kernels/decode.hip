@@ -399,7 +399,8 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t x, int src) {
 // compared in registers, partners within a wave via lane shuffles, and only the
 // strides that cross waves go through LDS (`keys`), which also receives the
 // sorted result.
-template <int KPT>
+// IDX32: store only the low 32 bits (the column index) of the sorted keys.
+template <int KPT, bool IDX32 = false>
 __device__ __forceinline__ void bitonic_sort_regs(uint64_t (&x)[KPT], uint64_t* keys, int npad) {
   const int tid = threadIdx.x;
   for (int k = 2; k <= npad; k <<= 1) {
@@ -449,7 +450,10 @@ __device__ __forceinline__ void bitonic_sort_regs(uint64_t (&x)[KPT], uint64_t* 
   }
   __syncthreads();
 #pragma unroll
-  for (int r = 0; r < KPT; ++r) keys[tid * KPT + r] = x[r];
+  for (int r = 0; r < KPT; ++r) {
+    if (IDX32) ((uint32_t*)keys)[tid * KPT + r] = (uint32_t)x[r];
+    else keys[tid * KPT + r] = x[r];
+  }
   __syncthreads();
 }
 
@@ -477,13 +481,15 @@ template <int MW, int RW, int KPT, bool BL, int NT>
 __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
   constexpr int W = MW + RW;
   extern __shared__ __align__(8) unsigned char sm[];
-  uint64_t* keys = (uint64_t*)sm;                                  // [npad]
-  uint64_t* lbasis = keys + a.npad;                                // BL: [rank][W]
+  uint64_t* keys = (uint64_t*)sm;                                  // [npad] (BL: u32 column indices)
+  uint64_t* lbasis = BL ? (uint64_t*)((uint32_t*)sm + a.npad) : keys + a.npad;   // BL: [rank][W]
   int32_t* pivot = (int32_t*)(BL ? lbasis + (size_t)a.rank * W : keys + a.npad);   // [rank] pivot row of basis i
   int32_t* kept = pivot + a.rank;                                  // [rank] column of basis i
   int32_t* prow = kept + a.rank;                                   // [m] basis index of a pivot row, or -1
   int32_t* srow = prow + a.m;                                      // [m] rows with a syndrome bit
-  uint64_t* acc = (uint64_t*)(((uintptr_t)(srow + a.m) + 7) & ~(uintptr_t)7);  // [W] solve accumulator
+  // (an offset from sm, not an integer cast, so that the compiler keeps LDS addressing)
+  const size_t acc_off = ((size_t)((unsigned char*)(srow + a.m) - sm) + 7) & ~(size_t)7;
+  uint64_t* acc = (uint64_t*)(sm + acc_off);                       // [W] solve accumulator
   __shared__ int s_job, s_r, s_ns;
   __shared__ uint64_t s_red;
   const int tid = threadIdx.x;
@@ -540,7 +546,7 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
         const int i = tid * KPT + r;
         x[r] = i < a.n ? (((uint64_t)order_key(L[i]) << 32) | (uint32_t)i) : ~0ull;
       }
-      bitonic_sort_regs<KPT>(x, keys, a.npad);
+      bitonic_sort_regs<KPT, BL>(x, keys, a.npad);
     }
     // 2. information set, 256 sorted candidates per pass (one per thread)
     for (int base = 0; base < a.n; base += NT) {
@@ -548,7 +554,7 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
       __syncthreads();           // every wave has read s_r before wave 0 advances it
       if (r_start >= a.rank) break;
       const int idx = base + tid;
-      const int col = idx < a.n ? (int)(keys[idx] & 0xFFFFFFFFu) : -1;
+      const int col = idx < a.n ? (BL ? (int)((const uint32_t*)keys)[idx] : (int)(keys[idx] & 0xFFFFFFFFu)) : -1;
       uint64_t v[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) v[w] = 0ull;
@@ -997,10 +1003,11 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int W = 2 * (mw <= 1 ? 1 : mw <= 2 ? 2 : mw <= 4 ? 4 : mw <= 5 ? 5 : mw <= 8 ? 8 : mw <= 12 ? 12
                    : mw <= 15 ? 15 : mw <= 18 ? 18 : mw <= 24 ? 24 : 32);
   size_t osd_lds = (size_t)npad * 8 + (size_t)D.rank * 8 + (size_t)D.rows * 8 + (size_t)W * 8 + 64;
-  // small DEMs keep the elimination basis in LDS as well (at least two workgroups per CU)
+  // small DEMs keep the elimination basis in LDS as well (at least two workgroups
+  // per CU); their sorted keys are stored as 32-bit column indices
   const size_t basis_bytes = (size_t)std::max(D.rank, 1) * W * 8;
-  const bool osd_bl = osd_lds_basis_ok(mw, npad) && osd_lds + basis_bytes <= 80 * 1024;
-  if (osd_bl) osd_lds += basis_bytes;
+  const bool osd_bl = osd_lds_basis_ok(mw, npad) && osd_lds - (size_t)npad * 4 + basis_bytes <= 80 * 1024;
+  if (osd_bl) osd_lds += basis_bytes - (size_t)npad * 4;
   const int osd_fit = std::max<int>(1, (int)((160 * 1024) / (osd_lds + 512)));
   const int osd_per_cu = std::min(osd_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : (osd_bl ? 16 : 4));
   const int osd_grid = std::max(1, cus * osd_per_cu);
