@@ -152,11 +152,19 @@ typedef struct {
   int32_t osd_per_cu;       /* resident OSD workgroups per compute unit */
   int32_t bp_global_state;  /* 1: keep each shot's BP state in device memory instead of LDS
                                (automatic when it exceeds the 160 KB LDS of a compute unit) */
+  int32_t osd_window;       /* 0: dense OSD-0 when H fits (<= 2048 detectors, <= 16384 columns),
+                               windowed otherwise; 1..2048: always windowed, with at most this
+                               many detectors in a window.  A window holds the first sorted
+                               columns (at most 2047) and the detectors they touch; when the
+                               syndrome is spanned inside it the result equals the dense OSD-0
+                               exactly, otherwise the shot keeps BP's hard decision and is
+                               counted in osd_incomplete (flags bit 3) */
   /* optional per-shot outputs (NULL to skip), each indexed by shot of the call: */
   uint8_t* ehat_dev;        /* [n_shots][cols] final correction (0/1 bytes) */
   float* llr_dev;           /* [n_shots][cols] final BP posterior LLRs */
   int32_t* iters_dev;       /* [n_shots] BP iterations (0 for an all-zero syndrome) */
-  uint8_t* flags_dev;       /* [n_shots] bit0 converged, bit1 OSD ran, bit2 OSD not in span */
+  uint8_t* flags_dev;       /* [n_shots] bit0 converged, bit1 OSD ran, bit2 OSD not in span,
+                               bit3 OSD window exhausted (BP's decision kept) */
 } tmcs_decoder_cfg;
 
 /* Decode statistics, accumulated on the device (caller zeroes them). */
@@ -167,7 +175,8 @@ typedef struct {
   uint64_t osd;          /* shots sent to OSD-0 */
   uint64_t not_in_span;  /* OSD shots whose syndrome was not in H's column space */
   uint64_t bp_iters;     /* sum of BP iterations */
-  uint64_t reserved[2];
+  uint64_t osd_incomplete; /* windowed OSD shots whose syndrome was not spanned inside the window */
+  uint64_t reserved;
 } tmcs_decode_stats;
 
 /* Decode det_dev ([rows][ceil(n/64)], as written by tmcs_sample) and write the

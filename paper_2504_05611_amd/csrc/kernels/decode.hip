@@ -42,6 +42,10 @@ namespace {
 constexpr float BP_BIG = 1e30f;
 constexpr int OSD_THREADS = 256;
 constexpr int OSD_MAX_KEYS = 16384;
+// windowed OSD-0: window length (sorted columns, power of two) and local rows
+constexpr int WIN_KEYS = 2048;
+constexpr int WIN_MW = 32;
+constexpr int WIN_MAX_ROWS = 64 * WIN_MW;
 
 struct DecodeDevice {
   int device = -1;
@@ -63,7 +67,8 @@ struct DecodeDevice {
   uint64_t* basis = nullptr;
   uint64_t* synd = nullptr;
   unsigned char* gstate = nullptr;  // BP state in device memory, one slab per team
-  size_t cap_queue = 0, cap_osd = 0, cap_llr = 0, cap_basis = 0, cap_synd = 0, cap_gstate = 0;
+  int32_t* rowmap = nullptr;        // windowed OSD: [grid][2][m] row tables (WIN_NONE between shots)
+  size_t cap_queue = 0, cap_osd = 0, cap_llr = 0, cap_basis = 0, cap_synd = 0, cap_gstate = 0, cap_rowmap = 0;
 };
 
 // Per-lane schedule records of the BP passes (int4 = {x, y, z, w}).
@@ -139,6 +144,10 @@ __global__ void k_add_shots(tmcs_decode_stats* stats, unsigned long long n) {
 __global__ void k_zero_i32(int32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
 // Detector-major bit planes -> shot-major syndrome words for the chunk
@@ -378,8 +387,29 @@ struct OSDArgs {
   tmcs_decode_stats* stats;
   uint8_t* ehat;
   uint8_t* flags;
-  int32_t npad;              // sort length (power of two >= n)
+  int32_t npad;              // sort length (power of two >= n; WIN: window length)
+  int32_t* rowmap;           // WIN: [grid][2][m] first window position touching a row, local row index
+  int32_t win_rows;          // WIN: most local rows a window may hold (<= 64 * MW)
 };
+
+constexpr int32_t WIN_NONE = 0x7FFFFFFF;   // rowmap: row not touched by the window
+
+// Coherent (L2) 32-bit load: rowmap entries are updated with atomics and by
+// other waves of the workgroup within one shot.
+__device__ __forceinline__ int32_t ld_l2(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
 
 __device__ __forceinline__ uint32_t order_key(float x) {
   if (x == 0.0f) x = 0.0f;   // -0 and +0 compare equal
@@ -477,24 +507,43 @@ __device__ __forceinline__ uint64_t bit_of(const uint64_t (&v)[W], int p) {
 // among themselves, and the older vectors are then reduced against them.
 // BL: the basis lives in LDS (after the sort keys) instead of HBM.
 // NT: threads per workgroup (64: one wave decodes a shot on its own).
-template <int MW, int RW, int KPT, bool BL, int NT>
+//
+// WIN (DEMs beyond the dense limits): the scan that ends at the early stop only
+// ever looks at a prefix of the sorted order, and those columns touch few rows.
+// The shot therefore works on a window: the npad - 1 smallest keys at most
+// (radix selection, then a sort), cut where the rows they touch would exceed
+// win_rows, with those rows renumbered 0, 1, ... in order of first touch.  Kept
+// columns are zero outside the window's rows, so independence tests, the early
+// stop and the solution are exactly those of the full OSD-0 whenever s is
+// spanned inside the window.  Otherwise (window too small) the shot keeps BP's
+// hard decision and is flagged (flags bit 3, stats osd_incomplete).
+template <int MW, int RW, int KPT, bool BL, int NT, bool WIN = false>
 __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
   constexpr int W = MW + RW;
+  static_assert(!(WIN && BL), "the window variant keeps its basis in HBM");
   extern __shared__ __align__(8) unsigned char sm[];
-  uint64_t* keys = (uint64_t*)sm;                                  // [npad] (BL: u32 column indices)
+  // local capacity: rank and rows of the problem the elimination sees
+  const int cap_r = WIN ? 64 * MW : a.rank;
+  const int cap_m = WIN ? 64 * MW : a.m;
+  uint64_t* keys = (uint64_t*)sm;                                  // [npad] (BL, WIN: u32 column indices)
   uint64_t* lbasis = BL ? (uint64_t*)((uint32_t*)sm + a.npad) : keys + a.npad;   // BL: [rank][W]
   int32_t* pivot = (int32_t*)(BL ? lbasis + (size_t)a.rank * W : keys + a.npad);   // [rank] pivot row of basis i
-  int32_t* kept = pivot + a.rank;                                  // [rank] column of basis i
-  int32_t* prow = kept + a.rank;                                   // [m] basis index of a pivot row, or -1
-  int32_t* srow = prow + a.m;                                      // [m] rows with a syndrome bit
+  int32_t* kept = pivot + cap_r;                                   // [rank] column of basis i
+  int32_t* prow = kept + cap_r;                                    // [m] basis index of a pivot row, or -1
+  int32_t* srow = prow + cap_m;                                    // [m] rows with a syndrome bit
   // (an offset from sm, not an integer cast, so that the compiler keeps LDS addressing)
-  const size_t acc_off = ((size_t)((unsigned char*)(srow + a.m) - sm) + 7) & ~(size_t)7;
+  const size_t acc_off = ((size_t)((unsigned char*)(srow + cap_m) - sm) + 7) & ~(size_t)7;
   uint64_t* acc = (uint64_t*)(sm + acc_off);                       // [W] solve accumulator
-  __shared__ int s_job, s_r, s_ns;
+  // WIN: after the sort, keys holds npad u32 column indices followed by npad
+  // per-position counts (then exclusive offsets) of newly touched rows
+  int32_t* pcnt = (int32_t*)keys + a.npad;
+  __shared__ int s_job, s_r, s_ns, s_inc;
   __shared__ uint64_t s_red;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  uint64_t* B = BL ? lbasis : a.basis + (int64_t)blockIdx.x * a.rank * W;
+  uint64_t* B = BL ? lbasis : a.basis + (int64_t)blockIdx.x * cap_r * W;
+  int32_t* fpos = WIN ? a.rowmap + (int64_t)blockIdx.x * 2 * a.m : nullptr;   // [m] first window position
+  int32_t* lmap = WIN ? fpos + a.m : nullptr;                                  // [m] local row index
   // acc = s + sum of the basis vectors pivoted on rows of s.  With a fully
   // reduced basis this is zero on every pivot row; its syndrome part is zero iff
   // s lies in the span of the kept columns, and its combination part then names
@@ -528,18 +577,19 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
     const int64_t ls = a.osd_queue[job];
     const int64_t shot = a.shot0 + ls;
     const float* L = a.osd_llr + (int64_t)job * a.n;
-    // 1. sort columns by (L_v, v); list the syndrome's rows
-    if (tid == 0) { s_r = 0; s_ns = 0; }
+    int n_loc = a.n, rank_loc = a.rank, n0 = a.n;
+    if (tid == 0) { s_r = 0; s_ns = 0; s_inc = 0; }
     __syncthreads();
-    for (int r = tid; r < a.m; r += NT) prow[r] = -1;
-    for (int wd = tid; wd < a.mw; wd += NT) {
-      uint64_t x = a.synd[ls * a.mw + wd];
-      if (x) {
-        const int base = atomicAdd(&s_ns, __popcll(x));
-        for (int k = 0; x; ++k, x &= x - 1) srow[base + k] = wd * 64 + (__ffsll((unsigned long long)x) - 1);
+    if constexpr (!WIN) {
+      // 1. sort columns by (L_v, v); list the syndrome's rows
+      for (int r = tid; r < a.m; r += NT) prow[r] = -1;
+      for (int wd = tid; wd < a.mw; wd += NT) {
+        uint64_t x = a.synd[ls * a.mw + wd];
+        if (x) {
+          const int base = atomicAdd(&s_ns, __popcll(x));
+          for (int k = 0; x; ++k, x &= x - 1) srow[base + k] = wd * 64 + (__ffsll((unsigned long long)x) - 1);
+        }
       }
-    }
-    {
       uint64_t x[KPT];
 #pragma unroll
       for (int r = 0; r < KPT; ++r) {
@@ -547,28 +597,157 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
         x[r] = i < a.n ? (((uint64_t)order_key(L[i]) << 32) | (uint32_t)i) : ~0ull;
       }
       bitonic_sort_regs<KPT, BL>(x, keys, a.npad);
+    } else {
+      __shared__ int s_hist[256];
+      __shared__ int s_wsum[NT / 64];
+      __shared__ int s_sel, s_want, s_cnt, s_cut, s_total;
+      if (tid == 0) s_cnt = 0;
+      __syncthreads();
+      // 1a. the window: every key below the npad-th smallest 32-bit order key
+      // (radix selection, 8 bits per pass), so at most npad - 1 columns, and all
+      // of them when n < npad
+      uint32_t kstar = 0xFFFFFFFFu;
+      bool all = a.n < a.npad;
+      if (!all) {
+        uint32_t pre = 0u;
+        int want = a.npad - 1;
+        for (int pass = 0; pass < 4; ++pass) {
+          const int sh = 24 - 8 * pass;
+          const uint32_t hmask = pass == 0 ? 0u : (0xFFFFFFFFu << (sh + 8));
+          for (int i = tid; i < 256; i += NT) s_hist[i] = 0;
+          __syncthreads();
+          for (int v = tid; v < a.n; v += NT) {
+            const uint32_t k = order_key(L[v]);
+            if ((k & hmask) == (pre & hmask)) atomicAdd(&s_hist[(k >> sh) & 255u], 1);
+          }
+          __syncthreads();
+          if (wave == 0) {
+            int c[4], t = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { c[q] = s_hist[lane * 4 + q]; t += c[q]; }
+            const int incl = wave_incl_scan(t);
+            int e = incl - t;
+            if (e <= want && want < incl) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                if (e <= want && want < e + c[q]) { s_sel = lane * 4 + q; s_want = want - e; }
+                e += c[q];
+              }
+            }
+          }
+          __syncthreads();
+          pre |= (uint32_t)s_sel << sh;
+          want = s_want;
+          __syncthreads();
+        }
+        kstar = pre;
+      }
+      // 1b. gather and sort the window's keys
+      for (int v = tid; v < a.n; v += NT) {
+        const uint32_t k = order_key(L[v]);
+        if (all || k < kstar) keys[atomicAdd(&s_cnt, 1)] = ((uint64_t)k << 32) | (uint32_t)v;
+      }
+      __syncthreads();
+      n0 = s_cnt;
+      uint64_t x[KPT];
+#pragma unroll
+      for (int r = 0; r < KPT; ++r) {
+        const int i = tid * KPT + r;
+        x[r] = i < n0 ? keys[i] : ~0ull;
+      }
+      bitonic_sort_regs<KPT, true>(x, keys, a.npad);
+      const uint32_t* col32 = (const uint32_t*)keys;
+      // 1c. first window position touching each row
+      for (int j = tid; j < n0; j += NT) {
+        const int col = (int)col32[j];
+        for (int32_t k = a.col_ptr[col]; k < a.col_ptr[col + 1]; ++k) atomicMin(&fpos[a.csc_row[k]], j);
+      }
+      if (tid == 0) s_cut = n0;
+      __syncthreads();
+      // 1d. rows first touched at each position, exclusive offsets, and the cut:
+      // the first position whose new rows would exceed win_rows
+      int cnt[KPT], tsum = 0;
+#pragma unroll
+      for (int r = 0; r < KPT; ++r) {
+        const int j = tid * KPT + r;
+        cnt[r] = 0;
+        if (j < n0) {
+          const int col = (int)col32[j];
+          for (int32_t k = a.col_ptr[col]; k < a.col_ptr[col + 1]; ++k) cnt[r] += ld_l2(&fpos[a.csc_row[k]]) == j;
+        }
+        tsum += cnt[r];
+      }
+      const int wincl = wave_incl_scan(tsum);
+      if (lane == 63) s_wsum[wave] = wincl;
+      __syncthreads();
+      int off = wincl - tsum;
+      for (int q = 0; q < wave; ++q) off += s_wsum[q];
+      if (tid == NT - 1) s_total = off + tsum;
+#pragma unroll
+      for (int r = 0; r < KPT; ++r) {
+        const int j = tid * KPT + r;
+        if (j < n0) {
+          pcnt[j] = off;
+          if (off + cnt[r] > a.win_rows) atomicMin(&s_cut, j);
+        }
+        off += cnt[r];
+      }
+      __syncthreads();
+      n_loc = s_cut;
+      rank_loc = n_loc < n0 ? pcnt[n_loc] : s_total;      // rows of the window = bound on its rank
+      // 1e. local row numbers, in order of first touch
+      for (int j = tid; j < n_loc; j += NT) {
+        const int col = (int)col32[j];
+        int t = pcnt[j];
+        for (int32_t k = a.col_ptr[col]; k < a.col_ptr[col + 1]; ++k) {
+          const int r = a.csc_row[k];
+          if (ld_l2(&fpos[r]) == j) __hip_atomic_store(&lmap[r], t++, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      for (int r = tid; r < rank_loc; r += NT) prow[r] = -1;
+      __syncthreads();
+      // 1f. the syndrome in local rows; a detection event outside the window
+      // cannot be spanned by it
+      for (int wd = tid; wd < a.mw; wd += NT) {
+        uint64_t x = a.synd[ls * a.mw + wd];
+        for (; x; x &= x - 1) {
+          const int r = wd * 64 + (__ffsll((unsigned long long)x) - 1);
+          if (ld_l2(&fpos[r]) >= n_loc) s_inc = 1;
+          else srow[atomicAdd(&s_ns, 1)] = ld_l2(&lmap[r]);
+        }
+      }
+      __syncthreads();
     }
+    // WIN: every column of H is in the window, so the result is the full OSD-0's
+    const bool whole = !WIN || n_loc == a.n;
+    const bool skip = WIN && !whole && s_inc;
+    // rows of the elimination: H's, or the window's local numbers
+    auto row_of = [&](int32_t k) -> int {
+      const int r = a.csc_row[k];
+      if constexpr (WIN) return ld_l2(&lmap[r]);
+      else return r;
+    };
     // 2. information set, 256 sorted candidates per pass (one per thread)
-    for (int base = 0; base < a.n; base += NT) {
+    for (int base = 0; base < (skip ? 0 : n_loc); base += NT) {
       const int r_start = s_r;
       __syncthreads();           // every wave has read s_r before wave 0 advances it
-      if (r_start >= a.rank) break;
+      if (r_start >= rank_loc) break;
       const int idx = base + tid;
-      const int col = idx < a.n ? (BL ? (int)((const uint32_t*)keys)[idx] : (int)(keys[idx] & 0xFFFFFFFFu)) : -1;
+      const int col = idx < n_loc ? ((BL || WIN) ? (int)((const uint32_t*)keys)[idx] : (int)(keys[idx] & 0xFFFFFFFFu)) : -1;
       uint64_t v[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) v[w] = 0ull;
       if (col >= 0) {
         const int32_t k0 = a.col_ptr[col], k1 = a.col_ptr[col + 1];
         for (int32_t k = k0; k < k1; ++k) {
-          const int r = a.csc_row[k];
+          const int r = row_of(k);
 #pragma unroll
           for (int w = 0; w < MW; ++w)
             if ((r >> 6) == w) v[w] ^= 1ull << (r & 63);
         }
         // phase 1: the basis vectors pivoted on rows of h
         for (int32_t k = k0; k < k1; ++k) {
-          const int i = prow[a.csc_row[k]];
+          const int i = prow[row_of(k)];
           if (i >= 0) {
             const uint64_t* b = B + (int64_t)i * W;
 #pragma unroll
@@ -591,7 +770,7 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
             return o != 0ull && col >= 0;
           };
           uint64_t live = __ballot(nz());
-          while (live && r < a.rank) {
+          while (live && r < rank_loc) {
             const int j = __ffsll((unsigned long long)live) - 1;
             uint64_t b[W];
 #pragma unroll
@@ -685,23 +864,45 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
     }
     // 3. solve: s reduced by the basis vectors pivoted on rows of s
     const int r = s_r;
-    const int not_in_span = reduce_syndrome();
+    const int unspanned = skip ? 1 : reduce_syndrome();
+    // WIN: a window that does not span s says nothing about H unless it is all of H
+    const bool incomplete = unspanned && !whole;
+    const int not_in_span = unspanned && whole;
     uint64_t pm = 0;
-    if (a.ehat)
-      for (int v = tid; v < a.n; v += NT) a.ehat[shot * a.n + v] = 0;
-    __syncthreads();
-    for (int i = tid; i < r; i += NT) {
-      if ((acc[MW + (i >> 6)] >> (i & 63)) & 1ull) {
-        const int col = kept[i];
-        pm ^= a.obs_mask[col];
-        if (a.ehat) a.ehat[shot * a.n + col] = 1;
+    if (incomplete) {
+      // BP's hard decision stands
+      for (int v = tid; v < a.n; v += NT) {
+        const bool e = L[v] < 0.0f;
+        if (e) pm ^= a.obs_mask[v];
+        if (a.ehat) a.ehat[shot * a.n + v] = e ? 1 : 0;
+      }
+    } else {
+      if (a.ehat)
+        for (int v = tid; v < a.n; v += NT) a.ehat[shot * a.n + v] = 0;
+      __syncthreads();
+      for (int i = tid; i < r; i += NT) {
+        if ((acc[MW + (i >> 6)] >> (i & 63)) & 1ull) {
+          const int col = kept[i];
+          pm ^= a.obs_mask[col];
+          if (a.ehat) a.ehat[shot * a.n + col] = 1;
+        }
       }
     }
     pm = block_xor_u64(pm, &s_red);
     if (tid == 0) {
       write_pred(a.pred, a.stride, a.nobs, shot, pm);
-      if (a.flags) a.flags[shot] = (uint8_t)(2 | (not_in_span ? 4 : 0));
+      if (a.flags) a.flags[shot] = (uint8_t)(2 | (not_in_span ? 4 : 0) | (incomplete ? 8 : 0));
       if (a.stats && not_in_span) atomicAdd((unsigned long long*)&a.stats->not_in_span, 1ull);
+      if (a.stats && incomplete) atomicAdd((unsigned long long*)&a.stats->osd_incomplete, 1ull);
+    }
+    if constexpr (WIN) {
+      // leave the row table untouched for the next shot
+      const uint32_t* col32 = (const uint32_t*)keys;
+      for (int j = tid; j < n0; j += NT) {
+        const int col = (int)col32[j];
+        for (int32_t k = a.col_ptr[col]; k < a.col_ptr[col + 1]; ++k)
+          __hip_atomic_store(&fpos[a.csc_row[k]], WIN_NONE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     __syncthreads();
   }
@@ -731,6 +932,7 @@ void free_device(DecodeDevice* d) {
   hipFree(d->row_ptr); hipFree(d->col_idx); hipFree(d->col_ptr); hipFree(d->csc_row); hipFree(d->csc_edge);
   hipFree(d->lam); hipFree(d->obs_mask); hipFree(d->counters); hipFree(d->queue); hipFree(d->osd_queue);
   hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd); hipFree(d->gstate); hipFree(d->init); hipFree(d->sign0);
+  hipFree(d->rowmap);
   for (auto& q : d->scheds) { hipFree(q.c); hipFree(q.v); }
   *d = DecodeDevice();
 }
@@ -928,6 +1130,14 @@ tmcs_status dispatch_kpt_lds(int kpt, const OSDArgs& a, int grid, size_t lds, hi
 
 bool osd_lds_basis_ok(int mw, int npad) { return mw <= 8 && npad <= 4096; }
 
+tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
+  auto k = k_osd<WIN_MW, WIN_MW, WIN_KEYS / OSD_THREADS, false, OSD_THREADS, true>;
+  if (lds > 64 * 1024 && hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return fail(TMCS_EUNSUPPORTED, "OSD workspace does not fit in LDS");
+  TMCS_LAUNCH("k_osd", k, dim3(grid), dim3(OSD_THREADS), lds, s, a);
+  return hip_check(hipGetLastError(), "k_osd launch");
+}
+
 tmcs_status dispatch_osd(int mw, int kpt, bool bl, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
   if (bl) {
     if (mw <= 1) return dispatch_kpt_lds<1>(kpt, a, grid, lds, s);
@@ -968,8 +1178,10 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int mw = (D.rows + 63) / 64;
   int npad = OSD_THREADS;   // sort length: a power of two, at least one key per thread
   while (npad < D.cols) npad <<= 1;
-  if (cfg.use_osd && (npad > OSD_MAX_KEYS || mw > 32))
-    return fail(TMCS_EUNSUPPORTED, "OSD-0 supports up to 16384 columns and 2048 detectors in this build");
+  if (cfg.osd_window < 0 || cfg.osd_window > WIN_MAX_ROWS)
+    return fail(TMCS_EINVAL, "osd_window must be in [0, 2048]");
+  // dense OSD-0 while H fits its registers and sort, windowed beyond (or on request)
+  const bool osd_win = cfg.use_osd && (cfg.osd_window > 0 || npad > OSD_MAX_KEYS || mw > 32);
   const int cus = device_cus();
   // BP launch shape: one team (workgroup) per shot in flight, state in LDS
   const size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (size_t)d->E4 + 4;
@@ -1000,13 +1212,18 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int64_t chunk = std::min<int64_t>((int64_t)n_shots,
                                           std::max<int64_t>(DECODE_CHUNK_MIN, ((1ll << 28) / std::max(D.cols, 1)) & ~63ll));
   // OSD launch shape
-  const int W = 2 * (mw <= 1 ? 1 : mw <= 2 ? 2 : mw <= 4 ? 4 : mw <= 5 ? 5 : mw <= 8 ? 8 : mw <= 12 ? 12
-                   : mw <= 15 ? 15 : mw <= 18 ? 18 : mw <= 24 ? 24 : 32);
-  size_t osd_lds = (size_t)npad * 8 + (size_t)D.rank * 8 + (size_t)D.rows * 8 + (size_t)W * 8 + 64;
+  const int W = osd_win ? 2 * WIN_MW
+                        : 2 * (mw <= 1 ? 1 : mw <= 2 ? 2 : mw <= 4 ? 4 : mw <= 5 ? 5 : mw <= 8 ? 8 : mw <= 12 ? 12
+                               : mw <= 15 ? 15 : mw <= 18 ? 18 : mw <= 24 ? 24 : 32);
+  // rank and rows the elimination works with: H's, or a window's
+  const int osd_rank = osd_win ? WIN_MAX_ROWS : D.rank;
+  const int osd_rows = osd_win ? WIN_MAX_ROWS : D.rows;
+  if (osd_win) npad = WIN_KEYS;
+  size_t osd_lds = (size_t)npad * 8 + (size_t)osd_rank * 8 + (size_t)osd_rows * 8 + (size_t)W * 8 + 64;
   // small DEMs keep the elimination basis in LDS as well (at least two workgroups
   // per CU); their sorted keys are stored as 32-bit column indices
-  const size_t basis_bytes = (size_t)std::max(D.rank, 1) * W * 8;
-  const bool osd_bl = osd_lds_basis_ok(mw, npad) && osd_lds - (size_t)npad * 4 + basis_bytes <= 80 * 1024;
+  const size_t basis_bytes = (size_t)std::max(osd_rank, 1) * W * 8;
+  const bool osd_bl = !osd_win && osd_lds_basis_ok(mw, npad) && osd_lds - (size_t)npad * 4 + basis_bytes <= 80 * 1024;
   if (osd_bl) osd_lds += basis_bytes - (size_t)npad * 4;
   const int osd_fit = std::max<int>(1, (int)((160 * 1024) / (osd_lds + 512)));
   const int osd_per_cu = std::min(osd_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : (osd_bl ? 16 : 4));
@@ -1017,8 +1234,19 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   if (cfg.use_osd) {
     if ((st = grow(&d->osd_queue, &d->cap_osd, (size_t)chunk)) != TMCS_OK ||
         (st = grow(&d->osd_llr, &d->cap_llr, (size_t)chunk * (size_t)D.cols)) != TMCS_OK ||
-        (!osd_bl && (st = grow(&d->basis, &d->cap_basis, (size_t)osd_grid * (size_t)std::max(D.rank, 1) * W)) != TMCS_OK))
+        (!osd_bl && (st = grow(&d->basis, &d->cap_basis, (size_t)osd_grid * (size_t)std::max(osd_rank, 1) * W)) != TMCS_OK))
       return st;
+    if (osd_win) {
+      const size_t n_map = (size_t)osd_grid * 2 * (size_t)std::max(D.rows, 1);
+      const int32_t* before = d->rowmap;
+      const size_t cap_before = d->cap_rowmap;
+      if ((st = grow(&d->rowmap, &d->cap_rowmap, n_map)) != TMCS_OK) return st;
+      if (d->rowmap != before || d->cap_rowmap != cap_before) {
+        const int64_t g = std::min<int64_t>(((int64_t)d->cap_rowmap + 255) / 256, 4096);
+        TMCS_LAUNCH("k_fill_i32", k_fill_i32, dim3((unsigned)g), dim3(256), 0, stream, d->rowmap,
+                    (int64_t)d->cap_rowmap, WIN_NONE);
+      }
+    }
   }
   const int64_t total_words = (int64_t)D.nobs * stride;
   if (total_words) {
@@ -1067,7 +1295,10 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
       o.counters = d->counters; o.osd_queue = d->osd_queue; o.osd_llr = d->osd_llr; o.basis = d->basis;
       o.pred = pred; o.nobs = D.nobs; o.stats = stats; o.ehat = cfg.ehat_dev; o.flags = cfg.flags_dev;
       o.npad = npad;
-      if ((st = dispatch_osd(mw, npad / (osd_bl ? 64 : OSD_THREADS), osd_bl, o, osd_grid, osd_lds, stream)) != TMCS_OK) return st;
+      o.rowmap = d->rowmap; o.win_rows = cfg.osd_window > 0 ? cfg.osd_window : WIN_MAX_ROWS;
+      if (osd_win) st = launch_osd_win(o, osd_grid, osd_lds, stream);
+      else st = dispatch_osd(mw, npad / (osd_bl ? 64 : OSD_THREADS), osd_bl, o, osd_grid, osd_lds, stream);
+      if (st != TMCS_OK) return st;
     }
   }
   return TMCS_OK;

@@ -50,7 +50,7 @@ class DecoderCfg(ctypes.Structure):
                 ("weights_dev", ctypes.c_void_p), ("use_osd", ctypes.c_int32),
                 ("bp_threads", ctypes.c_int32), ("bp_per_cu", ctypes.c_int32),
                 ("osd_per_cu", ctypes.c_int32), ("bp_global_state", ctypes.c_int32),
-                ("ehat_dev", ctypes.c_void_p),
+                ("osd_window", ctypes.c_int32), ("ehat_dev", ctypes.c_void_p),
                 ("llr_dev", ctypes.c_void_p), ("iters_dev", ctypes.c_void_p),
                 ("flags_dev", ctypes.c_void_p)]
 
@@ -59,7 +59,7 @@ class DecodeStats(ctypes.Structure):
     _fields_ = [("shots", ctypes.c_uint64), ("nontrivial", ctypes.c_uint64),
                 ("converged", ctypes.c_uint64), ("osd", ctypes.c_uint64),
                 ("not_in_span", ctypes.c_uint64), ("bp_iters", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint64 * 2)]
+                ("osd_incomplete", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
 
 
 class PlanItem(ctypes.Structure):
@@ -241,10 +241,10 @@ class DEM:
         return H
 
     def decode(self, det, n_shots, pred, *, max_iter=30, alpha=1.0, weights=None, use_osd=True,
-               bp_threads=0, bp_per_cu=0, osd_per_cu=0, bp_global_state=0, ehat=None, llr=None,
-               iters=None, flags=None, stats=None, stream=None):
+               bp_threads=0, bp_per_cu=0, osd_per_cu=0, bp_global_state=0, osd_window=0, ehat=None,
+               llr=None, iters=None, flags=None, stats=None, stream=None):
         cfg = DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads,
-                         bp_per_cu, osd_per_cu, bp_global_state,
+                         bp_per_cu, osd_per_cu, bp_global_state, osd_window,
                          _ptr(ehat), _ptr(llr), _ptr(iters), _ptr(flags))
         _check(_lib.tmcs_decode(self._h, ctypes.byref(cfg), _ptr(det), n_shots, _ptr(pred), _ptr(stats),
                                 _stream(stream)))
@@ -266,9 +266,9 @@ class DEM:
 
 
 def make_cfg(max_iter=30, alpha=1.0, weights=None, use_osd=True, bp_threads=0, bp_per_cu=0,
-             osd_per_cu=0, bp_global_state=0):
+             osd_per_cu=0, bp_global_state=0, osd_window=0):
     return DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads, bp_per_cu,
-                      osd_per_cu, bp_global_state, None, None, None, None)
+                      osd_per_cu, bp_global_state, osd_window, None, None, None, None)
 
 
 def autotune(dem, det, n_shots, cfg=None, stream=None) -> DecoderCfg:
@@ -313,7 +313,8 @@ class Plan:
         _check(_lib.tmcs_plan_result(self._h, item, ctypes.byref(shots), ctypes.byref(errs), ctypes.byref(st),
                                      _stream(stream)))
         return dict(shots=shots.value, errors=errs.value, nontrivial=st.nontrivial, converged=st.converged,
-                    osd=st.osd, not_in_span=st.not_in_span, bp_iters=st.bp_iters, stat_shots=st.shots)
+                    osd=st.osd, not_in_span=st.not_in_span, bp_iters=st.bp_iters,
+                    osd_incomplete=st.osd_incomplete, stat_shots=st.shots)
 
 
 def logical_error_rate(pred, obs, k, n_shots, stream=None):
@@ -351,4 +352,4 @@ def new_stats(device="cuda"):
 def read_stats(t) -> dict:
     v = t.cpu().numpy().astype(np.uint64)
     return dict(shots=int(v[0]), nontrivial=int(v[1]), converged=int(v[2]), osd=int(v[3]),
-                not_in_span=int(v[4]), bp_iters=int(v[5]))
+                not_in_span=int(v[4]), bp_iters=int(v[5]), osd_incomplete=int(v[6]))

@@ -40,6 +40,10 @@ def test_decoder_config_is_validated(lib, handles):
     cfg = lib.make_cfg(max_iter=10, alpha=0.0)
     assert raw.tmcs_decode(d._h, ctypes.byref(cfg), None, 64, None, None, None) == EINVAL
     assert "alpha" in _err(lib)
+    for w in (-1, 2049):
+        cfg = lib.make_cfg(max_iter=10, osd_window=w)
+        assert raw.tmcs_decode(d._h, ctypes.byref(cfg), None, 64, None, None, None) == EINVAL
+        assert "osd_window" in _err(lib)
     cfg = lib.make_cfg(max_iter=10)
     assert raw.tmcs_decode(None, ctypes.byref(cfg), None, 64, None, None, None) == EINVAL
     # no shots: nothing to do, no device work
