@@ -23,7 +23,9 @@
 // solved on them.  Elimination keeps an echelon basis of reduced columns in HBM
 // (each vector = m syndrome bits followed by rank bits recording which kept
 // columns it sums); candidates are reduced 256 at a time, one per thread, in
-// registers, then among themselves in order.
+// registers, then among themselves in order.  DEMs beyond 2048 detectors or
+// 16384 columns run the same elimination on a window of the sorted order (the
+// smallest keys, found by radix selection, and the detectors they touch).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
