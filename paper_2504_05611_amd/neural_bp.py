@@ -151,9 +151,11 @@ def main(argv=None):
     ap.add_argument("--eval-shots", type=int, default=1 << 20)
     ap.add_argument("--out", default="", help="save the trained weights (torch .pt)")
     ap.add_argument("--log-every", type=int, default=20)
+    ap.add_argument("--d", type=int, default=0, help="pick the workload's circuit of this distance")
+    ap.add_argument("--p", type=float, default=0.0, help="pick the workload's circuit of this p")
     args = ap.parse_args(argv)
     w = WORKLOADS[args.workload]
-    spec = w.specs[0]
+    spec = next(s for s in w.specs if (not args.d or s.d == args.d) and (not args.p or s.p == args.p))
     T = w.bp_iters
     circuit = tmcs.Circuit(spec)
     dem = tmcs.DEM(circuit)
@@ -165,7 +167,7 @@ def main(argv=None):
     t_train = time.perf_counter() - t0
     if args.out:
         torch.save(res.weights.cpu(), args.out)
-    out = dict(workload=w.name, T=T, edges=dem.edges, train_steps=args.steps, batch=args.batch, lr=args.lr,
+    out = dict(workload=w.name, d=spec.d, p=spec.p, T=T, edges=dem.edges, train_steps=args.steps, batch=args.batch, lr=args.lr,
                loss_iterations=args.last or T,
                train_syndromes=args.steps * args.batch, train_s=t_train,
                train_syndromes_per_s=args.steps * args.batch / t_train,

@@ -7,13 +7,13 @@ from workloads import MEMORY, NLCNOT, bb, sc
 pytestmark = pytest.mark.gpu
 
 
-def _eager(tmcs, c, dem, seed, inst, begin, n, T):
+def _eager(tmcs, c, dem, seed, inst, begin, n, T, **kw):
     import torch
     det, obs = c.alloc_outputs(n)
     c.sample(seed, inst, begin, n, det, obs)
     pred = torch.zeros_like(obs)
     st = tmcs.new_stats()
-    dem.decode(det, n, pred, max_iter=T, stats=st)
+    dem.decode(det, n, pred, max_iter=T, stats=st, **kw)
     ne, _, _ = tmcs.logical_error_rate(pred, obs, c.num_observables, n)
     return ne, tmcs.read_stats(st)
 
@@ -40,6 +40,34 @@ def test_plan_matches_eager(gpu_lib, use_graph):
         assert r["stat_shots"] == 3 * B
         assert r["osd"] == ref[i][1]["osd"] and r["converged"] == ref[i][1]["converged"]
         assert r["bp_iters"] == ref[i][1]["bp_iters"]
+
+
+def test_plan_with_weights_and_windowed_osd_matches_eager(gpu_lib):
+    """A captured plan whose items use per-edge, per-iteration BP weights and the
+    windowed OSD-0 gives the counts of eager calls with the same configuration."""
+    import torch
+    specs = [sc(5, NLCNOT, 3, 3, 3e-3, 2e-2), bb("bb18", MEMORY, 3, 0, 4e-3)]
+    B, T = 8192, 20
+    circuits = [gpu_lib.Circuit(s) for s in specs]
+    dems = [gpu_lib.DEM(c) for c in circuits]
+    g = torch.Generator().manual_seed(17)
+    wts = (0.6 + 0.4 * torch.rand((T, dems[0].edges), generator=g)).cuda()
+    kws = [dict(weights=wts), dict(osd_window=16)]
+    items = [(c, d, gpu_lib.make_cfg(max_iter=T, **kw), 4, i)
+             for i, (c, d, kw) in enumerate(zip(circuits, dems, kws))]
+    plan = gpu_lib.Plan(items, B, use_graph=True)
+    plan.run(1)
+    torch.cuda.synchronize()
+    ref = [_eager(gpu_lib, c, d, 4, i, 0, 2 * B, T, **kw)
+           for i, (c, d, kw) in enumerate(zip(circuits, dems, kws))]
+    plan.run(1)
+    for i in range(len(items)):
+        r = plan.result(i)
+        print(f"[plan-weights] item {i} {r} eager {ref[i]}", flush=True)
+        assert r["shots"] == 2 * B and r["errors"] == ref[i][0]
+        for k in ("osd", "converged", "bp_iters", "osd_incomplete"):
+            assert r[k] == ref[i][1][k], k
+    assert ref[0][1]["osd"] > 0 and ref[1][1]["osd"] > 0
 
 
 def test_autotune_keeps_results(gpu_lib):
