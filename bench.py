@@ -158,7 +158,8 @@ def main():
     value = total / elapsed
 
     sample_ms = sum(v[1] for n, v in kern.items() if n.startswith(("k_event", "k_scan", "k_frame", "k_zero_u32")))
-    decode_ms = sum(v[1] for n, v in kern.items() if n in ("k_bp", "k_osd", "k_compact", "k_zero_i32", "k_add_shots"))
+    decode_ms = sum(v[1] for n, v in kern.items()
+                    if n in ("k_bp", "k_osd", "k_osd_retry", "k_compact", "k_zero_i32", "k_add_shots"))
     dominant = max(kern.items(), key=lambda kv: kv[1][1])[0]
     launches, dom_ms = kern[dominant]
     avg_s = dom_ms / launches / 1e3

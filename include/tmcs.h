@@ -176,7 +176,11 @@ typedef struct {
   uint64_t not_in_span;  /* OSD shots whose syndrome was not in H's column space */
   uint64_t bp_iters;     /* sum of BP iterations */
   uint64_t osd_incomplete; /* windowed OSD shots whose syndrome was not spanned inside the window */
-  uint64_t reserved;
+  uint64_t osd_prefix_retry; /* OSD shots on DEMs within the dense limits whose first sorted
+                                columns (127 for DEMs whose elimination basis fits in LDS,
+                                else 1023) did not span the syndrome and that were decoded
+                                again with a full sort; the result is the dense OSD-0's
+                                either way */
 } tmcs_decode_stats;
 
 /* Decode det_dev ([rows][ceil(n/64)], as written by tmcs_sample) and write the

@@ -48,6 +48,9 @@ constexpr int OSD_MAX_KEYS = 16384;
 constexpr int WIN_KEYS = 2048;
 constexpr int WIN_MW = 32;
 constexpr int WIN_MAX_ROWS = 64 * WIN_MW;
+// dense OSD-0 first tries this many smallest keys (one-wave and 256-thread variants)
+constexpr int PFX_KEYS_WAVE = 128;
+constexpr int PFX_KEYS_WG = 1024;
 
 struct DecodeDevice {
   int device = -1;
@@ -70,7 +73,9 @@ struct DecodeDevice {
   uint64_t* synd = nullptr;
   unsigned char* gstate = nullptr;  // BP state in device memory, one slab per team
   int32_t* rowmap = nullptr;        // windowed OSD: [grid][2][m] row tables (WIN_NONE between shots)
+  int32_t* retry = nullptr;         // OSD jobs the sorted prefix did not settle
   size_t cap_queue = 0, cap_osd = 0, cap_llr = 0, cap_basis = 0, cap_synd = 0, cap_gstate = 0, cap_rowmap = 0;
+  size_t cap_retry = 0;
 };
 
 // Per-lane schedule records of the BP passes (int4 = {x, y, z, w}).
@@ -392,6 +397,9 @@ struct OSDArgs {
   int32_t npad;              // sort length (power of two >= n; WIN: window length)
   int32_t* rowmap;           // WIN: [grid][2][m] first window position touching a row, local row index
   int32_t win_rows;          // WIN: most local rows a window may hold (<= 64 * MW)
+  const int32_t* jobs;       // nullable: job j is jobs[j] (a retry pass), else j
+  int32_t cnt_total, cnt_next;   // counters[] holding the number of jobs and the next job
+  int32_t* retry;            // PFX: jobs whose prefix did not span s (counted in counters[4])
 };
 
 constexpr int32_t WIN_NONE = 0x7FFFFFFF;   // rowmap: row not touched by the window
@@ -519,10 +527,17 @@ __device__ __forceinline__ uint64_t bit_of(const uint64_t (&v)[W], int p) {
 // stop and the solution are exactly those of the full OSD-0 whenever s is
 // spanned inside the window.  Otherwise (window too small) the shot keeps BP's
 // hard decision and is flagged (flags bit 3, stats osd_incomplete).
-template <int MW, int RW, int KPT, bool BL, int NT, bool WIN = false>
+//
+// PFX (DEMs within the dense limits but wider than npad): the same selection
+// gives the npad - 1 smallest keys, and the elimination runs on that prefix of
+// the order with H's own rows.  If s is spanned there, the result is the full
+// OSD-0's; otherwise the job goes to a retry list, which the full-sort variant
+// then decodes, so every shot gets the exact OSD-0 correction.
+template <int MW, int RW, int KPT, bool BL, int NT, bool WIN = false, bool PFX = false>
 __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
   constexpr int W = MW + RW;
   static_assert(!(WIN && BL), "the window variant keeps its basis in HBM");
+  static_assert(!(WIN && PFX), "one front end per variant");
   extern __shared__ __align__(8) unsigned char sm[];
   // local capacity: rank and rows of the problem the elimination sees
   const int cap_r = WIN ? 64 * MW : a.rank;
@@ -571,18 +586,19 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
     return __syncthreads_or(nz);
   };
   while (true) {
-    if (tid == 0) s_job = atomicAdd(&a.counters[3], 1);
+    if (tid == 0) s_job = atomicAdd(&a.counters[a.cnt_next], 1);
     __syncthreads();
-    const int job = s_job;
+    const int jn = s_job;
     __syncthreads();
-    if (job >= a.counters[2]) break;
+    if (jn >= a.counters[a.cnt_total]) break;
+    const int job = a.jobs ? a.jobs[jn] : jn;
     const int64_t ls = a.osd_queue[job];
     const int64_t shot = a.shot0 + ls;
     const float* L = a.osd_llr + (int64_t)job * a.n;
     int n_loc = a.n, rank_loc = a.rank, n0 = a.n;
     if (tid == 0) { s_r = 0; s_ns = 0; s_inc = 0; }
     __syncthreads();
-    if constexpr (!WIN) {
+    if constexpr (!WIN && !PFX) {
       // 1. sort columns by (L_v, v); list the syndrome's rows
       for (int r = tid; r < a.m; r += NT) prow[r] = -1;
       for (int wd = tid; wd < a.mw; wd += NT) {
@@ -659,6 +675,19 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
       }
       bitonic_sort_regs<KPT, true>(x, keys, a.npad);
       const uint32_t* col32 = (const uint32_t*)keys;
+      if constexpr (PFX) {
+        // the prefix of the order, on H's rows
+        n_loc = n0;
+        for (int r = tid; r < a.m; r += NT) prow[r] = -1;
+        for (int wd = tid; wd < a.mw; wd += NT) {
+          uint64_t y = a.synd[ls * a.mw + wd];
+          if (y) {
+            const int base = atomicAdd(&s_ns, __popcll(y));
+            for (int k = 0; y; ++k, y &= y - 1) srow[base + k] = wd * 64 + (__ffsll((unsigned long long)y) - 1);
+          }
+        }
+        __syncthreads();
+      } else {
       // 1c. first window position touching each row
       for (int j = tid; j < n0; j += NT) {
         const int col = (int)col32[j];
@@ -719,9 +748,10 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
         }
       }
       __syncthreads();
+      }
     }
-    // WIN: every column of H is in the window, so the result is the full OSD-0's
-    const bool whole = !WIN || n_loc == a.n;
+    // WIN, PFX: every column of H is in the window, so the result is the full OSD-0's
+    const bool whole = !(WIN || PFX) || n_loc == a.n;
     const bool skip = WIN && !whole && s_inc;
     // rows of the elimination: H's, or the window's local numbers
     auto row_of = [&](int32_t k) -> int {
@@ -735,7 +765,7 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
       __syncthreads();           // every wave has read s_r before wave 0 advances it
       if (r_start >= rank_loc) break;
       const int idx = base + tid;
-      const int col = idx < n_loc ? ((BL || WIN) ? (int)((const uint32_t*)keys)[idx] : (int)(keys[idx] & 0xFFFFFFFFu)) : -1;
+      const int col = idx < n_loc ? ((BL || WIN || PFX) ? (int)((const uint32_t*)keys)[idx] : (int)(keys[idx] & 0xFFFFFFFFu)) : -1;
       uint64_t v[W];
 #pragma unroll
       for (int w = 0; w < W; ++w) v[w] = 0ull;
@@ -870,6 +900,12 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
     // WIN: a window that does not span s says nothing about H unless it is all of H
     const bool incomplete = unspanned && !whole;
     const int not_in_span = unspanned && whole;
+    if (PFX && incomplete) {
+      // the full sort decides this one
+      if (tid == 0) a.retry[atomicAdd(&a.counters[4], 1)] = job;
+      __syncthreads();
+      continue;
+    }
     uint64_t pm = 0;
     if (incomplete) {
       // BP's hard decision stands
@@ -896,6 +932,7 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
       if (a.flags) a.flags[shot] = (uint8_t)(2 | (not_in_span ? 4 : 0) | (incomplete ? 8 : 0));
       if (a.stats && not_in_span) atomicAdd((unsigned long long*)&a.stats->not_in_span, 1ull);
       if (a.stats && incomplete) atomicAdd((unsigned long long*)&a.stats->osd_incomplete, 1ull);
+      if (a.stats && a.jobs) atomicAdd((unsigned long long*)&a.stats->osd_prefix_retry, 1ull);
     }
     if constexpr (WIN) {
       // leave the row table untouched for the next shot
@@ -934,7 +971,7 @@ void free_device(DecodeDevice* d) {
   hipFree(d->row_ptr); hipFree(d->col_idx); hipFree(d->col_ptr); hipFree(d->csc_row); hipFree(d->csc_edge);
   hipFree(d->lam); hipFree(d->obs_mask); hipFree(d->counters); hipFree(d->queue); hipFree(d->osd_queue);
   hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd); hipFree(d->gstate); hipFree(d->init); hipFree(d->sign0);
-  hipFree(d->rowmap);
+  hipFree(d->rowmap); hipFree(d->retry);
   for (auto& q : d->scheds) { hipFree(q.c); hipFree(q.v); }
   *d = DecodeDevice();
 }
@@ -1093,14 +1130,44 @@ int device_cus() {
   return cus > 0 ? cus : 256;
 }
 
-template <int MW, int RW, int KPT, bool BL>
+template <int MW, int RW, int KPT, bool BL, bool PFX = false>
 tmcs_status launch_osd(const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
   constexpr int NT = BL ? 64 : OSD_THREADS;
-  if (lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_osd<MW, RW, KPT, BL, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+  auto k = k_osd<MW, RW, KPT, BL, NT, false, PFX>;
+  if (lds > 64 * 1024 && hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "OSD workspace does not fit in LDS");
-  TMCS_LAUNCH("k_osd", (k_osd<MW, RW, KPT, BL, NT>), dim3(grid), dim3(NT), lds, s, a);
+  // the full-sort pass over jobs a prefix left open is timed on its own
+  TMCS_LAUNCH(a.jobs ? "k_osd_retry" : "k_osd", k, dim3(grid), dim3(NT), lds, s, a);
   return hip_check(hipGetLastError(), "k_osd launch");
+}
+
+// prefix pass: PFX_KEYS_WAVE (one wave) or PFX_KEYS_WG (256 threads) keys, 4 per thread
+template <int MW>
+tmcs_status launch_osd_pfx(bool bl, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
+  return bl ? launch_osd<MW, MW, PFX_KEYS_WAVE / 64, true, true>(a, grid, lds, s)
+            : launch_osd<MW, MW, PFX_KEYS_WG / OSD_THREADS, false, true>(a, grid, lds, s);
+}
+
+tmcs_status dispatch_osd_pfx(int mw, bool bl, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (bl) {
+    if (mw <= 1) return launch_osd_pfx<1>(true, a, grid, lds, s);
+    if (mw <= 2) return launch_osd_pfx<2>(true, a, grid, lds, s);
+    if (mw <= 4) return launch_osd_pfx<4>(true, a, grid, lds, s);
+    if (mw <= 5) return launch_osd_pfx<5>(true, a, grid, lds, s);
+    if (mw <= 8) return launch_osd_pfx<8>(true, a, grid, lds, s);
+    return fail(TMCS_EUNSUPPORTED, "OSD basis in LDS: too many detectors");
+  }
+  if (mw <= 1) return launch_osd_pfx<1>(false, a, grid, lds, s);
+  if (mw <= 2) return launch_osd_pfx<2>(false, a, grid, lds, s);
+  if (mw <= 4) return launch_osd_pfx<4>(false, a, grid, lds, s);
+  if (mw <= 5) return launch_osd_pfx<5>(false, a, grid, lds, s);
+  if (mw <= 8) return launch_osd_pfx<8>(false, a, grid, lds, s);
+  if (mw <= 12) return launch_osd_pfx<12>(false, a, grid, lds, s);
+  if (mw <= 15) return launch_osd_pfx<15>(false, a, grid, lds, s);
+  if (mw <= 18) return launch_osd_pfx<18>(false, a, grid, lds, s);
+  if (mw <= 24) return launch_osd_pfx<24>(false, a, grid, lds, s);
+  if (mw <= 32) return launch_osd_pfx<32>(false, a, grid, lds, s);
+  return fail(TMCS_EUNSUPPORTED, "OSD supports at most 2048 detectors in this build");
 }
 
 template <int MW>
@@ -1227,6 +1294,13 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const size_t basis_bytes = (size_t)std::max(osd_rank, 1) * W * 8;
   const bool osd_bl = !osd_win && osd_lds_basis_ok(mw, npad) && osd_lds - (size_t)npad * 4 + basis_bytes <= 80 * 1024;
   if (osd_bl) osd_lds += basis_bytes - (size_t)npad * 4;
+  // dense OSD-0 on a DEM wider than the prefix: prefix pass, then a full sort of the rest
+  const int pfx_keys = osd_bl ? PFX_KEYS_WAVE : PFX_KEYS_WG;
+  // (the one-wave variant gathers 8-byte keys over its 4-byte index area and the LDS basis after it)
+  const bool osd_pfx = cfg.use_osd && !osd_win && D.cols >= pfx_keys &&
+                       (!osd_bl || basis_bytes >= (size_t)pfx_keys * 4);
+  size_t pfx_lds = (size_t)pfx_keys * 8 + (size_t)osd_rank * 8 + (size_t)osd_rows * 8 + (size_t)W * 8 + 64;
+  if (osd_bl) pfx_lds += basis_bytes - (size_t)pfx_keys * 4;
   const int osd_fit = std::max<int>(1, (int)((160 * 1024) / (osd_lds + 512)));
   const int osd_per_cu = std::min(osd_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : (osd_bl ? 16 : 4));
   const int osd_grid = std::max(1, cus * osd_per_cu);
@@ -1238,6 +1312,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
         (st = grow(&d->osd_llr, &d->cap_llr, (size_t)chunk * (size_t)D.cols)) != TMCS_OK ||
         (!osd_bl && (st = grow(&d->basis, &d->cap_basis, (size_t)osd_grid * (size_t)std::max(osd_rank, 1) * W)) != TMCS_OK))
       return st;
+    if (osd_pfx && (st = grow(&d->retry, &d->cap_retry, (size_t)chunk)) != TMCS_OK) return st;
     if (osd_win) {
       const size_t n_map = (size_t)osd_grid * 2 * (size_t)std::max(D.rows, 1);
       const int32_t* before = d->rowmap;
@@ -1298,8 +1373,20 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
       o.pred = pred; o.nobs = D.nobs; o.stats = stats; o.ehat = cfg.ehat_dev; o.flags = cfg.flags_dev;
       o.npad = npad;
       o.rowmap = d->rowmap; o.win_rows = cfg.osd_window > 0 ? cfg.osd_window : WIN_MAX_ROWS;
-      if (osd_win) st = launch_osd_win(o, osd_grid, osd_lds, stream);
-      else st = dispatch_osd(mw, npad / (osd_bl ? 64 : OSD_THREADS), osd_bl, o, osd_grid, osd_lds, stream);
+      o.jobs = nullptr; o.cnt_total = 2; o.cnt_next = 3; o.retry = nullptr;
+      if (osd_win) {
+        st = launch_osd_win(o, osd_grid, osd_lds, stream);
+      } else if (osd_pfx) {
+        OSDArgs op = o;
+        op.npad = pfx_keys;
+        op.retry = d->retry;
+        if ((st = dispatch_osd_pfx(mw, osd_bl, op, osd_grid, pfx_lds, stream)) != TMCS_OK) return st;
+        OSDArgs orr = o;
+        orr.jobs = d->retry; orr.cnt_total = 4; orr.cnt_next = 5;
+        st = dispatch_osd(mw, npad / (osd_bl ? 64 : OSD_THREADS), osd_bl, orr, osd_grid, osd_lds, stream);
+      } else {
+        st = dispatch_osd(mw, npad / (osd_bl ? 64 : OSD_THREADS), osd_bl, o, osd_grid, osd_lds, stream);
+      }
       if (st != TMCS_OK) return st;
     }
   }

@@ -59,7 +59,7 @@ class DecodeStats(ctypes.Structure):
     _fields_ = [("shots", ctypes.c_uint64), ("nontrivial", ctypes.c_uint64),
                 ("converged", ctypes.c_uint64), ("osd", ctypes.c_uint64),
                 ("not_in_span", ctypes.c_uint64), ("bp_iters", ctypes.c_uint64),
-                ("osd_incomplete", ctypes.c_uint64), ("reserved", ctypes.c_uint64)]
+                ("osd_incomplete", ctypes.c_uint64), ("osd_prefix_retry", ctypes.c_uint64)]
 
 
 class PlanItem(ctypes.Structure):
@@ -314,7 +314,8 @@ class Plan:
                                      _stream(stream)))
         return dict(shots=shots.value, errors=errs.value, nontrivial=st.nontrivial, converged=st.converged,
                     osd=st.osd, not_in_span=st.not_in_span, bp_iters=st.bp_iters,
-                    osd_incomplete=st.osd_incomplete, stat_shots=st.shots)
+                    osd_incomplete=st.osd_incomplete, osd_prefix_retry=st.osd_prefix_retry,
+                    stat_shots=st.shots)
 
 
 def logical_error_rate(pred, obs, k, n_shots, stream=None):
@@ -352,4 +353,5 @@ def new_stats(device="cuda"):
 def read_stats(t) -> dict:
     v = t.cpu().numpy().astype(np.uint64)
     return dict(shots=int(v[0]), nontrivial=int(v[1]), converged=int(v[2]), osd=int(v[3]),
-                not_in_span=int(v[4]), bp_iters=int(v[5]), osd_incomplete=int(v[6]))
+                not_in_span=int(v[4]), bp_iters=int(v[5]), osd_incomplete=int(v[6]),
+                osd_prefix_retry=int(v[7]))
