@@ -36,8 +36,8 @@ FRAME_OPS_PER_CX_WORD = 4      # two 64-bit XORs per CX per 64-shot word
 TRAFFIC = {
     "sc5_nlcnot": {
         "k_bp": {"src": "paper_2504_05611_amd/csrc/kernels/decode.hip",
-                 "sha256": "7fb9fb331fc62a844758c4fd21854e811d364ad56565e33315550d8f57d9043c",
-                 "fetch_kib": 14900.6, "write_kib": 27036.0},
+                 "sha256": "20bbdf655df41c5ba864872e5c72d1eb3ff12598588778a02712c3381419b977",
+                 "fetch_kib": 14884.1, "write_kib": 27035.6},
         "k_frame": {"src": "paper_2504_05611_amd/csrc/kernels/sample.hip",
                     "sha256": "aac13a06933cea5d844bbee436525c35d3f385c1dc3acc17043a360968da0597",
                     "fetch_kib": 61133.1, "write_kib": 38549.8},

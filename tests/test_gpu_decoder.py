@@ -173,3 +173,40 @@ def test_decoder_launch_shape_invariance(gpu_lib, name, spec, shots):
             assert (p == ref).all(), (kw, full)
             if full:
                 assert (ehat.cpu().numpy() == ref_e).all(), kw
+
+
+def test_osd_prefix_retry_matches_oracle(gpu_lib):
+    """Dense OSD-0 first eliminates on the 127 smallest keys and re-runs the full
+    sort when that prefix does not span s.  At p = 1e-2 some shots need the
+    early stop past column 127 of the (L, v) order (counted here from the
+    decoder's own FP32 posteriors): they must be retried, and every
+    correction must still equal the oracle's BP-OSD."""
+    import torch
+    from oracle.osd import column_ints
+    from test_gpu_osd_window import _early_stop
+    spec = sc(5, NLCNOT, 5, 5, 1e-2, 2e-2)
+    shots, T = 512, 30
+    print(f"[osd-prefix] sc5 p=1e-2 shots={shots}", flush=True)
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    det, obs = _oracle_det(spec, shots)
+    pred = torch.zeros_like(obs)
+    ehat = torch.zeros((shots, dem.cols), dtype=torch.uint8, device="cuda")
+    llr = torch.zeros((shots, dem.cols), dtype=torch.float32, device="cuda")
+    flags = torch.zeros(shots, dtype=torch.uint8, device="cuda")
+    stats = gpu_lib.new_stats()
+    dem.decode(det, shots, pred, max_iter=T, ehat=ehat, llr=llr, flags=flags, stats=stats)
+    torch.cuda.synchronize()
+    oc = build_circuit(spec)
+    od = build_dem(oc)
+    synd = unpack_bits(det.cpu().numpy().view(np.uint64), shots).T
+    o32 = Decoder(od.H(), od.priors(), od.L(), max_iter=T, dtype=np.float32).decode(synd, chunk=64)
+    e = ehat.cpu().numpy().astype(bool)
+    assert (e == o32["e_hat"]).all()
+    assert (unpack_bits(pred.cpu().numpy().view(np.uint64), shots).T[:, : od.L().shape[0]] == o32["pred_obs"]).all()
+    st = gpu_lib.read_stats(stats)
+    cols = column_ints(od.H())
+    L = llr.cpu().numpy()
+    late = sum(_early_stop(cols, synd[i], L[i])[0] >= 127 for i in np.nonzero(flags.cpu().numpy() & 2)[0])
+    print(f"[osd-prefix] osd {st['osd']} retried {st['osd_prefix_retry']} early stops past 127: {late}", flush=True)
+    assert late > 0 and st["osd_prefix_retry"] >= late
