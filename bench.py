@@ -27,6 +27,13 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 BP_OPS_PER_EDGE_ITER = 10      # |q|, two min compares, sign XORs, message rebuild, add
 FRAME_OPS_PER_CX_WORD = 4      # two 64-bit XORs per CX per 64-shot word
+# whole-sampler model (frame bit-ops plus the prescribed random numbers): a
+# Philox4x32-10 call is ~220 issue slots (quarter-rate 32-bit multiplies) for 4
+# draws, one draw starts every (site, 4096-shot block) stream, and an event costs
+# a gap draw, a component draw, a 12-step table search and its frame update
+PHILOX_OPS_PER_DRAW = 55
+GAP_SEARCH_OPS = 36
+EVENT_APPLY_OPS = 4
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch,
 # averaged over the dispatches of a --steps 1 --warmup 1 run of this workload),
@@ -83,6 +90,45 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 3}))
 
 
+def _cpu_worker(spec, seed, begin, n, bp_iters, barrier, q):
+    """One host process of the all-cores leg: oracle sample + BP-OSD decode of shots [begin, begin + n)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.circuits import build_circuit
+    from oracle.dem import build_dem
+    from oracle.frame import sample
+    from oracle.osd import Decoder
+    with threadpool_limits(limits=1):
+        oc = build_circuit(spec)
+        od = build_dem(oc)
+        dec = Decoder(od.H(), od.priors(), od.L(), max_iter=bp_iters, dtype=__import__("numpy").float64)
+        barrier.wait()
+        t0 = time.perf_counter()
+        det, _ = sample(oc, seed, 0, begin, n)
+        dec.decode(det.T)
+        q.put((t0, time.perf_counter()))
+
+
+def cpu_baseline_all_cores(w, spec, per_proc=1024):
+    """The oracle in one process per host core (at most 16), each on its own slice of the
+    workload's shots: total shots / (last finish - first start)."""
+    import multiprocessing as mp
+    nproc = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")
+    barrier, q = ctx.Barrier(nproc), ctx.Queue()
+    procs = [ctx.Process(target=_cpu_worker, args=(spec, w.seed, i * per_proc, per_proc, w.bp_iters, barrier, q))
+             for i in range(nproc)]
+    for p in procs:
+        p.start()
+    times = [q.get(timeout=600) for _ in procs]
+    for p in procs:
+        p.join()
+    wall = max(t[1] for t in times) - min(t[0] for t in times)
+    return dict(value=nproc * per_proc / wall, unit="shots/s", cores=nproc, kind="oracle",
+                sample=f"{nproc} processes x {per_proc} shots (shots [0, {nproc * per_proc}), seed {w.seed}), "
+                       f"one host thread each; FP64 oracle sample + BP-OSD decode, {wall:.2f} s wall")
+
+
 def cpu_baseline(w, spec, n_shots):
     """Time the oracle (as it stands) on a bounded sample of the workload on host cores."""
     from threadpoolctl import threadpool_limits
@@ -123,6 +169,12 @@ def main():
     w = WORKLOADS[args.workload]
     spec = w.specs[0]
     shots = args.shots or w.shots
+    # host baselines first, before this process initialises the GPU (the all-cores
+    # leg starts fresh interpreter processes)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_all_cores(w, spec)
+        cpu["single_thread"] = cpu_baseline(w, spec, 8192)
     torch.cuda.set_device(0)
     circ = tmcs.Circuit(spec)
     dem = tmcs.DEM(circ)
@@ -191,6 +243,19 @@ def main():
                                avg_launch_ms=fms / fl,
                                model=f"{FRAME_OPS_PER_CX_WORD} lane-ops per CX per 64-shot word x "
                                      f"{info['gates_2q']} CX x {words} words")
+    # the whole sampler (event generation and frames) against the frame + RNG model
+    sample_roofline_rng = None
+    if sample_ms:
+        ev = info["events_per_mshot"] / 1e6
+        w_shot = (FRAME_OPS_PER_CX_WORD * info["gates_2q"] / 64.0 + info["noise_sites"] / 4096.0 * PHILOX_OPS_PER_DRAW
+                  + ev * (2 * PHILOX_OPS_PER_DRAW + GAP_SEARCH_OPS + EVENT_APPLY_OPS))
+        s_ach = w_shot * total / (sample_ms / 1e3) / 1e12
+        sample_roofline_rng = dict(bound="alu", kernels="k_event_count + k_scan_* + k_event_write + k_frame",
+                                   achieved=s_ach, peak=VALU_PEAK_TOPS, unit="TOP/s", frac=s_ach / VALU_PEAK_TOPS,
+                                   model=(f"{w_shot:.1f} lane-ops per shot: {FRAME_OPS_PER_CX_WORD} per CX per 64 "
+                                          f"shots, {PHILOX_OPS_PER_DRAW} per Philox draw (one per site and "
+                                          f"4096-shot block, two per event), {GAP_SEARCH_OPS} per gap search, "
+                                          f"{EVENT_APPLY_OPS} per event applied; {ev:.2f} events per shot"))
     ler = errors / total
     out = {
         "metric": "shots/sec (sample+BP-OSD decode) on 1 MI355X at matched logical error rate",
@@ -207,9 +272,10 @@ def main():
         "kernels_ms": {n: round(v[1] / v[0], 4) for n, v in sorted(kern.items())},
         "roofline": roofline,
         "sample_roofline": sample_roofline,
+        "sample_roofline_rng": sample_roofline_rng,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, spec, 8192)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -82,6 +82,7 @@ enum {
   TMCS_INFO_QUBITS = 0, TMCS_INFO_GATES_1Q, TMCS_INFO_GATES_2Q, TMCS_INFO_MEAS,
   TMCS_INFO_MEAS_FINAL, TMCS_INFO_DETECTORS, TMCS_INFO_OBSERVABLES,
   TMCS_INFO_NOISE_SITES, TMCS_INFO_INSTRUCTIONS, TMCS_INFO_CODE_N, TMCS_INFO_CODE_K,
+  TMCS_INFO_EVENTS_PER_MSHOT,   /* expected noise events per 10^6 shots (sum of site p), rounded */
   TMCS_INFO_LEN = 16
 };
 enum {

@@ -25,6 +25,7 @@
 // pair k is (E0 + k, E0 + n + k) with E0 after the blocks.
 #include <algorithm>
 #include <array>
+#include <cmath>
 #include <cstdio>
 #include <set>
 
@@ -333,7 +334,10 @@ std::string circuit_text(const Circuit& c) {
 
 void circuit_counts(const Circuit& c, int64_t info[TMCS_INFO_LEN]) {
   for (int i = 0; i < TMCS_INFO_LEN; ++i) info[i] = 0;
+  double events = 0.0;
   for (const Op& op : c.ops) {
+    if (op.kind == OP_XERR || op.kind == OP_ZERR || op.kind == OP_DEP1 || op.kind == OP_DEP2)
+      events += op.p * (double)(op.kind == OP_DEP2 ? op.t.size() / 2 : op.t.size());
     if (op.kind == OP_H || op.kind == OP_CXREC || op.kind == OP_CZREC)
       info[TMCS_INFO_GATES_1Q] += op.kind == OP_H ? (int64_t)op.t.size() : (int64_t)op.t.size() / 2;
     else if (op.kind == OP_CX)
@@ -348,6 +352,7 @@ void circuit_counts(const Circuit& c, int64_t info[TMCS_INFO_LEN]) {
   info[TMCS_INFO_INSTRUCTIONS] = (int64_t)c.ops.size();
   info[TMCS_INFO_CODE_N] = c.code.n;
   info[TMCS_INFO_CODE_K] = c.code.k;
+  info[TMCS_INFO_EVENTS_PER_MSHOT] = (int64_t)std::llround(events * 1e6);
 }
 
 }  // namespace tmcs

@@ -27,7 +27,7 @@ TMCS_MEMORY, TMCS_NONLOCAL_CNOT, TMCS_TELEPORT = 0, 1, 2
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED",
           5: "ENONDETERMINISTIC", 6: "ENOTINSPAN"}
 INFO_KEYS = ["qubits", "gates_1q", "gates_2q", "meas", "meas_final", "detectors",
-             "observables", "noise_sites", "instructions", "code_n", "code_k"]
+             "observables", "noise_sites", "instructions", "code_n", "code_k", "events_per_mshot"]
 DEM_KEYS = ["rows", "cols", "obs", "edges", "rank", "undetectable", "max_row_deg", "max_col_deg"]
 
 

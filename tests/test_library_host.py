@@ -50,6 +50,10 @@ def test_circuit_and_dem_match_oracle(lib, spec):
     k = oc.counts()
     assert lc.info["detectors"] == k["dets"] and lc.info["noise_sites"] == k["sites"]
     assert lc.info["gates_1q"] == k["q1"] and lc.info["gates_2q"] == k["q2"]
+    # expected noise events per shot: one Bernoulli(p) event per site of every noise instruction
+    ev = sum(arg * (len(t) // 2 if name == "DEPOLARIZE2" else len(t))
+             for name, arg, t in oc.ops if name in ("X_ERROR", "Z_ERROR", "DEPOLARIZE1", "DEPOLARIZE2"))
+    assert lc.info["events_per_mshot"] == round(ev * 1e6)
     ld = lib.DEM(lc)
     od = build_dem(oc)
     assert ld.cols == od.num_cols and ld.rows == od.num_dets
