@@ -72,6 +72,14 @@ typedef struct {
   int32_t op;
   int32_t rounds_before, rounds_after;
   double p, p_ebit;
+  /* ebit decoherence (Methods, Decoherence; T1 = T2 = T): the n ebits of a
+   * non-local CNOT are made ebit_per_step at a time (0: no decoherence), the last
+   * group just before the CNOT, so ebit k has waited
+   * age_k = ceil(n / ebit_per_step) - 1 - floor(k / ebit_per_step) generation
+   * steps.  Both halves then get DEPOLARIZE1(3/4 (1 - exp(-age_k * ebit_rate)))
+   * (p_X = p_Y = p_Z = (1 - exp(-t/T)) / 4), with ebit_rate = t_gen / T. */
+  int32_t ebit_per_step;
+  double ebit_rate;
 } tmcs_circuit_spec;
 
 typedef struct tmcs_circuit tmcs_circuit; /* opaque, library-owned */

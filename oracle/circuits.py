@@ -28,6 +28,14 @@ circuit; Fig. 1b/1c; Table III).  Readings where the paper is silent:
   idle DEPOLARIZE1(p) on every qubit of the block left idle by a layer of the
   round (reset, each CX layer, measurement).  Ebits are prepared perfectly and
   then get DEPOLARIZE2(p_ebit); classically controlled Paulis are noiseless.
+* Ebit decoherence (Methods, Decoherence), when spec.ebit_per_step > 0: the n
+  ebits are made f = ebit_per_step at a time, the last group just before the
+  non-local CNOT, so ebit k (generation order) has waited
+  age_k = ceil(n / f) - 1 - floor(k / f) steps of t_gen.  Both halves then get
+  the Pauli channel of [PhysRevA.90.062320] for t = age_k t_gen with T1 = T2 = T,
+  p_X = p_Y = p_Z = (1 - exp(-t/T)) / 4, i.e. DEPOLARIZE1 with
+  p = 3/4 (1 - exp(-age_k * ebit_rate)) (omitted where p = 0), applied right
+  after the ebit's DEPOLARIZE2(p_ebit).
 * X-type ancillas use RX/MX and there are no Hadamards in syndrome
   extraction (fixed by the 1q counts 3n / 7n of Table III).
 * Detectors exist for Z checks only (Methods, Non-local CNOT circuit); after a
@@ -47,6 +55,8 @@ forms; detector determinism pinned with the stabilizer tableau; circuit
 distance of the d=3 surface-code operations pinned by brute force (Table I).
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -188,6 +198,14 @@ def _syndrome_round(c: Circuit, blocks, spec):
     c.add("TICK", None, [])
 
 
+def ebit_decoherence(n: int, f: int, rate: float):
+    """Per ebit (generation order): the DEPOLARIZE1 probability of its age."""
+    if f <= 0:
+        return [0.0] * n
+    steps = -(-n // f)
+    return [0.75 * (1.0 - math.exp(-(steps - 1 - k // f) * rate)) for k in range(n)]
+
+
 def _nonlocal_cnot(c: Circuit, ctl: _Block, tgt: _Block, e0: int, spec):
     n = ctl.code.n
     p = spec.p
@@ -196,6 +214,9 @@ def _nonlocal_cnot(c: Circuit, ctl: _Block, tgt: _Block, e0: int, spec):
     pairs = [q for k in range(n) for q in (ea[k], eb[k])]
     c.add("BELL_PREP", None, pairs)
     c.add("DEPOLARIZE2", spec.p_ebit, pairs)
+    for k, pk in enumerate(ebit_decoherence(n, spec.ebit_per_step, spec.ebit_rate)):
+        if pk > 0.0:
+            c.add("DEPOLARIZE1", pk, [ea[k], eb[k]])
     c.add("TICK", None, [])
     cx1 = [q for k in range(n) for q in (ctl.data[k], ea[k])]
     c.add("CX", None, cx1)

@@ -127,6 +127,15 @@ void nonlocal_cnot(Builder& B, Block& ctl, Block& tgt, int e0, int n, const tmcs
   for (int k = 0; k < n; ++k) { pairs.push_back(ea[k]); pairs.push_back(eb[k]); }
   B.add(OP_BELL, pairs);
   B.add(OP_DEP2, pairs, s.p_ebit);
+  if (s.ebit_per_step > 0) {
+    // decoherence of each ebit for its age in generation steps (T1 = T2)
+    const int f = s.ebit_per_step, steps = (n + f - 1) / f;
+    for (int k = 0; k < n; ++k) {
+      const int age = steps - 1 - k / f;
+      const double pk = 0.75 * (1.0 - std::exp(-(double)age * s.ebit_rate));
+      if (pk > 0.0) B.add(OP_DEP1, {ea[k], eb[k]}, pk);
+    }
+  }
   B.add(OP_TICK, {});
   for (int k = 0; k < n; ++k) { cx1.push_back(ctl.data[k]); cx1.push_back(ea[k]); }
   B.add(OP_CX, cx1);
@@ -188,6 +197,8 @@ void final_readout(Builder& B, std::vector<Block*> blocks, const CodeBlock& code
 tmcs_status build_circuit(const tmcs_circuit_spec& s, Circuit* c) {
   if (!(s.p >= 0.0 && s.p < 0.5) || !(s.p_ebit >= 0.0 && s.p_ebit < 0.5))
     return fail(TMCS_EINVAL, "p and p_ebit must lie in [0, 0.5)");
+  if (s.ebit_per_step < 0 || !(s.ebit_rate >= 0.0 && s.ebit_rate < 1e300))
+    return fail(TMCS_EINVAL, "ebit_per_step must be >= 0 and ebit_rate finite and >= 0");
   if (s.op != TMCS_MEMORY && s.op != TMCS_NONLOCAL_CNOT && s.op != TMCS_TELEPORT)
     return fail(TMCS_EINVAL, "unknown operation");
   if (s.rounds_before < 1 || s.rounds_before > 10000)

@@ -167,19 +167,27 @@ tmcs_status compile_program(const Circuit& c, Program* P) {
       case OP_ZERR:
       case OP_DEP1:
       case OP_DEP2: {
-        const int g = op.kind == OP_DEP2 ? 2 : 1;
-        const NoiseKind nk = op.kind == OP_XERR ? NK_XERR : op.kind == OP_ZERR ? NK_ZERR
-                           : op.kind == OP_DEP1 ? NK_DEP1 : NK_DEP2;
-        const int ti = tab_index(op.p);
-        for (size_t k = 0; k < op.t.size(); k += g) {
-          items.insert(items.end(), {(int32_t)site, (int32_t)nk, op.t[k], g == 2 ? op.t[k + 1] : -1});
-          P->site_kind.push_back((uint8_t)nk);
-          P->site_tab.push_back((uint16_t)ti);
-          P->events_per_shot += op.p;
-          ++site;
+        // one noise layer (split only where a qubit repeats) for a run of
+        // consecutive noise instructions: Pauli events commute, and the run's
+        // sites stay consecutive
+        auto is_noise = [](OpKind k) { return k == OP_XERR || k == OP_ZERR || k == OP_DEP1 || k == OP_DEP2; };
+        while (i < c.ops.size() && is_noise(c.ops[i].kind)) {
+          const Op& nop = c.ops[i];
+          const int g = nop.kind == OP_DEP2 ? 2 : 1;
+          const NoiseKind nk = nop.kind == OP_XERR ? NK_XERR : nop.kind == OP_ZERR ? NK_ZERR
+                             : nop.kind == OP_DEP1 ? NK_DEP1 : NK_DEP2;
+          const int ti = tab_index(nop.p);
+          for (size_t k = 0; k < nop.t.size(); k += g) {
+            items.insert(items.end(), {(int32_t)site, (int32_t)nk, nop.t[k], g == 2 ? nop.t[k + 1] : -1});
+            P->site_kind.push_back((uint8_t)nk);
+            P->site_tab.push_back((uint16_t)ti);
+            P->events_per_shot += nop.p;
+            ++site;
+          }
+          ++i;
         }
         E.layer(L_NOISE, items);
-        break;
+        continue;
       }
       case OP_DET: {
         // one EMIT layer for a run of consecutive DETECTOR instructions

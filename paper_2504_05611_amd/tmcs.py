@@ -42,7 +42,8 @@ class _Spec(ctypes.Structure):
                 ("bb_l", ctypes.c_int32), ("bb_m", ctypes.c_int32),
                 ("bb_a", (ctypes.c_int32 * 2) * 3), ("bb_b", (ctypes.c_int32 * 2) * 3),
                 ("op", ctypes.c_int32), ("rounds_before", ctypes.c_int32),
-                ("rounds_after", ctypes.c_int32), ("p", ctypes.c_double), ("p_ebit", ctypes.c_double)]
+                ("rounds_after", ctypes.c_int32), ("p", ctypes.c_double), ("p_ebit", ctypes.c_double),
+                ("ebit_per_step", ctypes.c_int32), ("ebit_rate", ctypes.c_double)]
 
 
 class DecoderCfg(ctypes.Structure):
@@ -141,6 +142,8 @@ def spec_struct(spec) -> _Spec:
     s.rounds_after = spec.rounds_after
     s.p = spec.p
     s.p_ebit = spec.p_ebit
+    s.ebit_per_step = getattr(spec, "ebit_per_step", 0)
+    s.ebit_rate = getattr(spec, "ebit_rate", 0.0)
     return s
 
 

@@ -4,7 +4,7 @@ import pytest
 
 from oracle.circuits import build_circuit
 from oracle.frame import pack_bits, sample as oracle_sample
-from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc
+from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc, with_decoherence
 
 pytestmark = pytest.mark.gpu
 
@@ -15,6 +15,8 @@ CASES = [
     ("bb18-teleport", bb("bb18", TELEPORT, 2, 2, 4e-3, 1e-2)),
     ("sc5-nlcnot", WORKLOADS["sc5_nlcnot"].specs[0]),
     ("bb144-memory", bb("bb144", MEMORY, 3, 0, 2e-3)),
+    ("sc5-nlcnot-decoherence", with_decoherence(sc(5, NLCNOT, 3, 3, 1e-3, 1e-2), 0.01, False)),
+    ("bb18-teleport-decoherence-lines", with_decoherence(bb("bb18", TELEPORT, 2, 2, 4e-3, 1e-2), 0.05, True)),
 ]
 
 

@@ -11,7 +11,7 @@ import pytest
 
 from oracle.circuits import build_circuit
 from oracle.dem import build_dem
-from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc
+from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc, with_decoherence
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -39,10 +39,14 @@ def test_exports_every_declared_symbol(lib):
 
 SPECS = [sc(3, MEMORY, 3, 0), sc(3, NLCNOT, 4, 3, 1e-3, 1e-2), sc(3, TELEPORT, 4, 3),
          sc(5, NLCNOT, 5, 5, 1e-3, 1e-2), bb("bb18", NLCNOT, 4, 3), bb("bb18", TELEPORT, 4, 3),
-         bb("bb36", MEMORY, 2, 0, 2e-3)]
+         bb("bb36", MEMORY, 2, 0, 2e-3),
+         with_decoherence(sc(3, NLCNOT, 4, 3, 1e-3, 1e-2), 0.05, False),
+         with_decoherence(sc(5, NLCNOT, 3, 3, 1e-3, 1e-3), 0.02, True),
+         with_decoherence(bb("bb18", TELEPORT, 4, 3), 0.01, True)]
 
 
-@pytest.mark.parametrize("spec", SPECS, ids=lambda s: f"{s.code}{s.d if s.code == 'sc' else s.bb}-{s.op}")
+@pytest.mark.parametrize("spec", SPECS, ids=lambda s: f"{s.code}{s.d if s.code == 'sc' else s.bb}-{s.op}"
+                         + (f"-decoh{s.ebit_per_step}" if s.ebit_per_step else ""))
 def test_circuit_and_dem_match_oracle(lib, spec):
     lc = lib.Circuit(spec)
     oc = build_circuit(spec)

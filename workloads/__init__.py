@@ -50,6 +50,11 @@ class CircuitSpec:
     rounds_after: int = 0
     p: float = 1e-3
     p_ebit: float = 1e-3
+    # ebit decoherence while the n ebits are generated (Methods, Decoherence):
+    # ebit_per_step ebits are made together per generation step (0: no
+    # decoherence), ebit_rate = t_gen / T with T1 = T2 = T
+    ebit_per_step: int = 0
+    ebit_rate: float = 0.0
 
     def bb_params(self):
         return BB_CODES[self.bb]
@@ -63,6 +68,22 @@ def sc(d, op=MEMORY, rb=3, ra=0, p=1e-3, p_ebit=None):
 def bb(name, op=MEMORY, rb=3, ra=0, p=1e-3, p_ebit=None):
     return CircuitSpec(code=BB, bb=name, op=op, rounds_before=rb, rounds_after=ra,
                        p=p, p_ebit=p if p_ebit is None else p_ebit)
+
+
+def line_width(spec: CircuitSpec) -> int:
+    """Ebits generated together in the line schedule (Methods, Decoherence): d for
+    surface codes; for BB codes the divisor of n closest to d (the smaller one on
+    a tie)."""
+    if spec.code == SC:
+        return spec.d
+    n, _, d = BB_PARAMS[spec.bb]
+    divs = [f for f in range(1, n + 1) if n % f == 0]
+    return min(divs, key=lambda f: (abs(f - d), f))
+
+
+def with_decoherence(spec: CircuitSpec, rate: float, lines: bool) -> CircuitSpec:
+    """spec with ebit decoherence at t_gen / T = rate, one ebit at a time or in lines."""
+    return replace(spec, ebit_per_step=line_width(spec) if lines else 1, ebit_rate=rate)
 
 
 @dataclass(frozen=True)
