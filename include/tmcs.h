@@ -48,7 +48,7 @@ typedef enum {
 } tmcs_status;
 
 enum { TMCS_SC = 0, TMCS_BB = 1 };                                  /* code family */
-enum { TMCS_MEMORY = 0, TMCS_NONLOCAL_CNOT = 1, TMCS_TELEPORT = 2 }; /* operation */
+enum { TMCS_MEMORY = 0, TMCS_NONLOCAL_CNOT = 1, TMCS_TELEPORT = 2, TMCS_PAULI_STRING = 3 }; /* operation */
 
 /* Circuit specification.
  *  Rotated surface code [[d^2,1,d]] (Supplementary Note 2): code = TMCS_SC, d odd >= 3.
@@ -80,6 +80,13 @@ typedef struct {
    * (p_X = p_Y = p_Z = (1 - exp(-t/T)) / 4), with ebit_rate = t_gen / T. */
   int32_t ebit_per_step;
   double ebit_rate;
+  /* TMCS_PAULI_STRING (Methods, "Pauli string compute"): weight w >= 2 data blocks
+   * and one ancilla block, rounds_before rounds on all of them, then the chain of
+   * block CNOTs 1 -> 2 -> ... -> w (non-local for the 1st, 3rd, ... link, local
+   * transversal for the others) and a local CNOT w -> ancilla, each followed by
+   * one round on its two blocks; every block's Z logicals are observables (at
+   * most 64 in all).  rounds_after is ignored. */
+  int32_t weight;
 } tmcs_circuit_spec;
 
 typedef struct tmcs_circuit tmcs_circuit; /* opaque, library-owned */

@@ -47,6 +47,13 @@ circuit; Fig. 1b/1c; Table III).  Readings where the paper is silent:
 * Schedules: surface code 4 interleaved CX layers (X checks NW, NE, SW, SE;
   Z checks NW, SW, NE, SE); BB code six Z-check layers (terms of B^T, A^T)
   then six X-check layers (terms of A, B).
+* Pauli-string compute (Methods, Pauli string compute): blocks 1..w and the
+  ancilla start in |0> with rounds_before rounds on all of them; CNOT m -> m+1
+  for m = 1..w-1 is non-local for odd m and local (transversal CX with
+  DEPOLARIZE2(p)) for even m (patterns 1, 10, 101, ...), then a local CNOT
+  w -> ancilla; after every CNOT one round on its two blocks only (the other
+  blocks wait without noise); all blocks are then read out, every block's Z
+  logicals being observables.  The non-local CNOTs reuse one ebit register.
 * Qubits: block b occupies [b*(n+n_anc), (b+1)*(n+n_anc)) as data, X
   ancillas, Z ancillas; ebit pair k is (E0 + k, E0 + n + k) after the blocks.
 
@@ -60,7 +67,7 @@ import math
 
 import numpy as np
 
-from workloads import BB, CircuitSpec, MEMORY, NLCNOT, SC, TELEPORT
+from workloads import BB, CircuitSpec, MEMORY, NLCNOT, PSTRING, SC, TELEPORT
 
 from .codes import make_code
 
@@ -269,7 +276,9 @@ def build_circuit(spec: CircuitSpec) -> Circuit:
         raise ValueError("rounds_before must be >= 1")
     if spec.op in (NLCNOT, TELEPORT) and spec.rounds_after < 1:
         raise ValueError("rounds_after must be >= 1 for nlcnot/teleport")
-    nblocks = {MEMORY: 1, NLCNOT: 2, TELEPORT: 3}[spec.op]
+    if spec.op == PSTRING and spec.weight < 2:
+        raise ValueError("a Pauli string needs weight >= 2")
+    nblocks = {MEMORY: 1, NLCNOT: 2, TELEPORT: 3}.get(spec.op, spec.weight + 1)
     size = code.n + code.hx.shape[0] + code.hz.shape[0]
     blocks = [_Block(code, b * size) for b in range(nblocks)]
     e0 = nblocks * size
@@ -289,6 +298,21 @@ def build_circuit(spec: CircuitSpec) -> Circuit:
         _nonlocal_cnot(c, blocks[0], blocks[1], e0, spec)
         for _ in range(spec.rounds_after):
             _syndrome_round(c, blocks, spec)
+        _final_readout(c, blocks, spec)
+    elif spec.op == PSTRING:
+        w = spec.weight
+        for m in range(w):
+            ctl, tgt = blocks[m], blocks[m + 1]
+            if m < w - 1 and m % 2 == 0:
+                _nonlocal_cnot(c, ctl, tgt, e0, spec)
+            else:
+                cx = [q for k in range(code.n) for q in (ctl.data[k], tgt.data[k])]
+                c.add("CX", None, cx)
+                c.add("DEPOLARIZE2", spec.p, cx)
+                c.add("TICK", None, [])
+                for i in range(tgt.nz):
+                    tgt.prev[i] = _xor_lists(tgt.prev[i], ctl.prev[i])
+            _syndrome_round(c, [ctl, tgt], spec)
         _final_readout(c, blocks, spec)
     else:
         cb1, cb2, cb3 = blocks

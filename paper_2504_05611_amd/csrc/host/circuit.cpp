@@ -199,17 +199,20 @@ tmcs_status build_circuit(const tmcs_circuit_spec& s, Circuit* c) {
     return fail(TMCS_EINVAL, "p and p_ebit must lie in [0, 0.5)");
   if (s.ebit_per_step < 0 || !(s.ebit_rate >= 0.0 && s.ebit_rate < 1e300))
     return fail(TMCS_EINVAL, "ebit_per_step must be >= 0 and ebit_rate finite and >= 0");
-  if (s.op != TMCS_MEMORY && s.op != TMCS_NONLOCAL_CNOT && s.op != TMCS_TELEPORT)
+  if (s.op != TMCS_MEMORY && s.op != TMCS_NONLOCAL_CNOT && s.op != TMCS_TELEPORT && s.op != TMCS_PAULI_STRING)
     return fail(TMCS_EINVAL, "unknown operation");
+  if (s.op == TMCS_PAULI_STRING && (s.weight < 2 || s.weight > 63))
+    return fail(TMCS_EINVAL, "a Pauli string needs weight in [2, 63]");
   if (s.rounds_before < 1 || s.rounds_before > 10000)
     return fail(TMCS_EINVAL, "rounds_before must be in [1, 10000]");
-  if (s.op != TMCS_MEMORY && (s.rounds_after < 1 || s.rounds_after > 10000))
+  if ((s.op == TMCS_NONLOCAL_CNOT || s.op == TMCS_TELEPORT) && (s.rounds_after < 1 || s.rounds_after > 10000))
     return fail(TMCS_EINVAL, "rounds_after must be in [1, 10000] for nlcnot/teleport");
   tmcs_status st = make_code(s, &c->code);
   if (st != TMCS_OK) return st;
   const CodeBlock& code = c->code;
   c->spec = s;
-  const int nblocks = s.op == TMCS_MEMORY ? 1 : (s.op == TMCS_NONLOCAL_CNOT ? 2 : 3);
+  const int nblocks = s.op == TMCS_MEMORY ? 1 : s.op == TMCS_NONLOCAL_CNOT ? 2 : s.op == TMCS_TELEPORT ? 3 : s.weight + 1;
+  if ((int64_t)code.k * nblocks > 64) return fail(TMCS_EUNSUPPORTED, "more than 64 logical observables");
   const int size = code.n + code.nx + code.nz;
   std::vector<Block> blocks(nblocks);
   for (int b = 0; b < nblocks; ++b) {
@@ -240,6 +243,25 @@ tmcs_status build_circuit(const tmcs_circuit_spec& s, Circuit* c) {
     for (int r = 0; r < s.rounds_after; ++r) syndrome_round(Bd, all, code, s.p);
     final_readout(Bd, all, code, s.p);
     c->final_meas = 2 * code.n;
+  } else if (s.op == TMCS_PAULI_STRING) {
+    const int w = s.weight;
+    for (int m = 0; m < w; ++m) {
+      Block &ctl = blocks[m], &tgt = blocks[m + 1];
+      if (m < w - 1 && m % 2 == 0) {
+        nonlocal_cnot(Bd, ctl, tgt, e0, code.n, s);
+      } else {
+        std::vector<int32_t> cx;
+        for (int k = 0; k < code.n; ++k) { cx.push_back(ctl.data[k]); cx.push_back(tgt.data[k]); }
+        Bd.add(OP_CX, cx);
+        Bd.add(OP_DEP2, cx, s.p);
+        Bd.add(OP_TICK, {});
+        for (int i = 0; i < code.nz; ++i) tgt.prev[i] = sym_diff(tgt.prev[i], ctl.prev[i]);
+      }
+      std::vector<Block*> pair = {&ctl, &tgt};
+      syndrome_round(Bd, pair, code, s.p);
+    }
+    final_readout(Bd, all, code, s.p);
+    c->final_meas = nblocks * code.n;
   } else {
     Block &cb1 = blocks[0], &cb2 = blocks[1], &cb3 = blocks[2];
     std::vector<int32_t> d2(cb2.data.begin(), cb2.data.end());

@@ -23,7 +23,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 TMCS_SC, TMCS_BB = 0, 1
-TMCS_MEMORY, TMCS_NONLOCAL_CNOT, TMCS_TELEPORT = 0, 1, 2
+TMCS_MEMORY, TMCS_NONLOCAL_CNOT, TMCS_TELEPORT, TMCS_PAULI_STRING = 0, 1, 2, 3
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED",
           5: "ENONDETERMINISTIC", 6: "ENOTINSPAN"}
 INFO_KEYS = ["qubits", "gates_1q", "gates_2q", "meas", "meas_final", "detectors",
@@ -43,7 +43,8 @@ class _Spec(ctypes.Structure):
                 ("bb_a", (ctypes.c_int32 * 2) * 3), ("bb_b", (ctypes.c_int32 * 2) * 3),
                 ("op", ctypes.c_int32), ("rounds_before", ctypes.c_int32),
                 ("rounds_after", ctypes.c_int32), ("p", ctypes.c_double), ("p_ebit", ctypes.c_double),
-                ("ebit_per_step", ctypes.c_int32), ("ebit_rate", ctypes.c_double)]
+                ("ebit_per_step", ctypes.c_int32), ("ebit_rate", ctypes.c_double),
+                ("weight", ctypes.c_int32)]
 
 
 class DecoderCfg(ctypes.Structure):
@@ -137,13 +138,15 @@ def spec_struct(spec) -> _Spec:
         for k in range(3):
             s.bb_a[k][0], s.bb_a[k][1] = a[k]
             s.bb_b[k][0], s.bb_b[k][1] = b[k]
-    s.op = {"memory": TMCS_MEMORY, "nlcnot": TMCS_NONLOCAL_CNOT, "teleport": TMCS_TELEPORT}[spec.op]
+    s.op = {"memory": TMCS_MEMORY, "nlcnot": TMCS_NONLOCAL_CNOT, "teleport": TMCS_TELEPORT,
+            "pstring": TMCS_PAULI_STRING}[spec.op]
     s.rounds_before = spec.rounds_before
     s.rounds_after = spec.rounds_after
     s.p = spec.p
     s.p_ebit = spec.p_ebit
     s.ebit_per_step = getattr(spec, "ebit_per_step", 0)
     s.ebit_rate = getattr(spec, "ebit_rate", 0.0)
+    s.weight = getattr(spec, "weight", 0)
     return s
 
 

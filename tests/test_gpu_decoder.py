@@ -12,7 +12,7 @@ from oracle.circuits import build_circuit
 from oracle.dem import build_dem
 from oracle.frame import pack_bits, sample as oracle_sample, unpack_bits
 from oracle.osd import Decoder, logical_errors
-from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc, with_decoherence
+from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, pstring, sc, with_decoherence
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +23,7 @@ CASES = [
     ("bb18-nlcnot", bb("bb18", NLCNOT, 2, 2, 4e-3, 1e-2), 512 + 3, 30),
     ("bb144-memory", bb("bb144", MEMORY, 4, 0, 2e-3), 96, 20),
     ("sc3-nlcnot-decoherence", with_decoherence(sc(3, NLCNOT, 3, 3, 3e-3, 1e-2), 0.03, False), 2048 + 11, 30),
+    ("sc3-pstring4", pstring(sc(3, p=4e-3), 4, rounds=2), 1024 + 7, 30),
 ]
 
 

@@ -4,7 +4,7 @@ import pytest
 
 from oracle.circuits import build_circuit
 from oracle.frame import pack_bits, sample as oracle_sample
-from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc, with_decoherence
+from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, pstring, sc, with_decoherence
 
 pytestmark = pytest.mark.gpu
 
@@ -17,6 +17,8 @@ CASES = [
     ("bb144-memory", bb("bb144", MEMORY, 3, 0, 2e-3)),
     ("sc5-nlcnot-decoherence", with_decoherence(sc(5, NLCNOT, 3, 3, 1e-3, 1e-2), 0.01, False)),
     ("bb18-teleport-decoherence-lines", with_decoherence(bb("bb18", TELEPORT, 2, 2, 4e-3, 1e-2), 0.05, True)),
+    ("sc5-pstring5", pstring(sc(5, p=2e-3), 5, rounds=2)),
+    ("bb18-pstring4", pstring(bb("bb18", p=3e-3), 4, rounds=1)),
 ]
 
 

@@ -11,7 +11,7 @@ import pytest
 
 from oracle.circuits import build_circuit
 from oracle.dem import build_dem
-from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, sc, with_decoherence
+from workloads import MEMORY, NLCNOT, TELEPORT, WORKLOADS, bb, pstring, sc, with_decoherence
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -42,11 +42,13 @@ SPECS = [sc(3, MEMORY, 3, 0), sc(3, NLCNOT, 4, 3, 1e-3, 1e-2), sc(3, TELEPORT, 4
          bb("bb36", MEMORY, 2, 0, 2e-3),
          with_decoherence(sc(3, NLCNOT, 4, 3, 1e-3, 1e-2), 0.05, False),
          with_decoherence(sc(5, NLCNOT, 3, 3, 1e-3, 1e-3), 0.02, True),
-         with_decoherence(bb("bb18", TELEPORT, 4, 3), 0.01, True)]
+         with_decoherence(bb("bb18", TELEPORT, 4, 3), 0.01, True),
+         pstring(sc(3), 2), pstring(sc(5), 5), pstring(bb("bb18"), 4, rounds=2)]
 
 
 @pytest.mark.parametrize("spec", SPECS, ids=lambda s: f"{s.code}{s.d if s.code == 'sc' else s.bb}-{s.op}"
-                         + (f"-decoh{s.ebit_per_step}" if s.ebit_per_step else ""))
+                         + (f"-decoh{s.ebit_per_step}" if s.ebit_per_step else "")
+                         + (f"{s.weight}" if s.op == "pstring" else ""))
 def test_circuit_and_dem_match_oracle(lib, spec):
     lc = lib.Circuit(spec)
     oc = build_circuit(spec)

@@ -9,7 +9,7 @@ from oracle.circuits import build_circuit
 from oracle.dem import build_dem
 from oracle.frame import K_OF, inject
 from oracle.tableau import run
-from workloads import MEMORY, NLCNOT, TELEPORT, bb, sc
+from workloads import MEMORY, NLCNOT, PSTRING, TELEPORT, bb, pstring, sc
 
 T3 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table3.json")))
 
@@ -55,10 +55,15 @@ def _sites_kinds(c):
 
 
 SMALL = [sc(3, MEMORY, 3, 0), sc(3, NLCNOT, 2, 2), sc(3, TELEPORT, 2, 2),
-         bb("bb18", MEMORY, 2, 0), bb("bb18", NLCNOT, 1, 1), bb("bb18", TELEPORT, 1, 1)]
+         bb("bb18", MEMORY, 2, 0), bb("bb18", NLCNOT, 1, 1), bb("bb18", TELEPORT, 1, 1),
+         pstring(sc(3), 2, rounds=2), pstring(sc(3), 4, rounds=1), pstring(bb("bb18"), 3, rounds=1)]
 
 
-@pytest.mark.parametrize("spec", SMALL, ids=lambda s: f"{s.code}{s.d if s.code=='sc' else s.bb}-{s.op}")
+def _id(s):
+    return f"{s.code}{s.d if s.code == 'sc' else s.bb}-{s.op}" + (f"{s.weight}" if s.op == PSTRING else "")
+
+
+@pytest.mark.parametrize("spec", SMALL, ids=_id)
 def test_noiseless_detectors_deterministic(spec):
     """Tableau with random measurement outcomes: every detector/observable is 0."""
     c = build_circuit(spec)
@@ -68,7 +73,7 @@ def test_noiseless_detectors_deterministic(spec):
         assert rnd.any()   # the circuits do contain random outcomes
 
 
-@pytest.mark.parametrize("spec", SMALL, ids=lambda s: f"{s.code}{s.d if s.code=='sc' else s.bb}-{s.op}")
+@pytest.mark.parametrize("spec", SMALL, ids=_id)
 def test_frame_matches_tableau(spec):
     c = build_circuit(spec)
     kinds = _sites_kinds(c)
@@ -86,10 +91,12 @@ def test_frame_matches_tableau(spec):
         assert (td == fd[:, i]).all() and (to == fo[:, i]).all()
 
 
-@pytest.mark.parametrize("op", [MEMORY, NLCNOT, TELEPORT])
+@pytest.mark.parametrize("op", [MEMORY, NLCNOT, TELEPORT, PSTRING])
 def test_sc3_circuit_distance(op):
-    """Table I: the d=3 surface-code operations have circuit distance 3."""
-    spec = sc(3, op, 4 if op != MEMORY else 3, 3 if op != MEMORY else 0)
+    """Table I: the d=3 surface-code operations have circuit distance 3 (the
+    Pauli-string chain is not in Table I; it must keep distance 3 too)."""
+    spec = (pstring(sc(3), 2, rounds=2) if op == PSTRING
+            else sc(3, op, 4 if op != MEMORY else 3, 3 if op != MEMORY else 0))
     dem = build_dem(build_circuit(spec))
     assert not dem.undetectable                           # no weight-1 logical
     by = {}

@@ -17,6 +17,10 @@ Operations
     n-pair ebit layer (Methods, Non-local CNOT circuit; Fig. 1b);
   * ``teleport`` : logical teleportation CB1 -> CB3 through a logical Bell
     pair of CB2 and CB3 (Methods, State teleportation circuit; Fig. 1c).
+  * ``pstring``  : Pauli-string parity of weight w (Methods, Pauli string
+    compute): w data blocks and an ancilla, a chain of block CNOTs
+    1 -> 2 -> ... -> w alternating non-local (first) and local, then a local
+    CNOT w -> ancilla, one round on the two blocks after every CNOT.
 """
 from __future__ import annotations
 
@@ -36,7 +40,7 @@ BB_CODES = {
 BB_PARAMS = {"bb18": (18, 4, 4), "bb36": (36, 4, 6), "bb54": (54, 4, 8),
              "bb90": (90, 8, 10), "bb144": (144, 12, 12)}
 
-MEMORY, NLCNOT, TELEPORT = "memory", "nlcnot", "teleport"
+MEMORY, NLCNOT, TELEPORT, PSTRING = "memory", "nlcnot", "teleport", "pstring"
 SC, BB = "sc", "bb"
 
 
@@ -55,6 +59,7 @@ class CircuitSpec:
     # decoherence), ebit_rate = t_gen / T with T1 = T2 = T
     ebit_per_step: int = 0
     ebit_rate: float = 0.0
+    weight: int = 0                 # pstring: number of data blocks w (>= 2)
 
     def bb_params(self):
         return BB_CODES[self.bb]
@@ -68,6 +73,13 @@ def sc(d, op=MEMORY, rb=3, ra=0, p=1e-3, p_ebit=None):
 def bb(name, op=MEMORY, rb=3, ra=0, p=1e-3, p_ebit=None):
     return CircuitSpec(code=BB, bb=name, op=op, rounds_before=rb, rounds_after=ra,
                        p=p, p_ebit=p if p_ebit is None else p_ebit)
+
+
+def pstring(code_spec: CircuitSpec, w: int, rounds=4) -> CircuitSpec:
+    """Pauli-string compute of weight w on copies of code_spec's code (Methods:
+    four rounds on every block first; ebit noise equal to the PER)."""
+    return replace(code_spec, op=PSTRING, weight=w, rounds_before=rounds, rounds_after=1,
+                   p_ebit=code_spec.p)
 
 
 def line_width(spec: CircuitSpec) -> int:
@@ -116,6 +128,10 @@ WORKLOADS = {
         "bb144_teleport", (bb("bb144", TELEPORT, 4, 3, 1e-3, 1e-2),), 1_000_000, 1, 20,
         "teleportation of a BB [[144,12,12]] block, 144 ebits, 4/4/4 + 3 rounds, "
         "p=1e-3, p_ebit=1e-2"),
+    "sc5_pstring": Workload(
+        "sc5_pstring", tuple(pstring(sc(5, p=1e-3), w) for w in (2, 3, 4, 5, 6)), 1_000_000, 1, 30,
+        "Pauli-string compute of weight w = 2..6 on SC d=5 blocks (chain patterns 1, 10, 101, 1010, "
+        "10101), 4 rounds first, one round after each CNOT, p = p_ebit = 1e-3"),
     "sc_nlcnot_mixed": Workload(
         "sc_nlcnot_mixed",
         tuple(sc(d, NLCNOT, d, d, p, 10 * p) for d in (11, 15, 21, 29)
