@@ -168,6 +168,13 @@ typedef struct {
   int32_t osd_per_cu;       /* resident OSD workgroups per compute unit */
   int32_t bp_global_state;  /* 1: keep each shot's BP state in device memory instead of LDS
                                (automatic when it exceeds the 160 KB LDS of a compute unit) */
+  int32_t osd_order;        /* 0: OSD-0.  1..64: OSD-CS of this order (combination sweep,
+                               Roffe et al. 2020; the paper's BP-OSD uses order 7): after the
+                               full information set S, every weight-1 flip of the other
+                               columns T and every weight-2 flip among T's first osd_order
+                               columns; the solution of least soft weight sum L_v over its
+                               support wins (FP32, ties to the earlier candidate).  Dense
+                               elimination only (<= 2048 detectors, <= 16384 columns) */
   int32_t osd_window;       /* 0: dense OSD-0 when H fits (<= 2048 detectors, <= 16384 columns),
                                windowed otherwise; 1..2048: always windowed, with at most this
                                many detectors in a window.  A window holds the first sorted

@@ -87,11 +87,94 @@ def osd0(cols, rank_h: int, synd_bits, llr):
     return e, kept, s == 0
 
 
+def osd_cs(cols, rank_h: int, synd_bits, llr, order: int):
+    """OSD-CS of order lambda (Roffe, White, Burton, Campbell 2020, "combination
+    sweep"; the higher-order OSD the paper's BP-OSD runs with order 7).
+
+    The information set S is the first rank(H) GF(2)-independent columns in
+    (L_v, v) order, and T the other columns in that order.  Candidates: the
+    OSD-0 solution (e_T = 0), then e_T of weight one over all of T, then e_T of
+    weight two over the first `order` columns of T (pairs a < b in order); for
+    each, e_S solves H_S e_S = s + H_T e_T.  The one with the least soft weight
+    sum_{e_i = 1} L_i wins; the soft weight is summed in FP32, over S in order of
+    selection and then the flipped T columns in order, and a later candidate
+    must be strictly lighter.  Returns (e_hat bool[n], in_span flag).
+    """
+    n = len(cols)
+    llr = np.asarray(llr, dtype=np.float32)
+    order_v = np.lexsort((np.arange(n), llr))
+    basis = {}
+    kept, rest = [], []
+    for v in order_v:
+        v = int(v)
+        if len(kept) < rank_h:
+            vec, combo = cols[v], 1 << len(kept)
+            while vec:
+                hb = vec.bit_length() - 1
+                if hb not in basis:
+                    break
+                bv, bc = basis[hb]
+                vec ^= bv
+                combo ^= bc
+            if vec:
+                basis[vec.bit_length() - 1] = (vec, combo)
+                kept.append(v)
+                continue
+        rest.append(v)
+
+    def rep(x):
+        """Kept columns whose sum is the column vector x (x must be in the span)."""
+        combo = 0
+        while x:
+            hb = x.bit_length() - 1
+            if hb not in basis:
+                return None
+            bv, bc = basis[hb]
+            x ^= bv
+            combo ^= bc
+        return combo
+
+    e_s = rep(vec_int(synd_bits))
+    if e_s is None:
+        e, _, _ = osd0(cols, rank_h, synd_bits, llr)
+        return e, False
+
+    def weight(combo, extra):
+        c = np.float32(0.0)
+        for i in range(len(kept)):
+            if (combo >> i) & 1:
+                c = np.float32(c + llr[kept[i]])
+        for j in extra:
+            c = np.float32(c + llr[j])
+        return c
+
+    best = (weight(e_s, []), e_s, [])
+    for j in rest:
+        r = rep(cols[j])
+        cand = (weight(e_s ^ r, [j]), e_s ^ r, [j])
+        if cand[0] < best[0]:
+            best = cand
+    head = rest[:order]
+    for a in range(len(head)):
+        for b in range(a + 1, len(head)):
+            r = rep(cols[head[a]]) ^ rep(cols[head[b]])
+            cand = (weight(e_s ^ r, [head[a], head[b]]), e_s ^ r, [head[a], head[b]])
+            if cand[0] < best[0]:
+                best = cand
+    e = np.zeros(n, dtype=bool)
+    for i, v in enumerate(kept):
+        if (best[1] >> i) & 1:
+            e[v] = True
+    for j in best[2]:
+        e[j] = True
+    return e, True
+
+
 class Decoder:
     """BP-OSD over one DEM (H, priors, L)."""
 
     def __init__(self, H, priors, L, max_iter=30, alpha=1.0, weights=None,
-                 dtype=np.float64, use_osd=True):
+                 dtype=np.float64, use_osd=True, osd_order=0):
         self.H = np.asarray(H, dtype=np.uint8)
         self.priors = np.asarray(priors, dtype=np.float64)
         self.L = np.asarray(L, dtype=np.uint8)
@@ -100,6 +183,7 @@ class Decoder:
         self.weights = weights
         self.dtype = dtype
         self.use_osd = use_osd
+        self.osd_order = osd_order
         self.graph = Graph(self.H)
         self.cols = column_ints(self.H)
         self.rank = gf2_rank(self.H)
@@ -122,7 +206,10 @@ class Decoder:
             if not self.use_osd:
                 continue
             for i in np.nonzero(~r["converged"])[0]:
-                e, _, ok = osd0(self.cols, self.rank, synd[a + i], r["llr"][i])
+                if self.osd_order > 0:
+                    e, ok = osd_cs(self.cols, self.rank, synd[a + i], r["llr"][i], self.osd_order)
+                else:
+                    e, _, ok = osd0(self.cols, self.rank, synd[a + i], r["llr"][i])
                 out_e[a + i] = e
                 out["osd"][a + i] = True
                 out["in_span"][a + i] = ok

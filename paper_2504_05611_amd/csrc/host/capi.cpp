@@ -137,6 +137,7 @@ tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg, const ui
   if (cfg->max_iter < 1 || cfg->max_iter > 100000) return fail(TMCS_EINVAL, "max_iter must be in [1, 100000]");
   if (!std::isfinite(cfg->alpha) || cfg->alpha <= 0.0f) return fail(TMCS_EINVAL, "alpha must be positive");
   if (cfg->osd_window < 0 || cfg->osd_window > 2048) return fail(TMCS_EINVAL, "osd_window must be in [0, 2048]");
+  if (cfg->osd_order < 0 || cfg->osd_order > 64) return fail(TMCS_EINVAL, "osd_order must be in [0, 64]");
   TMCS_TRY({
     return decode_run(d->d, *cfg, det_dev, n_shots, pred_obs_dev, stats_dev, (hipStream_t)stream);
   })

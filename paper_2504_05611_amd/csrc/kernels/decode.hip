@@ -400,6 +400,7 @@ struct OSDArgs {
   const int32_t* jobs;       // nullable: job j is jobs[j] (a retry pass), else j
   int32_t cnt_total, cnt_next;   // counters[] holding the number of jobs and the next job
   int32_t* retry;            // PFX: jobs whose prefix did not span s (counted in counters[4])
+  int32_t order;             // > 0: OSD-CS of this order (dense variants only)
 };
 
 constexpr int32_t WIN_NONE = 0x7FFFFFFF;   // rowmap: row not touched by the window
@@ -551,11 +552,14 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
   // (an offset from sm, not an integer cast, so that the compiler keeps LDS addressing)
   const size_t acc_off = ((size_t)((unsigned char*)(srow + cap_m) - sm) + 7) & ~(size_t)7;
   uint64_t* acc = (uint64_t*)(sm + acc_off);                       // [W] solve accumulator
+  uint32_t* tk = (uint32_t*)(acc + W);                             // OSD-CS: [npad / 32] kept sorted positions
   // WIN: after the sort, keys holds npad u32 column indices followed by npad
   // per-position counts (then exclusive offsets) of newly touched rows
   int32_t* pcnt = (int32_t*)keys + a.npad;
   __shared__ int s_job, s_r, s_ns, s_inc;
   __shared__ uint64_t s_red;
+  __shared__ unsigned long long s_best;     // OSD-CS: (order key of the soft weight, candidate rank)
+  __shared__ int s_tpos[64], s_nt, s_f1, s_f2;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   uint64_t* B = BL ? lbasis : a.basis + (int64_t)blockIdx.x * cap_r * W;
@@ -601,6 +605,8 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
     if constexpr (!WIN && !PFX) {
       // 1. sort columns by (L_v, v); list the syndrome's rows
       for (int r = tid; r < a.m; r += NT) prow[r] = -1;
+      if (a.order > 0)
+        for (int i = tid; i < (a.npad >> 5); i += NT) tk[i] = 0u;
       for (int wd = tid; wd < a.mw; wd += NT) {
         uint64_t x = a.synd[ls * a.mw + wd];
         if (x) {
@@ -821,6 +827,7 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
               pivot[r] = p;
               kept[r] = col;
               prow[p] = r;
+              if (!WIN && !PFX && a.order > 0) atomicOr(&tk[idx >> 5], 1u << (idx & 31));
             }
             const uint64_t mask = (lane > j) ? 0ull - bit_of<MW, W>(v, p) : 0ull;
 #pragma unroll
@@ -892,7 +899,7 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
       // full information set are independent, so s has exactly one
       // representation over them; the one found here (zero on the columns not
       // yet kept) is it, and the rest of the scan could only add zeros.
-      if (!reduce_syndrome()) break;
+      if ((WIN || PFX || a.order == 0) && !reduce_syndrome()) break;
     }
     // 3. solve: s reduced by the basis vectors pivoted on rows of s
     const int r = s_r;
@@ -905,6 +912,96 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
       if (tid == 0) a.retry[atomicAdd(&a.counters[4], 1)] = job;
       __syncthreads();
       continue;
+    }
+    if constexpr (!WIN && !PFX) {
+      if (tid == 0) { s_f1 = -1; s_f2 = -1; }
+      if (a.order > 0 && !not_in_span) {
+        // OSD-CS: T = sorted positions not kept; candidates e_T of weight one over
+        // T and of weight two over T's first `order` positions.  The soft weight of
+        // a candidate sums L over e_S + rep(e_T) (kept columns in order of
+        // selection) and then over e_T; the lightest wins, ties to the earlier.
+        auto col_at = [&](int p) -> int {
+          return BL ? (int)((const uint32_t*)keys)[p] : (int)(keys[p] & 0xFFFFFFFFu);
+        };
+        auto weight = [&](int c1, int c2) -> float {
+          uint64_t x[RW];
+#pragma unroll
+          for (int w = 0; w < RW; ++w) x[w] = acc[MW + w];
+          for (int q = 0; q < 2; ++q) {
+            const int cc = q ? c2 : c1;
+            if (cc < 0) continue;
+            for (int32_t k = a.col_ptr[cc]; k < a.col_ptr[cc + 1]; ++k) {
+              const int pi = prow[a.csc_row[k]];
+              if (pi >= 0) {
+                const uint64_t* bp = B + (int64_t)pi * W + MW;
+#pragma unroll
+                for (int w = 0; w < RW; ++w) x[w] ^= bp[w];
+              }
+            }
+          }
+          float c = 0.0f;
+#pragma unroll
+          for (int w = 0; w < RW; ++w)
+            for (uint64_t y = x[w]; y; y &= y - 1) c = __fadd_rn(c, L[kept[w * 64 + (__ffsll((unsigned long long)y) - 1)]]);
+          if (c1 >= 0) c = __fadd_rn(c, L[c1]);
+          if (c2 >= 0) c = __fadd_rn(c, L[c2]);
+          return c;
+        };
+        auto pair_of = [](int q, int nt, int* pa, int* pb) {
+          int a0 = 0;
+          while (q >= nt - 1 - a0) { q -= nt - 1 - a0; ++a0; }
+          *pa = a0;
+          *pb = a0 + 1 + q;
+        };
+        if (tid == 0) {
+          int cnt = 0;
+          for (int p = 0; p < n_loc && cnt < a.order; ++p)
+            if (!((tk[p >> 5] >> (p & 31)) & 1u)) s_tpos[cnt++] = p;
+          s_nt = cnt;
+          s_best = ((unsigned long long)order_key(weight(-1, -1)) << 32);   // OSD-0 itself, rank 0
+        }
+        __syncthreads();
+        unsigned long long best = ~0ull;
+        for (int p = tid; p < n_loc; p += NT) {
+          if ((tk[p >> 5] >> (p & 31)) & 1u) continue;
+          const unsigned long long key = ((unsigned long long)order_key(weight(col_at(p), -1)) << 32) | (uint32_t)(1 + p);
+          best = key < best ? key : best;
+        }
+        const int nt = s_nt, npairs = nt * (nt - 1) / 2;
+        for (int q = tid; q < npairs; q += NT) {
+          int ia, ib;
+          pair_of(q, nt, &ia, &ib);
+          const unsigned long long key = ((unsigned long long)order_key(weight(col_at(s_tpos[ia]), col_at(s_tpos[ib]))) << 32)
+                                         | (uint32_t)(1 + a.npad + q);
+          best = key < best ? key : best;
+        }
+        atomicMin(&s_best, best);
+        __syncthreads();
+        if (tid == 0) {
+          const uint32_t rk = (uint32_t)(s_best & 0xFFFFFFFFu);
+          int c1 = -1, c2 = -1;
+          if (rk >= 1 && rk <= (uint32_t)a.npad) {
+            c1 = col_at((int)rk - 1);
+          } else if (rk > (uint32_t)a.npad) {
+            int ia, ib;
+            pair_of((int)rk - 1 - a.npad, nt, &ia, &ib);
+            c1 = col_at(s_tpos[ia]);
+            c2 = col_at(s_tpos[ib]);
+          }
+          for (int q = 0; q < 2; ++q) {
+            const int cc = q ? c2 : c1;
+            if (cc < 0) continue;
+            for (int32_t k = a.col_ptr[cc]; k < a.col_ptr[cc + 1]; ++k) {
+              const int pi = prow[a.csc_row[k]];
+              if (pi >= 0)
+                for (int w = 0; w < RW; ++w) acc[MW + w] ^= B[(int64_t)pi * W + MW + w];
+            }
+          }
+          s_f1 = c1;
+          s_f2 = c2;
+        }
+        __syncthreads();
+      }
     }
     uint64_t pm = 0;
     if (incomplete) {
@@ -924,6 +1021,16 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
           pm ^= a.obs_mask[col];
           if (a.ehat) a.ehat[shot * a.n + col] = 1;
         }
+      }
+      if constexpr (!WIN && !PFX) {
+        // OSD-CS: the flipped columns outside the information set
+        if (tid == 0)
+          for (int q = 0; q < 2; ++q) {
+            const int cc = q ? s_f2 : s_f1;
+            if (cc < 0) continue;
+            pm ^= a.obs_mask[cc];
+            if (a.ehat) a.ehat[shot * a.n + cc] = 1;
+          }
       }
     }
     pm = block_xor_u64(pm, &s_red);
@@ -1249,8 +1356,11 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   while (npad < D.cols) npad <<= 1;
   if (cfg.osd_window < 0 || cfg.osd_window > WIN_MAX_ROWS)
     return fail(TMCS_EINVAL, "osd_window must be in [0, 2048]");
+  if (cfg.osd_order < 0 || cfg.osd_order > 64) return fail(TMCS_EINVAL, "osd_order must be in [0, 64]");
   // dense OSD-0 while H fits its registers and sort, windowed beyond (or on request)
   const bool osd_win = cfg.use_osd && (cfg.osd_window > 0 || npad > OSD_MAX_KEYS || mw > 32);
+  if (osd_win && cfg.osd_order > 0)
+    return fail(TMCS_EUNSUPPORTED, "OSD-CS needs the dense elimination (<= 2048 detectors, <= 16384 columns)");
   const int cus = device_cus();
   // BP launch shape: one team (workgroup) per shot in flight, state in LDS
   const size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (size_t)d->E4 + 4;
@@ -1288,7 +1398,9 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int osd_rank = osd_win ? WIN_MAX_ROWS : D.rank;
   const int osd_rows = osd_win ? WIN_MAX_ROWS : D.rows;
   if (osd_win) npad = WIN_KEYS;
-  size_t osd_lds = (size_t)npad * 8 + (size_t)osd_rank * 8 + (size_t)osd_rows * 8 + (size_t)W * 8 + 64;
+  // (+ the OSD-CS bitset of kept sorted positions after the accumulator)
+  size_t osd_lds = (size_t)npad * 8 + (size_t)osd_rank * 8 + (size_t)osd_rows * 8 + (size_t)W * 8 + 64 +
+                   (cfg.osd_order > 0 ? (size_t)npad / 8 + 16 : 0);
   // small DEMs keep the elimination basis in LDS as well (at least two workgroups
   // per CU); their sorted keys are stored as 32-bit column indices
   const size_t basis_bytes = (size_t)std::max(osd_rank, 1) * W * 8;
@@ -1297,7 +1409,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   // dense OSD-0 on a DEM wider than the prefix: prefix pass, then a full sort of the rest
   const int pfx_keys = osd_bl ? PFX_KEYS_WAVE : PFX_KEYS_WG;
   // (the one-wave variant gathers 8-byte keys over its 4-byte index area and the LDS basis after it)
-  const bool osd_pfx = cfg.use_osd && !osd_win && D.cols >= pfx_keys &&
+  const bool osd_pfx = cfg.use_osd && !osd_win && cfg.osd_order == 0 && D.cols >= pfx_keys &&
                        (!osd_bl || basis_bytes >= (size_t)pfx_keys * 4);
   size_t pfx_lds = (size_t)pfx_keys * 8 + (size_t)osd_rank * 8 + (size_t)osd_rows * 8 + (size_t)W * 8 + 64;
   if (osd_bl) pfx_lds += basis_bytes - (size_t)pfx_keys * 4;
@@ -1373,7 +1485,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
       o.pred = pred; o.nobs = D.nobs; o.stats = stats; o.ehat = cfg.ehat_dev; o.flags = cfg.flags_dev;
       o.npad = npad;
       o.rowmap = d->rowmap; o.win_rows = cfg.osd_window > 0 ? cfg.osd_window : WIN_MAX_ROWS;
-      o.jobs = nullptr; o.cnt_total = 2; o.cnt_next = 3; o.retry = nullptr;
+      o.jobs = nullptr; o.cnt_total = 2; o.cnt_next = 3; o.retry = nullptr; o.order = cfg.osd_order;
       if (osd_win) {
         st = launch_osd_win(o, osd_grid, osd_lds, stream);
       } else if (osd_pfx) {

@@ -52,7 +52,8 @@ class DecoderCfg(ctypes.Structure):
                 ("weights_dev", ctypes.c_void_p), ("use_osd", ctypes.c_int32),
                 ("bp_threads", ctypes.c_int32), ("bp_per_cu", ctypes.c_int32),
                 ("osd_per_cu", ctypes.c_int32), ("bp_global_state", ctypes.c_int32),
-                ("osd_window", ctypes.c_int32), ("ehat_dev", ctypes.c_void_p),
+                ("osd_order", ctypes.c_int32), ("osd_window", ctypes.c_int32),
+                ("ehat_dev", ctypes.c_void_p),
                 ("llr_dev", ctypes.c_void_p), ("iters_dev", ctypes.c_void_p),
                 ("flags_dev", ctypes.c_void_p)]
 
@@ -247,10 +248,10 @@ class DEM:
         return H
 
     def decode(self, det, n_shots, pred, *, max_iter=30, alpha=1.0, weights=None, use_osd=True,
-               bp_threads=0, bp_per_cu=0, osd_per_cu=0, bp_global_state=0, osd_window=0, ehat=None,
-               llr=None, iters=None, flags=None, stats=None, stream=None):
+               bp_threads=0, bp_per_cu=0, osd_per_cu=0, bp_global_state=0, osd_order=0, osd_window=0,
+               ehat=None, llr=None, iters=None, flags=None, stats=None, stream=None):
         cfg = DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads,
-                         bp_per_cu, osd_per_cu, bp_global_state, osd_window,
+                         bp_per_cu, osd_per_cu, bp_global_state, osd_order, osd_window,
                          _ptr(ehat), _ptr(llr), _ptr(iters), _ptr(flags))
         _check(_lib.tmcs_decode(self._h, ctypes.byref(cfg), _ptr(det), n_shots, _ptr(pred), _ptr(stats),
                                 _stream(stream)))
@@ -272,9 +273,9 @@ class DEM:
 
 
 def make_cfg(max_iter=30, alpha=1.0, weights=None, use_osd=True, bp_threads=0, bp_per_cu=0,
-             osd_per_cu=0, bp_global_state=0, osd_window=0):
+             osd_per_cu=0, bp_global_state=0, osd_order=0, osd_window=0):
     return DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads, bp_per_cu,
-                      osd_per_cu, bp_global_state, osd_window, None, None, None, None)
+                      osd_per_cu, bp_global_state, osd_order, osd_window, None, None, None, None)
 
 
 def autotune(dem, det, n_shots, cfg=None, stream=None) -> DecoderCfg:

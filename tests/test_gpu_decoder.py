@@ -212,3 +212,41 @@ def test_osd_prefix_retry_matches_oracle(gpu_lib):
     late = sum(_early_stop(cols, synd[i], L[i])[0] >= 127 for i in np.nonzero(flags.cpu().numpy() & 2)[0])
     print(f"[osd-prefix] osd {st['osd']} retried {st['osd_prefix_retry']} early stops past 127: {late}", flush=True)
     assert late > 0 and st["osd_prefix_retry"] >= late
+
+
+@pytest.mark.parametrize("name,spec,shots", [
+    ("sc5-nlcnot", sc(5, NLCNOT, 3, 3, 4e-3, 2e-2), 1024 + 3),
+    ("bb18-nlcnot", bb("bb18", NLCNOT, 2, 2, 4e-3, 1e-2), 512 + 5),
+], ids=["sc5-nlcnot", "bb18-nlcnot"])
+def test_osd_cs_matches_oracle(gpu_lib, name, spec, shots):
+    """OSD-CS of order 7 (the paper's BP-OSD order) against the oracle's: every
+    correction and prediction equal, on oracle-sampled syndromes."""
+    import torch
+    T = 30
+    print(f"[osd-cs] {name} shots={shots}", flush=True)
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    det, obs = _oracle_det(spec, shots)
+    outs = []
+    for order in (7, 0):
+        pred = torch.zeros_like(obs)
+        ehat = torch.zeros((shots, dem.cols), dtype=torch.uint8, device="cuda")
+        flags = torch.zeros(shots, dtype=torch.uint8, device="cuda")
+        dem.decode(det, shots, pred, max_iter=T, ehat=ehat, flags=flags, osd_order=order)
+        pred2 = torch.zeros_like(obs)
+        dem.decode(det, shots, pred2, max_iter=T, osd_order=order)          # compacted path
+        torch.cuda.synchronize()
+        outs.append((ehat.cpu().numpy().astype(bool), pred.cpu().numpy(), pred2.cpu().numpy(), flags.cpu().numpy()))
+    e_cs, p_cs, p2_cs, flags = outs[0]
+    assert (p2_cs == p_cs).all()
+    oc = build_circuit(spec)
+    od = build_dem(oc)
+    synd = unpack_bits(det.cpu().numpy().view(np.uint64), shots).T
+    o = Decoder(od.H(), od.priors(), od.L(), max_iter=T, dtype=np.float32, osd_order=7).decode(synd, chunk=64)
+    assert (e_cs == o["e_hat"]).all()
+    assert (unpack_bits(p_cs.view(np.uint64), shots).T[:, : od.L().shape[0]] == o["pred_obs"]).all()
+    assert ((e_cs.astype(np.int64) @ od.H().T.astype(np.int64)) % 2 == synd).all()
+    osd = (flags & 2).astype(bool)
+    changed = (e_cs != outs[1][0]).any(axis=1)
+    print(f"[osd-cs] {name}: OSD shots {int(osd.sum())}, corrections changed by CS {int(changed.sum())}", flush=True)
+    assert osd.sum() > 10 and changed.sum() > 0 and not (changed & ~osd).any()

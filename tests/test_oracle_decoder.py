@@ -7,7 +7,7 @@ import pytest
 from oracle.bp import decode_bp, prior_llr
 from oracle.codes import rank, surface_code
 from oracle.ml import expected_ler, ml_ler
-from oracle.osd import Decoder, column_ints, logical_errors, osd0
+from oracle.osd import osd_cs, Decoder, column_ints, logical_errors, osd0
 
 
 def _tree_H(rng, n_checks):
@@ -141,6 +141,50 @@ def test_osd0_exhaustive_small():
         sols = [x for x in itertools.product([0, 1], repeat=len(kept))
                 if ((H[:, kept].astype(int) @ np.array(x)) % 2 == s).all()]
         assert len(sols) == 1 and tuple(e[kept].astype(int)) == sols[0]
+
+
+@pytest.mark.parametrize("seed,lam", [(0, 3), (1, 7), (2, 7), (3, 40)])
+def test_osd_cs_picks_the_lightest_candidate(seed, lam):
+    """OSD-CS against its definition, restated with dense algebra: information
+    set from GF(2) ranks, every candidate solved by Gauss-Jordan, soft weights in
+    FP32 (S in selection order, then the flipped T columns), strict minimum."""
+    rng = np.random.default_rng(100 + seed)
+    m, n = 14, 30
+    H = (rng.random((m, n)) < 0.2).astype(np.uint8)
+    H[rng.integers(m), :] = 0
+    r = rank(H)
+    cols = column_ints(H)
+    for trial in range(6):
+        s = (H.astype(int) @ (rng.random(n) < 0.15)) % 2
+        llr = rng.normal(size=n).astype(np.float32)
+        order = sorted(range(n), key=lambda v: (llr[v], v))
+        S = []
+        for v in order:
+            if len(S) < r and rank(H[:, S + [v]]) > len(S):
+                S.append(v)
+        T = [v for v in order if v not in S]
+        cands = [[]] + [[j] for j in T] + [[T[a], T[b]] for a in range(min(lam, len(T)))
+                                           for b in range(a + 1, min(lam, len(T)))]
+        best = None
+        for c in cands:
+            rhs = (s + H[:, c].sum(axis=1)) % 2
+            x = _gauss_jordan_solve(H[:, S], rhs)
+            w = np.float32(0.0)
+            for i, v in enumerate(S):
+                if x[i]:
+                    w = np.float32(w + llr[v])
+            for j in c:
+                w = np.float32(w + llr[j])
+            if best is None or w < best[0]:
+                e = np.zeros(n, dtype=bool)
+                e[np.array(S)[x.astype(bool)]] = True
+                e[c] = True
+                best = (w, e)
+        e, ok = osd_cs(cols, r, s, llr, lam)
+        assert ok and ((H.astype(int) @ e) % 2 == s).all()
+        assert (e == best[1]).all(), (seed, trial)
+        e0, _, _ = osd0(cols, r, s, llr)
+        assert llr[e].sum(dtype=np.float64) <= llr[e0].sum(dtype=np.float64) + 1e-4
 
 
 def _rep_code_phenomenological(d, rounds):
