@@ -136,6 +136,18 @@ tmcs_status tmcs_dem_info(const tmcs_dem* d, int64_t info[TMCS_DEM_INFO_LEN]);
 tmcs_status tmcs_dem_export(const tmcs_dem* d, int32_t* col_ptr, int32_t* row_idx,
                             double* priors, uint64_t* obs_mask);
 
+/* Circuit-level distance search (Results, "Circuit-level distance of distributed
+ * primitives"; Table I lists upper bounds): *weight receives the fewest DEM
+ * mechanisms found whose detector flips cancel while an observable flips, or 0
+ * when none is found with at most max_weight mechanisms, intermediate sets of
+ * at most max_active detection events and at most max_states search states.
+ * Breadth-first over (active detection events, observable mask), growing a state
+ * only by mechanisms on its smallest active detector; exact when max_active is
+ * at least the number of detectors and the state budget suffices, an upper
+ * bound otherwise.  Host only. */
+tmcs_status tmcs_dem_distance(const tmcs_dem* d, int32_t max_active, int32_t max_weight,
+                              int64_t max_states, int32_t* weight);
+
 /* Sample n_shots shots [shot_begin, shot_begin + n_shots) of circuit c.
  * Noise: Philox4x32-10 with key (seed lo, seed hi) and counter (block, site,
  * instance, call) draws the events of each noise site per 4096-shot block; a draw

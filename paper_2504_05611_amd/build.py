@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtmcs.so")
 
 SOURCES = [
-    "host/capi.cpp", "host/codes.cpp", "host/circuit.cpp", "host/dem.cpp", "host/program.cpp", "host/timing.cpp",
+    "host/capi.cpp", "host/codes.cpp", "host/circuit.cpp", "host/dem.cpp", "host/program.cpp", "host/timing.cpp", "host/distance.cpp",
     "kernels/sample.hip", "kernels/decode.hip", "kernels/wbp.hip", "kernels/plan.hip",
 ]
 

@@ -111,6 +111,12 @@ tmcs_status tmcs_dem_info(const tmcs_dem* d, int64_t info[TMCS_DEM_INFO_LEN]) {
   return TMCS_OK;
 }
 
+tmcs_status tmcs_dem_distance(const tmcs_dem* d, int32_t max_active, int32_t max_weight, int64_t max_states,
+                              int32_t* weight) {
+  if (!d || !weight || max_active < 1 || max_weight < 1 || max_states < 1) return fail(TMCS_EINVAL, "invalid argument");
+  TMCS_TRY({ return dem_distance(d->d, max_active, max_weight, max_states, weight); })
+}
+
 tmcs_status tmcs_dem_export(const tmcs_dem* d, int32_t* col_ptr, int32_t* row_idx, double* priors,
                             uint64_t* obs_mask) {
   if (!d) return fail(TMCS_EINVAL, "null dem");

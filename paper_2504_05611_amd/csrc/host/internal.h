@@ -73,6 +73,7 @@ struct Dem {
   void* device = nullptr;                     // decoder-side device copy (decode.hip)
 };
 tmcs_status build_dem(const Circuit& c, Dem* d);
+tmcs_status dem_distance(const Dem& D, int max_active, int max_weight, int64_t max_states, int32_t* weight);
 
 // Probability of one independent mechanism of a channel (shared by the DEM
 // builder; definitions in dem.cpp).

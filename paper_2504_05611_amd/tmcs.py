@@ -80,6 +80,7 @@ _SIGS = {
     "tmcs_free_dem": [_vp],
     "tmcs_dem_info": [_vp, ctypes.POINTER(ctypes.c_int64)],
     "tmcs_dem_export": [_vp, _vp, _vp, _vp, _vp],
+    "tmcs_dem_distance": [_vp, _i32, _i32, ctypes.c_int64, ctypes.POINTER(_i32)],
     "tmcs_sample": [_vp, _u64, _u32, _u64, _u64, _vp, _vp, _vp],
     "tmcs_decode": [_vp, ctypes.POINTER(DecoderCfg), _vp, _u64, _vp, _vp, _vp],
     "tmcs_logical_error_rate": [_vp, _vp, _u32, _u64, ctypes.POINTER(_u64),
@@ -230,6 +231,13 @@ class DEM:
     @property
     def edges(self):
         return self.info["edges"]
+
+    def distance(self, max_active=8, max_weight=16, max_states=20_000_000) -> int:
+        """Fewest mechanisms found forming an undetectable logical error (0: none
+        within the limits); exact when max_active >= rows and the budget suffices."""
+        w = ctypes.c_int32()
+        _check(_lib.tmcs_dem_distance(self._h, max_active, max_weight, max_states, ctypes.byref(w)))
+        return w.value
 
     def export(self) -> DemHost:
         n, e = self.info["cols"], self.info["edges"]

@@ -90,3 +90,33 @@ def test_invalid_specs_are_rejected(lib):
         lib.Circuit(sc(3, NLCNOT, 3, 0))                       # no rounds after the CNOT
     with pytest.raises(lib.TmcsError):
         lib.Circuit(sc(3, MEMORY, 3, 0, p=0.7))
+
+
+def test_distance_search_is_exact_on_a_small_dem(lib):
+    """With no cap on the active detection events the search returns the minimum
+    weight of an undetectable logical error: brute force over all sets of up to
+    three mechanisms of the d = 3 memory DEM (55 columns)."""
+    import itertools
+    d = lib.DEM(lib.Circuit(sc(3, MEMORY, 3, 0)))
+    H = d.H().astype(np.int64)
+    om = d.export().obs_mask
+    best = None
+    for w in (1, 2, 3):
+        for cs in itertools.combinations(range(d.cols), w):
+            if not (H[:, list(cs)].sum(axis=1) % 2).any() and np.bitwise_xor.reduce(om[list(cs)]):
+                best = w
+                break
+        if best:
+            break
+    assert best == 3
+    assert d.distance(max_active=d.rows, max_weight=6) == best
+
+
+@pytest.mark.parametrize("op", ["nlcnot", "teleport"])
+@pytest.mark.parametrize("key", ["sc3", "sc5", "sc7"])
+def test_distance_search_matches_table1(lib, key, op):
+    import json
+    t1 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1.json")))
+    spec = sc(int(key[2:]), NLCNOT if op == "nlcnot" else TELEPORT, 4, 3)
+    d = lib.DEM(lib.Circuit(spec))
+    assert d.distance(max_active=6, max_weight=12, max_states=5_000_000) == t1[op][key]
