@@ -38,16 +38,16 @@ EVENT_APPLY_OPS = 4
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch,
 # averaged over the dispatches of a --steps 1 --warmup 1 run of this workload),
 # scaled by what the counters read for a plain 1 GiB device copy.  Valid only for
-# the kernel source they were taken on: the SHA-256 of that source file must match.
+# the sources they were taken on: the SHA-256 of those files, in order, must match.
 # Commands and raw figures: profiles/hbm_traffic_sc5_nlcnot.md
 TRAFFIC = {
     "sc5_nlcnot": {
-        "k_bp": {"src": "paper_2504_05611_amd/csrc/kernels/decode.hip",
-                 "sha256": "20bbdf655df41c5ba864872e5c72d1eb3ff12598588778a02712c3381419b977",
-                 "fetch_kib": 14884.1, "write_kib": 27035.6},
-        "k_frame": {"src": "paper_2504_05611_amd/csrc/kernels/sample.hip",
-                    "sha256": "aac13a06933cea5d844bbee436525c35d3f385c1dc3acc17043a360968da0597",
-                    "fetch_kib": 61133.1, "write_kib": 38549.8},
+        "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
+                 "sha256": "c52767107d74cbcdecf0209dcb86dae030e6d7f44764b8a0c8e13b58d5eaa9bd",
+                 "fetch_kib": 14893.9, "write_kib": 27035.4},
+        "k_frame": {"src": ['paper_2504_05611_amd/csrc/kernels/sample.hip', 'paper_2504_05611_amd/csrc/host/program.cpp'],
+                    "sha256": "a995ee3c19865f8598c874400fecec85e360bbb766f1e7164d0f5f422eff8eb4",
+                    "fetch_kib": 59909.7, "write_kib": 38549.7},
     },
 }
 FETCH_SCALE = 1048576.0 / 524302.5   # copy-kernel calibration (1 GiB read per launch)
@@ -60,9 +60,12 @@ def traffic_bytes(workload, kernel):
     t = TRAFFIC.get(workload, {}).get(kernel)
     if t is None:
         return None
-    with open(os.path.join(ROOT, t["src"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != t["sha256"]:
-            return None
+    h = hashlib.sha256()
+    for src in t["src"]:                      # every source the counted kernel depends on
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != t["sha256"]:
+        return None
     return (t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0
 
 
