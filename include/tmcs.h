@@ -252,6 +252,11 @@ tmcs_status tmcs_wbp_backward(const tmcs_dem* d, const float* weights_dev, int32
                               const float* grad_llr_dev, float* grad_w_dev,
                               const void* workspace_dev, size_t workspace_bytes,
                               void* stream);
+/* Where the forward/backward kernels keep a shot's working state: in LDS when it
+ * fits in the 160 KB of a compute unit (default), else in per-workgroup slabs of
+ * device memory that the library allocates.  on = 1 uses the device-memory slabs
+ * always (process-wide; results are identical either way). */
+tmcs_status tmcs_wbp_global_state(int32_t on);
 
 /* Launch-shape autotuner: decodes the caller's syndromes (det_dev, n_shots
  * shots, as for tmcs_decode) with each candidate launch shape - BP threads and

@@ -164,6 +164,11 @@ tmcs_status tmcs_logical_error_rate(const uint64_t* pred_obs_dev, const uint64_t
   })
 }
 
+tmcs_status tmcs_wbp_global_state(int32_t on) {
+  wbp_set_global_state(on != 0);
+  return TMCS_OK;
+}
+
 tmcs_status tmcs_wbp_workspace_size(const tmcs_dem* d, int32_t T, uint64_t n_shots, size_t* bytes) {
   if (!d || !bytes || T < 1) return fail(TMCS_EINVAL, "invalid argument");
   *bytes = wbp_workspace_bytes(d->d, T, n_shots);

@@ -49,5 +49,6 @@ tmcs_status wbp_backward_run(const Dem& d, const float* w, int T, const uint64_t
                              uint64_t n_shots, const float* gllr, float* gw, const void* ws,
                              size_t ws_bytes, hipStream_t stream);
 void wbp_release(const Dem& d);
+void wbp_set_global_state(bool on);
 
 }  // namespace tmcs

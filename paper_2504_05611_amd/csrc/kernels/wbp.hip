@@ -16,6 +16,10 @@
 //   gq_{t-1} at the argmin edge of each message += gm_t w_t sigma_t sgn(q_{t-1}).
 // gq_t is nonzero only on each check's argmin and second-argmin edge, so it is
 // carried as two numbers per check.
+//
+// A shot's working state lives in LDS, or (GS, when it exceeds the 160 KB of a
+// compute unit, as for the surface-code CNOT at d >= 15) in a slab of device
+// memory per workgroup with the same layout.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +42,11 @@ struct WbpDevice {
   float* lam = nullptr;
   uint64_t* synd = nullptr;
   size_t cap_synd = 0;
+  unsigned char* gstate = nullptr;   // GS: [grid][slab] per-workgroup state
+  size_t cap_gstate = 0;
 };
+
+bool g_force_gs = false;             // keep the state in device memory even when it fits in LDS
 
 // Per-iteration record in the workspace.
 struct Layout {
@@ -78,14 +86,26 @@ struct WbpArgs {
   float* gw;                 // [T][E]           (backward output, accumulated)
   unsigned char* ws;         // workspace
   Layout lay;
+  unsigned char* gstate;     // GS: per-workgroup slabs
+  int64_t slab;              // GS: bytes per slab
 };
 
+// 32-bit load from L2 (GS: the sign words are updated with atomics)
+__device__ __forceinline__ uint32_t ld_sign(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <bool GS>
 __global__ void __launch_bounds__(WBP_THREADS) k_wbp_forward(WbpArgs a) {
   extern __shared__ __align__(8) unsigned char sm[];
+  unsigned char* base = GS ? a.gstate + (int64_t)blockIdx.x * a.slab : sm;
   const int tid = threadIdx.x;
   const int m = a.m, n = a.n;
   const int64_t nwords = (a.E + 31) / 32;
-  float* Lf = (float*)sm;                                // [n]
+  auto sbit = [&](const uint32_t* es, int64_t e) -> int {
+    return (int)(((GS ? ld_sign(&es[e >> 5]) : es[e >> 5]) >> (e & 31)) & 1u);
+  };
+  float* Lf = (float*)base;                              // [n]
   float* n1s = Lf + n;                                   // [m]
   float* n2s = n1s + m;                                  // [m]
   int32_t* ags = (int32_t*)(n2s + m);                    // [m]
@@ -119,7 +139,7 @@ __global__ void __launch_bounds__(WBP_THREADS) k_wbp_forward(WbpArgs a) {
         int npar = 0;
         for (int32_t e = r0; e < r1; ++e) {
           const float Lv = Lf[a.col_idx[e]];
-          const int se = (int)((es[e >> 5] >> (e & 31)) & 1u);
+          const int se = sbit(es, e);
           const float wold = (t == 1) ? 1.0f : a.w[(int64_t)(t - 2) * a.E + e];
           const float mag = __fmul_rn(wold, e == ag ? m2 : m1);
           const float mo = (sc ^ sp ^ se) ? -mag : mag;
@@ -142,7 +162,7 @@ __global__ void __launch_bounds__(WBP_THREADS) k_wbp_forward(WbpArgs a) {
         fl_out[c] = (uint8_t)((sc << 1) | npar);
       }
       __syncthreads();
-      for (int64_t i = tid; i < nwords; i += WBP_THREADS) sg_out[i] = es[i];
+      for (int64_t i = tid; i < nwords; i += WBP_THREADS) sg_out[i] = GS ? ld_sign(&es[i]) : es[i];
       // variable pass: L_t = lambda + sum_c m_t (checks ascending)
       float* Lout = a.llr + ((int64_t)(t - 1) * a.nshots + shot) * n;
       for (int v = tid; v < n; v += WBP_THREADS) {
@@ -150,7 +170,7 @@ __global__ void __launch_bounds__(WBP_THREADS) k_wbp_forward(WbpArgs a) {
         for (int32_t k = a.col_ptr[v]; k < a.col_ptr[v + 1]; ++k) {
           const int32_t c = a.csc_row[k], e = a.csc_edge[k];
           const uint8_t fl = cf[c];
-          const int se = (int)((es[e >> 5] >> (e & 31)) & 1u);
+          const int se = sbit(es, e);
           const float mag = __fmul_rn(a.w[(int64_t)(t - 1) * a.E + e], e == ags[c] ? n2s[c] : n1s[c]);
           const int neg = ((fl >> 1) ^ fl ^ se) & 1;
           acc = __fadd_rn(acc, neg ? -mag : mag);
@@ -163,11 +183,13 @@ __global__ void __launch_bounds__(WBP_THREADS) k_wbp_forward(WbpArgs a) {
   }
 }
 
+template <bool GS>
 __global__ void __launch_bounds__(WBP_THREADS) k_wbp_backward(WbpArgs a) {
   extern __shared__ __align__(8) unsigned char sm[];
+  unsigned char* base = GS ? a.gstate + (int64_t)blockIdx.x * a.slab : sm;
   const int tid = threadIdx.x;
   const int m = a.m, n = a.n;
-  float* gL = (float*)sm;                                // [n]
+  float* gL = (float*)base;                              // [n]
   float* g1n = gL + n;                                   // [m] gradient routed to argmin (next iteration)
   float* g2n = g1n + m;                                  // [m] ... to the second argmin
   int32_t* agn = (int32_t*)(g2n + m);                    // [m] argmin edges of the next iteration
@@ -318,6 +340,22 @@ tmcs_status prepare(const Dem& D, int T, const uint64_t* det, uint64_t n_shots, 
   return TMCS_OK;
 }
 
+// per-workgroup device-memory slabs of `bytes` each for the GS variants
+tmcs_status slabs(WbpDevice* d, int grid, size_t bytes, WbpArgs* a) {
+  const size_t slab = (bytes + 255) & ~(size_t)255;
+  const size_t need = slab * (size_t)grid;
+  if (d->cap_gstate < need) {
+    hipFree(d->gstate);
+    d->gstate = nullptr;
+    d->cap_gstate = 0;
+    if (hipMalloc((void**)&d->gstate, need) != hipSuccess) return fail(TMCS_ENOMEM, "hipMalloc (wbp state)");
+    d->cap_gstate = need;
+  }
+  a->gstate = d->gstate;
+  a->slab = (int64_t)slab;
+  return TMCS_OK;
+}
+
 int grid_for(uint64_t n_shots) {
   int dev = 0, cus = 0;
   hipGetDevice(&dev);
@@ -326,6 +364,8 @@ int grid_for(uint64_t n_shots) {
 }
 
 }  // namespace
+
+void wbp_set_global_state(bool on) { g_force_gs = on; }
 
 size_t wbp_workspace_bytes(const Dem& d, int T, uint64_t n_shots) {
   return (size_t)layout(d, T).shot * (size_t)n_shots;
@@ -343,11 +383,16 @@ tmcs_status wbp_forward_run(const Dem& D, const float* w, int T, const uint64_t*
   a.w = w; a.llr = llr; a.ws = (unsigned char*)ws;
   const int64_t nwords = (D.edges + 31) / 32;
   const size_t lds = (size_t)D.cols * 4 + (size_t)D.rows * 13 + (size_t)nwords * 4 + 16;
-  if (lds > 160 * 1024) return fail(TMCS_EUNSUPPORTED, "weighted BP state exceeds LDS");
+  const int grid = grid_for(n_shots);
+  if (g_force_gs || lds > 160 * 1024) {
+    if ((st = slabs(d, grid, lds, &a)) != TMCS_OK) return st;
+    TMCS_LAUNCH("k_wbp_forward", k_wbp_forward<true>, dim3(grid), dim3(WBP_THREADS), 0, stream, a);
+    return hip_check(hipGetLastError(), "k_wbp_forward launch");
+  }
   if (lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_wbp_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      hipFuncSetAttribute((const void*)k_wbp_forward<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "weighted BP state does not fit in LDS");
-  TMCS_LAUNCH("k_wbp_forward", k_wbp_forward, dim3(grid_for(n_shots)), dim3(WBP_THREADS), lds, stream, a);
+  TMCS_LAUNCH("k_wbp_forward", k_wbp_forward<false>, dim3(grid), dim3(WBP_THREADS), lds, stream, a);
   return hip_check(hipGetLastError(), "k_wbp_forward launch");
 }
 
@@ -362,11 +407,16 @@ tmcs_status wbp_backward_run(const Dem& D, const float* w, int T, const uint64_t
   if (st != TMCS_OK) return st;
   a.w = w; a.gllr = gllr; a.gw = gw; a.ws = (unsigned char*)ws;
   const size_t lds = (size_t)D.cols * 4 + (size_t)D.rows * 32 + 16;
-  if (lds > 160 * 1024) return fail(TMCS_EUNSUPPORTED, "weighted BP state exceeds LDS");
+  const int grid = grid_for(n_shots);
+  if (g_force_gs || lds > 160 * 1024) {
+    if ((st = slabs(d, grid, lds, &a)) != TMCS_OK) return st;
+    TMCS_LAUNCH("k_wbp_backward", k_wbp_backward<true>, dim3(grid), dim3(WBP_THREADS), 0, stream, a);
+    return hip_check(hipGetLastError(), "k_wbp_backward launch");
+  }
   if (lds > 64 * 1024 &&
-      hipFuncSetAttribute((const void*)k_wbp_backward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+      hipFuncSetAttribute((const void*)k_wbp_backward<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "weighted BP state does not fit in LDS");
-  TMCS_LAUNCH("k_wbp_backward", k_wbp_backward, dim3(grid_for(n_shots)), dim3(WBP_THREADS), lds, stream, a);
+  TMCS_LAUNCH("k_wbp_backward", k_wbp_backward<false>, dim3(grid), dim3(WBP_THREADS), lds, stream, a);
   return hip_check(hipGetLastError(), "k_wbp_backward launch");
 }
 

@@ -88,6 +88,7 @@ _SIGS = {
     "tmcs_wbp_workspace_size": [_vp, _i32, _u64, ctypes.POINTER(_sz)],
     "tmcs_wbp_forward": [_vp, _vp, _i32, _vp, _u64, _vp, _vp, _sz, _vp],
     "tmcs_wbp_backward": [_vp, _vp, _i32, _vp, _u64, _vp, _vp, _vp, _sz, _vp],
+    "tmcs_wbp_global_state": [_i32],
     "tmcs_autotune": [_vp, _vp, _u64, ctypes.POINTER(DecoderCfg), _vp],
     "tmcs_plan_create": [ctypes.POINTER(PlanItem), _i32, _u64, _i32, ctypes.POINTER(_vp)],
     "tmcs_plan_run": [_vp, _u32, _vp],
@@ -278,6 +279,11 @@ class DEM:
         _check(_lib.tmcs_wbp_backward(self._h, _ptr(weights), T, _ptr(det), n_shots, _ptr(grad_llr),
                                       _ptr(grad_w), _ptr(workspace),
                                       workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def wbp_global_state(on=True):
+    """Keep the training kernels' per-shot state in device memory (1) or in LDS when it fits (0)."""
+    _check(_lib.tmcs_wbp_global_state(1 if on else 0))
 
 
 def make_cfg(max_iter=30, alpha=1.0, weights=None, use_osd=True, bp_threads=0, bp_per_cu=0,

@@ -97,3 +97,64 @@ def test_training_lowers_the_loss_and_bp_failures(gpu_lib):
           f"non-converged plain {1 - plain['converged']:.4e} learned {1 - learned['converged']:.4e}", flush=True)
     assert learned["ler"] < plain["ler"]
     assert learned["converged"] > plain["converged"]
+
+
+def test_state_in_device_memory_matches_lds(gpu_lib):
+    """The device-memory variant of the training kernels (used when a shot's state
+    exceeds LDS) gives the LDS variant's forward bit for bit and its gradient up
+    to the order of FP32 atomic additions."""
+    import torch
+    spec = bb("bb18", NLCNOT, 1, 1, 4e-3, 1e-2)
+    T, shots = 5, 96
+    c, dem, det, obs, w, wt = _setup(gpu_lib, spec, shots, T)
+    G = torch.from_numpy(np.random.default_rng(3).normal(size=(T, shots, dem.cols)).astype(np.float32)).cuda()
+    out = []
+    try:
+        for gs in (False, True):
+            gpu_lib.wbp_global_state(gs)
+            ws = torch.empty(dem.wbp_workspace_size(T, shots), dtype=torch.uint8, device="cuda")
+            llr = torch.empty((T, shots, dem.cols), dtype=torch.float32, device="cuda")
+            dem.wbp_forward(wt, T, det, shots, llr, ws)
+            gw = torch.zeros_like(wt)
+            dem.wbp_backward(wt, T, det, shots, G, gw, ws)
+            torch.cuda.synchronize()
+            out.append((llr.cpu().numpy(), gw.cpu().numpy().astype(np.float64)))
+    finally:
+        gpu_lib.wbp_global_state(False)
+    assert (out[0][0] == out[1][0]).all()
+    assert np.linalg.norm(out[0][1] - out[1][1]) <= 1e-5 * np.linalg.norm(out[0][1])
+
+
+def test_training_kernels_at_d15(gpu_lib):
+    """d = 15 non-local CNOT of the mixed batch: the per-shot state (~245 KB
+    forward, ~370 KB backward) exceeds LDS, so the kernels use device memory;
+    forward against the oracle in FP32 bit for bit, gradient against the oracle's.
+    The oracle's DEM comes from tests/golden/dem_sc15_nlcnot_p1e-3.npz."""
+    import os
+    import torch
+    from workloads import WORKLOADS
+    w_ = WORKLOADS["sc_nlcnot_mixed"]
+    inst, spec = next((i, s) for i, s in enumerate(w_.specs) if s.d == 15 and s.p == 1e-3)
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "dem_sc15_nlcnot_p1e-3.npz"))
+    m, ncol = int(g["num_dets"]), len(g["priors"])
+    H = np.zeros((m, ncol), dtype=np.uint8)
+    cp = g["col_ptr"]
+    for j in range(ncol):
+        H[g["rows"][cp[j]:cp[j + 1]], j] = 1
+    T, shots = 3, 4
+    print(f"[wbp-d15] m={m} cols={ncol}", flush=True)
+    c, dem, det, obs, w, wt = _setup(gpu_lib, spec, shots, T)
+    assert dem.rows == m and dem.cols == ncol
+    ws = torch.empty(dem.wbp_workspace_size(T, shots), dtype=torch.uint8, device="cuda")
+    llr = torch.empty((T, shots, dem.cols), dtype=torch.float32, device="cuda")
+    dem.wbp_forward(wt, T, det, shots, llr, ws)
+    G = np.random.default_rng(5).normal(size=(T, shots, dem.cols)).astype(np.float32)
+    gw = torch.zeros_like(wt)
+    dem.wbp_backward(wt, T, det, shots, torch.from_numpy(G).cuda(), gw, ws)
+    torch.cuda.synchronize()
+    synd = unpack_bits(det.cpu().numpy().view(np.uint64), shots).T
+    f32 = oracle_forward(H, g["priors"], synd, w, dtype=np.float32)
+    assert (llr.cpu().numpy() == f32["L"]).all()
+    ref = oracle_backward(f32, G.astype(np.float64))
+    got = gw.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-4 * max(np.linalg.norm(ref), 1e-30)
