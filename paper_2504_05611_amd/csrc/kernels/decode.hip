@@ -177,13 +177,41 @@ __global__ void __launch_bounds__(64) k_synd_transpose(const uint64_t* __restric
   if (s < nshots) synd[s * mw + rt] = out;
 }
 
-// Queue the shots of the chunk whose syndrome is non-zero.
-__global__ void k_compact(const uint64_t* __restrict__ synd, int32_t mw, int64_t nshots,
-                          int32_t* __restrict__ queue, int32_t* __restrict__ counters) {
-  for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nshots; s += (int64_t)gridDim.x * blockDim.x) {
-    uint64_t any = 0ull;
-    for (int k = 0; k < mw; ++k) any |= synd[s * mw + k];
-    if (any) queue[atomicAdd(&counters[0], 1)] = (int32_t)s;
+// Queue the shots of the chunk whose syndrome is non-zero.  Same-address
+// atomics serialise, so a workgroup (256 lanes) takes tiles of 16 x 256 shots
+// and reserves the queue slots of a whole tile with one atomic.
+constexpr int COMPACT_SLABS = 16;
+__global__ void __launch_bounds__(256) k_compact(const uint64_t* __restrict__ synd, int32_t mw, int64_t nshots,
+                                                 int32_t* __restrict__ queue, int32_t* __restrict__ counters) {
+  __shared__ int s_wave[4];
+  __shared__ int s_base;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  constexpr int64_t TILE = 256 * COMPACT_SLABS;
+  for (int64_t t0 = (int64_t)blockIdx.x * TILE; t0 < nshots; t0 += (int64_t)gridDim.x * TILE) {
+    uint64_t keep[COMPACT_SLABS];
+    int tot = 0;
+#pragma unroll
+    for (int i = 0; i < COMPACT_SLABS; ++i) {
+      const int64_t sh = t0 + i * 256 + threadIdx.x;
+      uint64_t any = 0ull;
+      if (sh < nshots)
+        for (int k = 0; k < mw; ++k) any |= synd[sh * mw + k];
+      keep[i] = __ballot(any != 0ull);
+      tot += __popcll(keep[i]);
+    }
+    if (lane == 0) s_wave[wv] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) s_base = atomicAdd(&counters[0], s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3]);
+    __syncthreads();
+    int base = s_base;
+    for (int w = 0; w < wv; ++w) base += s_wave[w];
+#pragma unroll
+    for (int i = 0; i < COMPACT_SLABS; ++i) {
+      if ((keep[i] >> lane) & 1ull) queue[base + __popcll(keep[i] & below)] = (int32_t)(t0 + i * 256 + threadIdx.x);
+      base += __popcll(keep[i]);
+    }
+    __syncthreads();   // s_wave and s_base are rewritten for the next tile
   }
 }
 
@@ -1387,9 +1415,11 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
        hipFuncSetAttribute((const void*)k_bp<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess))
     return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
   const int per_cu = std::max(1, std::min({team_fit, 32 / (P / 64), cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 32}));
-  // shots per internal pass: bounded so the OSD LLR staging stays <= 1 GiB
-  const int64_t chunk = std::min<int64_t>((int64_t)n_shots,
-                                          std::max<int64_t>(DECODE_CHUNK_MIN, ((1ll << 28) / std::max(D.cols, 1)) & ~63ll));
+  // shots per internal pass: as few passes as the OSD LLR staging allows
+  // (<= 8 GiB), each ending on its slowest teams; passes of equal size
+  const int64_t cmax = std::max<int64_t>(DECODE_CHUNK_MIN, ((1ll << 31) / std::max(D.cols, 1)) & ~63ll);
+  const int64_t nch = std::max<int64_t>(1, ((int64_t)n_shots + cmax - 1) / cmax);
+  const int64_t chunk = std::min<int64_t>((int64_t)n_shots, (((int64_t)n_shots + nch - 1) / nch + 63) & ~63ll);
   // OSD launch shape
   const int W = osd_win ? 2 * WIN_MW
                         : 2 * (mw <= 1 ? 1 : mw <= 2 ? 2 : mw <= 4 ? 4 : mw <= 5 ? 5 : mw <= 8 ? 8 : mw <= 12 ? 12
@@ -1453,7 +1483,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
                   D.rows, stride, s0, ns, mt, d->synd);
     }
     if (!full) {
-      const int64_t g = std::min<int64_t>((ns + 255) / 256, 4096);
+      const int64_t g = std::min<int64_t>((ns + 256 * COMPACT_SLABS - 1) / (256 * COMPACT_SLABS), 1024);
       TMCS_LAUNCH("k_compact", k_compact, dim3((unsigned)g), dim3(256), 0, stream, d->synd, std::max(mw, 1), ns,
                   d->queue, d->counters);
     }
