@@ -1279,7 +1279,8 @@ tmcs_status launch_osd(const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
 // prefix pass: PFX_KEYS_WAVE (one wave) or PFX_KEYS_WG (256 threads) keys, 4 per thread
 template <int MW>
 tmcs_status launch_osd_pfx(bool bl, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
-  return bl ? launch_osd<MW, MW, PFX_KEYS_WAVE / 64, true, true>(a, grid, lds, s)
+  // (one wave: at most PFX_KEYS_WAVE - 1 pivots, so PFX_KEYS_WAVE / 64 words of combination part)
+  return bl ? launch_osd<MW, PFX_KEYS_WAVE / 64, PFX_KEYS_WAVE / 64, true, true>(a, grid, lds, s)
             : launch_osd<MW, MW, PFX_KEYS_WG / OSD_THREADS, false, true>(a, grid, lds, s);
 }
 
@@ -1438,14 +1439,22 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   if (osd_bl) osd_lds += basis_bytes - (size_t)npad * 4;
   // dense OSD-0 on a DEM wider than the prefix: prefix pass, then a full sort of the rest
   const int pfx_keys = osd_bl ? PFX_KEYS_WAVE : PFX_KEYS_WG;
+  // the prefix holds at most pfx_keys - 1 columns, so at most that many pivots:
+  // its basis and pivot lists need pfx_rank rows, and with the basis in LDS
+  // more workgroups fit on a CU than for the full sort
+  const int pfx_rank = std::min(osd_rank, pfx_keys);
+  // and the one-wave variant's basis vectors carry PFX_KEYS_WAVE / 64 words of combination part
+  const int W_pfx = osd_bl ? W / 2 + PFX_KEYS_WAVE / 64 : W;
   // (the one-wave variant gathers 8-byte keys over its 4-byte index area and the LDS basis after it)
   const bool osd_pfx = cfg.use_osd && !osd_win && cfg.osd_order == 0 && D.cols >= pfx_keys &&
-                       (!osd_bl || basis_bytes >= (size_t)pfx_keys * 4);
-  size_t pfx_lds = (size_t)pfx_keys * 8 + (size_t)osd_rank * 8 + (size_t)osd_rows * 8 + (size_t)W * 8 + 64;
-  if (osd_bl) pfx_lds += basis_bytes - (size_t)pfx_keys * 4;
+                       (!osd_bl || (size_t)pfx_rank * W_pfx * 8 >= (size_t)pfx_keys * 4);
+  size_t pfx_lds = (size_t)pfx_keys * 8 + (size_t)pfx_rank * 8 + (size_t)osd_rows * 8 + (size_t)W_pfx * 8 + 64;
+  if (osd_bl) pfx_lds += (size_t)pfx_rank * W_pfx * 8 - (size_t)pfx_keys * 4;
   const int osd_fit = std::max<int>(1, (int)((160 * 1024) / (osd_lds + 512)));
   const int osd_per_cu = std::min(osd_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : (osd_bl ? 16 : 4));
   const int osd_grid = std::max(1, cus * osd_per_cu);
+  const int pfx_fit = std::max<int>(1, (int)((160 * 1024) / (pfx_lds + 512)));
+  const int pfx_grid = osd_bl ? std::max(1, cus * std::min(pfx_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 16)) : osd_grid;
   if ((st = grow(&d->queue, &d->cap_queue, (size_t)chunk)) != TMCS_OK) return st;
   if ((st = grow(&d->synd, &d->cap_synd, (size_t)chunk * (size_t)std::max(mw, 1))) != TMCS_OK) return st;
   if (gstate && (st = grow(&d->gstate, &d->cap_gstate, (size_t)cus * per_cu * team_bytes)) != TMCS_OK) return st;
@@ -1521,8 +1530,9 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
       } else if (osd_pfx) {
         OSDArgs op = o;
         op.npad = pfx_keys;
+        op.rank = pfx_rank;
         op.retry = d->retry;
-        if ((st = dispatch_osd_pfx(mw, osd_bl, op, osd_grid, pfx_lds, stream)) != TMCS_OK) return st;
+        if ((st = dispatch_osd_pfx(mw, osd_bl, op, pfx_grid, pfx_lds, stream)) != TMCS_OK) return st;
         OSDArgs orr = o;
         orr.jobs = d->retry; orr.cnt_total = 4; orr.cnt_next = 5;
         st = dispatch_osd(mw, npad / (osd_bl ? 64 : OSD_THREADS), osd_bl, orr, osd_grid, osd_lds, stream);
