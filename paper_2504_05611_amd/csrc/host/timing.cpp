@@ -26,7 +26,9 @@ bool timing_on() { return g_on; }
 
 void timing_begin(const char* name, hipStream_t s, void** token) {
   Rec* r = new Rec{name, nullptr, nullptr};
-  if (hipEventCreate(&r->a) != hipSuccess || hipEventCreate(&r->b) != hipSuccess) {
+  // timing only: no system-scope fence (cache writeback and invalidation) per record
+  if (hipEventCreateWithFlags(&r->a, hipEventDisableSystemFence) != hipSuccess ||
+      hipEventCreateWithFlags(&r->b, hipEventDisableSystemFence) != hipSuccess) {
     delete r;
     *token = nullptr;
     return;
