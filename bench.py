@@ -43,8 +43,8 @@ EVENT_APPLY_OPS = 4
 TRAFFIC = {
     "sc5_nlcnot": {
         "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
-                 "sha256": "e9b3a47679501b80b132f4ad742ff223a247280a7f46556ea253f89e8f09a905",
-                 "fetch_kib": 72882.7, "write_kib": 133333.7},
+                 "sha256": "0d0c7337ec53858c2f1b3ec9b164ff38263c0608141e48822e37c0f511b23045",
+                 "fetch_kib": 72901.5, "write_kib": 133337.7},
         "k_frame": {"src": ['paper_2504_05611_amd/csrc/kernels/sample.hip', 'paper_2504_05611_amd/csrc/host/program.cpp'],
                     "sha256": "a995ee3c19865f8598c874400fecec85e360bbb766f1e7164d0f5f422eff8eb4",
                     "fetch_kib": 59909.7, "write_kib": 38549.7},
