@@ -194,6 +194,11 @@ typedef struct {
                                syndrome is spanned inside it the result equals the dense OSD-0
                                exactly, otherwise the shot keeps BP's hard decision and is
                                counted in osd_incomplete (flags bit 3) */
+  int32_t decode_chunk;     /* shots per internal decoder pass: 0 = as many as keep the OSD
+                               posterior staging (4 * cols bytes per shot) under 8 GiB;
+                               otherwise a positive multiple of 64 that caps it.  Results
+                               never depend on it (each pass ends on its slowest shots, so
+                               fewer passes are faster) */
   /* optional per-shot outputs (NULL to skip), each indexed by shot of the call: */
   uint8_t* ehat_dev;        /* [n_shots][cols] final correction (0/1 bytes) */
   float* llr_dev;           /* [n_shots][cols] final BP posterior LLRs */
@@ -206,7 +211,7 @@ typedef struct {
 typedef struct {
   uint64_t shots;        /* shots decoded */
   uint64_t nontrivial;   /* shots with a non-zero syndrome */
-  uint64_t converged;    /* shots where BP satisfied the syndrome */
+  uint64_t converged;    /* shots where BP satisfied the syndrome (all-zero syndromes included) */
   uint64_t osd;          /* shots sent to OSD-0 */
   uint64_t not_in_span;  /* OSD shots whose syndrome was not in H's column space */
   uint64_t bp_iters;     /* sum of BP iterations */

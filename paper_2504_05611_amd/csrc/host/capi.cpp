@@ -144,6 +144,8 @@ tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg, const ui
   if (!std::isfinite(cfg->alpha) || cfg->alpha <= 0.0f) return fail(TMCS_EINVAL, "alpha must be positive");
   if (cfg->osd_window < 0 || cfg->osd_window > 2048) return fail(TMCS_EINVAL, "osd_window must be in [0, 2048]");
   if (cfg->osd_order < 0 || cfg->osd_order > 64) return fail(TMCS_EINVAL, "osd_order must be in [0, 64]");
+  if (cfg->decode_chunk < 0 || cfg->decode_chunk % 64 != 0)
+    return fail(TMCS_EINVAL, "decode_chunk must be 0 or a positive multiple of 64");
   TMCS_TRY({
     return decode_run(d->d, *cfg, det_dev, n_shots, pred_obs_dev, stats_dev, (hipStream_t)stream);
   })

@@ -148,6 +148,12 @@ __global__ void k_add_shots(tmcs_decode_stats* stats, unsigned long long n) {
   if (threadIdx.x == 0) atomicAdd((unsigned long long*)&stats->shots, n);
 }
 
+// Shots the compaction left out (all-zero syndrome) are converged: their
+// all-zero hard decision satisfies s, as on the path that visits every shot.
+__global__ void k_add_trivial(tmcs_decode_stats* stats, const int32_t* counters, unsigned long long n) {
+  atomicAdd((unsigned long long*)&stats->converged, n - (unsigned long long)counters[0]);
+}
+
 __global__ void k_zero_i32(int32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1418,7 +1424,8 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int per_cu = std::max(1, std::min({team_fit, 32 / (P / 64), cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 32}));
   // shots per internal pass: as few passes as the OSD LLR staging allows
   // (<= 8 GiB), each ending on its slowest teams; passes of equal size
-  const int64_t cmax = std::max<int64_t>(DECODE_CHUNK_MIN, ((1ll << 31) / std::max(D.cols, 1)) & ~63ll);
+  int64_t cmax = std::max<int64_t>(DECODE_CHUNK_MIN, ((1ll << 31) / std::max(D.cols, 1)) & ~63ll);
+  if (cfg.decode_chunk > 0) cmax = std::min<int64_t>(cmax, cfg.decode_chunk);
   const int64_t nch = std::max<int64_t>(1, ((int64_t)n_shots + cmax - 1) / cmax);
   const int64_t chunk = std::min<int64_t>((int64_t)n_shots, (((int64_t)n_shots + nch - 1) / nch + 63) & ~63ll);
   // OSD launch shape
@@ -1495,6 +1502,8 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
       const int64_t g = std::min<int64_t>((ns + 256 * COMPACT_SLABS - 1) / (256 * COMPACT_SLABS), 1024);
       TMCS_LAUNCH("k_compact", k_compact, dim3((unsigned)g), dim3(256), 0, stream, d->synd, std::max(mw, 1), ns,
                   d->queue, d->counters);
+      if (stats) TMCS_LAUNCH("k_add_trivial", k_add_trivial, dim3(1), dim3(1), 0, stream, stats, d->counters,
+                             (unsigned long long)ns);
     }
     BPArgs a;
     a.csched = sch.c; a.vsched = sch.v; a.Kc = sch.Kc; a.Kv = sch.Kv; a.init = d->init; a.sign0 = d->sign0;

@@ -53,6 +53,7 @@ class DecoderCfg(ctypes.Structure):
                 ("bp_threads", ctypes.c_int32), ("bp_per_cu", ctypes.c_int32),
                 ("osd_per_cu", ctypes.c_int32), ("bp_global_state", ctypes.c_int32),
                 ("osd_order", ctypes.c_int32), ("osd_window", ctypes.c_int32),
+                ("decode_chunk", ctypes.c_int32),
                 ("ehat_dev", ctypes.c_void_p),
                 ("llr_dev", ctypes.c_void_p), ("iters_dev", ctypes.c_void_p),
                 ("flags_dev", ctypes.c_void_p)]
@@ -258,9 +259,9 @@ class DEM:
 
     def decode(self, det, n_shots, pred, *, max_iter=30, alpha=1.0, weights=None, use_osd=True,
                bp_threads=0, bp_per_cu=0, osd_per_cu=0, bp_global_state=0, osd_order=0, osd_window=0,
-               ehat=None, llr=None, iters=None, flags=None, stats=None, stream=None):
+               decode_chunk=0, ehat=None, llr=None, iters=None, flags=None, stats=None, stream=None):
         cfg = DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads,
-                         bp_per_cu, osd_per_cu, bp_global_state, osd_order, osd_window,
+                         bp_per_cu, osd_per_cu, bp_global_state, osd_order, osd_window, decode_chunk,
                          _ptr(ehat), _ptr(llr), _ptr(iters), _ptr(flags))
         _check(_lib.tmcs_decode(self._h, ctypes.byref(cfg), _ptr(det), n_shots, _ptr(pred), _ptr(stats),
                                 _stream(stream)))
@@ -287,9 +288,9 @@ def wbp_global_state(on=True):
 
 
 def make_cfg(max_iter=30, alpha=1.0, weights=None, use_osd=True, bp_threads=0, bp_per_cu=0,
-             osd_per_cu=0, bp_global_state=0, osd_order=0, osd_window=0):
+             osd_per_cu=0, bp_global_state=0, osd_order=0, osd_window=0, decode_chunk=0):
     return DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads, bp_per_cu,
-                      osd_per_cu, bp_global_state, osd_order, osd_window, None, None, None, None)
+                      osd_per_cu, bp_global_state, osd_order, osd_window, decode_chunk, None, None, None, None)
 
 
 def autotune(dem, det, n_shots, cfg=None, stream=None) -> DecoderCfg:

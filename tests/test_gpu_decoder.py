@@ -250,3 +250,46 @@ def test_osd_cs_matches_oracle(gpu_lib, name, spec, shots):
     changed = (e_cs != outs[1][0]).any(axis=1)
     print(f"[osd-cs] {name}: OSD shots {int(osd.sum())}, corrections changed by CS {int(changed.sum())}", flush=True)
     assert osd.sum() > 10 and changed.sum() > 0 and not (changed & ~osd).any()
+
+
+def test_several_decoder_passes_equal_one(gpu_lib):
+    """Shots split over several internal passes (at most 4096, 1024 or 64 shots
+    each; 3 x 4096 + 77 shots, so the last pass is ragged) give the same
+    predictions, per-shot outputs and statistics as a single pass, on both the
+    full path (per-shot outputs) and the compacted one.  The single pass itself
+    is compared with the oracle in test_decoder_parity."""
+    import torch
+    spec = sc(5, NLCNOT, 5, 5, 3e-3, 2e-2)
+    shots, T = 3 * 4096 + 77, 30
+    print(f"[decoder] passes sc5-nlcnot shots={shots}", flush=True)
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    det, obs = c.alloc_outputs(shots)
+    c.sample(5, 0, 0, shots, det, obs)
+    N, k, w = dem.cols, max(c.num_observables, 1), (shots + 63) // 64
+
+    def run(chunk):
+        pred = torch.zeros((k, w), dtype=torch.int64, device="cuda")
+        ehat = torch.zeros((shots, N), dtype=torch.uint8, device="cuda")
+        llr = torch.zeros((shots, N), dtype=torch.float32, device="cuda")
+        iters = torch.zeros(shots, dtype=torch.int32, device="cuda")
+        flags = torch.zeros(shots, dtype=torch.uint8, device="cuda")
+        stats = gpu_lib.new_stats()
+        dem.decode(det, shots, pred, max_iter=T, ehat=ehat, llr=llr, iters=iters, flags=flags, stats=stats,
+                   decode_chunk=chunk)
+        pred2 = torch.zeros_like(pred)
+        stats2 = gpu_lib.new_stats()
+        dem.decode(det, shots, pred2, max_iter=T, stats=stats2, decode_chunk=chunk)     # compacted path
+        torch.cuda.synchronize()
+        return dict(pred=pred.cpu(), pred2=pred2.cpu(), ehat=ehat.cpu(), llr=llr.cpu(), iters=iters.cpu(),
+                    flags=flags.cpu()), gpu_lib.read_stats(stats), gpu_lib.read_stats(stats2)
+
+    ref, st, st2 = run(0)
+    assert st["osd"] > 0 and st["shots"] == shots
+    assert st2 == st
+    assert torch.equal(ref["pred"], ref["pred2"])
+    for chunk in (4096, 1024, 64):
+        r, s, s2 = run(chunk)
+        for key, v in ref.items():
+            assert torch.equal(r[key], v), (chunk, key)
+        assert s == st and s2 == st, chunk

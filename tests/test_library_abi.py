@@ -48,6 +48,10 @@ def test_decoder_config_is_validated(lib, handles):
         cfg = lib.make_cfg(max_iter=10, osd_order=o)
         assert raw.tmcs_decode(d._h, ctypes.byref(cfg), None, 64, None, None, None) == EINVAL
         assert "osd_order" in _err(lib)
+    for ch in (-64, 100):
+        cfg = lib.make_cfg(max_iter=10, decode_chunk=ch)
+        assert raw.tmcs_decode(d._h, ctypes.byref(cfg), None, 64, None, None, None) == EINVAL
+        assert "decode_chunk" in _err(lib)
     cfg = lib.make_cfg(max_iter=10)
     assert raw.tmcs_decode(None, ctypes.byref(cfg), None, 64, None, None, None) == EINVAL
     # no shots: nothing to do, no device work
