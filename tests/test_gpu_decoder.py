@@ -24,6 +24,9 @@ CASES = [
     ("bb144-memory", bb("bb144", MEMORY, 4, 0, 2e-3), 96, 20),
     ("sc3-nlcnot-decoherence", with_decoherence(sc(3, NLCNOT, 3, 3, 3e-3, 1e-2), 0.03, False), 2048 + 11, 30),
     ("sc3-pstring4", pstring(sc(3, p=4e-3), 4, rounds=2), 1024 + 7, 30),
+    # OSD basis widths of the prefix pass not covered above: 156 detectors (3 words) and 336 (6 words)
+    ("sc5-teleport", sc(5, TELEPORT, 3, 3, 3e-3, 1e-2), 1024 + 9, 30),
+    ("sc7-nlcnot", sc(7, NLCNOT, 3, 3, 2e-3, 1e-2), 512 + 3, 30),
 ]
 
 
