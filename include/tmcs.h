@@ -225,7 +225,12 @@ typedef struct {
 
 /* Decode det_dev ([rows][ceil(n/64)], as written by tmcs_sample) and write the
  * predicted observable flips pred_obs_dev ([observables][ceil(n/64)]).
- * stats_dev (device, may be NULL) is incremented. */
+ * stats_dev (device, may be NULL) is incremented.  Work is enqueued on stream;
+ * the call does not wait for it.  The DEM handle keeps device scratch that grows
+ * with the shots of a pass: about 4 * cols bytes per shot for the posteriors
+ * handed to OSD (at most 8 GiB; decode_chunk caps it) plus a few words per shot.
+ * Calls on one DEM handle share that scratch, so calls that may overlap in time
+ * (different streams) need different handles. */
 tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg,
                         const uint64_t* det_dev, uint64_t n_shots, uint64_t* pred_obs_dev,
                         tmcs_decode_stats* stats_dev, void* stream);
