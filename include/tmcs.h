@@ -161,6 +161,16 @@ tmcs_status tmcs_sample(const tmcs_circuit* c, uint64_t seed, uint32_t instance,
                         uint64_t shot_begin, uint64_t n_shots, uint64_t* det_dev,
                         uint64_t* obs_dev, void* stream);
 
+/* tmcs_sample without the wait, for pipelines that keep the device busy: the
+ * same shots and outputs, but an event-buffer overflow sets *overflow_dev
+ * (device uint32 that the caller zeroes; it stays set) instead of returning an
+ * error, and the call never synchronises.  The caller checks the flag after the
+ * work; outputs of calls made while it was set are not valid.  NULL
+ * overflow_dev: TMCS_EINVAL. */
+tmcs_status tmcs_sample_async(const tmcs_circuit* c, uint64_t seed, uint32_t instance,
+                              uint64_t shot_begin, uint64_t n_shots, uint64_t* det_dev,
+                              uint64_t* obs_dev, uint32_t* overflow_dev, void* stream);
+
 /* Decoder configuration: flooding min-sum BP over the DEM with an OSD-0 fallback
  * (Supplementary Note 7 names BP-OSD).  With priors lambda_v = ln((1-p_v)/p_v):
  *   m_{c->v} = (-1)^{s_c} prod_{v' != v} sgn(q_{v'->c}) * alpha * min_{v' != v} |q_{v'->c}|,
@@ -242,6 +252,12 @@ tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg,
 tmcs_status tmcs_logical_error_rate(const uint64_t* pred_obs_dev, const uint64_t* obs_dev,
                                     uint32_t k, uint64_t n_shots, uint64_t* n_errors_host,
                                     double* ler, double* sigma, void* stream);
+
+/* The failing-shot count of tmcs_logical_error_rate, added to *n_errors_dev
+ * (device uint64) without waiting, so that counts over many calls are read
+ * once.  NULL n_errors_dev: TMCS_EINVAL. */
+tmcs_status tmcs_count_errors(const uint64_t* pred_obs_dev, const uint64_t* obs_dev, uint32_t k,
+                              uint64_t n_shots, uint64_t* n_errors_dev, void* stream);
 
 /* Weighted (neural) min-sum BP, unrolled for T iterations without early stop,
  * for training per-edge per-iteration weights w[t][e] (FP32 [T][edges]).

@@ -136,6 +136,17 @@ tmcs_status tmcs_sample(const tmcs_circuit* c, uint64_t seed, uint32_t instance,
   })
 }
 
+tmcs_status tmcs_sample_async(const tmcs_circuit* c, uint64_t seed, uint32_t instance, uint64_t shot_begin,
+                              uint64_t n_shots, uint64_t* det_dev, uint64_t* obs_dev, uint32_t* overflow_dev,
+                              void* stream) {
+  if (!c) return fail(TMCS_EINVAL, "null circuit");
+  if (!overflow_dev) return fail(TMCS_EINVAL, "null overflow flag");
+  TMCS_TRY({
+    return sample_run(c->c, seed, instance, shot_begin, n_shots, det_dev, obs_dev, (hipStream_t)stream, nullptr,
+                      overflow_dev);
+  })
+}
+
 tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg, const uint64_t* det_dev,
                         uint64_t n_shots, uint64_t* pred_obs_dev, tmcs_decode_stats* stats_dev,
                         void* stream) {
@@ -148,6 +159,15 @@ tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg, const ui
     return fail(TMCS_EINVAL, "decode_chunk must be 0 or a positive multiple of 64");
   TMCS_TRY({
     return decode_run(d->d, *cfg, det_dev, n_shots, pred_obs_dev, stats_dev, (hipStream_t)stream);
+  })
+}
+
+tmcs_status tmcs_count_errors(const uint64_t* pred_obs_dev, const uint64_t* obs_dev, uint32_t k, uint64_t n_shots,
+                              uint64_t* n_errors_dev, void* stream) {
+  if (!n_errors_dev) return fail(TMCS_EINVAL, "null error counter");
+  TMCS_TRY({
+    return count_errors_async(pred_obs_dev, obs_dev, k, n_shots, (unsigned long long*)n_errors_dev,
+                              (hipStream_t)stream);
   })
 }
 

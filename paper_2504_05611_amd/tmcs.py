@@ -83,6 +83,8 @@ _SIGS = {
     "tmcs_dem_export": [_vp, _vp, _vp, _vp, _vp],
     "tmcs_dem_distance": [_vp, _i32, _i32, ctypes.c_int64, ctypes.POINTER(_i32)],
     "tmcs_sample": [_vp, _u64, _u32, _u64, _u64, _vp, _vp, _vp],
+    "tmcs_sample_async": [_vp, _u64, _u32, _u64, _u64, _vp, _vp, _vp, _vp],
+    "tmcs_count_errors": [_vp, _vp, _u32, _u64, _vp, _vp],
     "tmcs_decode": [_vp, ctypes.POINTER(DecoderCfg), _vp, _u64, _vp, _vp, _vp],
     "tmcs_logical_error_rate": [_vp, _vp, _u32, _u64, ctypes.POINTER(_u64),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _vp],
@@ -189,6 +191,12 @@ class Circuit:
         """det/obs: int64 device tensors [rows][ceil(n/64)] (bit-packed uint64)."""
         _check(_lib.tmcs_sample(self._h, seed, instance, shot_begin, n_shots, _ptr(det), _ptr(obs),
                                 _stream(stream)))
+
+    def sample_async(self, seed, instance, shot_begin, n_shots, det, obs, overflow, stream=None):
+        """sample() without waiting; an event-buffer overflow sets the device flag
+        `overflow` (int32 tensor of one element, zeroed by the caller)."""
+        _check(_lib.tmcs_sample_async(self._h, seed, instance, shot_begin, n_shots, _ptr(det), _ptr(obs),
+                                      _ptr(overflow), _stream(stream)))
 
     def alloc_outputs(self, n_shots, device="cuda"):
         import torch
@@ -338,6 +346,11 @@ class Plan:
                     osd=st.osd, not_in_span=st.not_in_span, bp_iters=st.bp_iters,
                     osd_incomplete=st.osd_incomplete, osd_prefix_retry=st.osd_prefix_retry,
                     stat_shots=st.shots)
+
+
+def count_errors(pred, obs, k, n_shots, counter, stream=None):
+    """Add the failing-shot count to the device counter (int64 tensor of one element) without waiting."""
+    _check(_lib.tmcs_count_errors(_ptr(pred), _ptr(obs), k, n_shots, _ptr(counter), _stream(stream)))
 
 
 def logical_error_rate(pred, obs, k, n_shots, stream=None):

@@ -94,3 +94,32 @@ def test_sampler_rejects_bad_arguments(gpu_lib):
     with pytest.raises(gpu_lib.TmcsError):
         c.sample(1, 0, 32, 64, det, obs)   # shot_begin not a multiple of 64
     torch.cuda.synchronize()
+
+
+def test_async_sample_and_error_count_match_the_waiting_calls(gpu_lib):
+    """tmcs_sample_async writes the same bits as tmcs_sample (two shot ranges,
+    the second at an offset and ragged) and leaves the overflow flag clear;
+    tmcs_count_errors accumulates the count tmcs_logical_error_rate returns."""
+    import torch
+    spec = sc(5, NLCNOT, 5, 5, 3e-3, 2e-2)
+    print("[sampler] async sc5-nlcnot", flush=True)
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    k = c.num_observables
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for begin, n in ((0, 3 * 4096), (64 * 1000, 4096 + 70)):
+        det, obs = c.alloc_outputs(n)
+        c.sample(7, 0, begin, n, det, obs)
+        det2, obs2 = c.alloc_outputs(n)
+        c.sample_async(7, 0, begin, n, det2, obs2, flag)
+        torch.cuda.synchronize()
+        assert torch.equal(det, det2) and torch.equal(obs, obs2), begin
+        assert int(flag.item()) == 0
+        pred = torch.zeros_like(obs)
+        dem.decode(det, n, pred, max_iter=30)
+        ne, _, _ = gpu_lib.logical_error_rate(pred, obs, k, n)
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        gpu_lib.count_errors(pred, obs, k, n, cnt)
+        gpu_lib.count_errors(pred, obs, k, n, cnt)
+        torch.cuda.synchronize()
+        assert ne > 0 and int(cnt.item()) == 2 * ne, (begin, ne, int(cnt.item()))

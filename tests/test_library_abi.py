@@ -65,6 +65,11 @@ def test_sample_arguments_are_validated(lib, handles):
     assert "multiple of 64" in _err(lib)
     assert raw.tmcs_sample(c._h, 1, 0, 0, 0, None, None, None) == OK           # empty range
     assert raw.tmcs_sample(None, 1, 0, 0, 64, None, None, None) == EINVAL
+    # the non-waiting variants need their device flag / counter
+    assert raw.tmcs_sample_async(c._h, 1, 0, 0, 64, None, None, None, None) == EINVAL
+    assert "overflow" in _err(lib)
+    assert raw.tmcs_count_errors(None, None, 1, 64, None, None) == EINVAL
+    assert "counter" in _err(lib)
 
 
 def test_plan_arguments_are_validated(lib, handles):
