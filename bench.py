@@ -44,7 +44,7 @@ TRAFFIC = {
     "sc5_nlcnot": {
         "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
                  "sha256": "b5b323ca86e80a4567f6739786993d70d09e81bfaef8481a8a05985e616975ce",
-                 "fetch_kib": 72956.0, "write_kib": 133334.2},
+                 "fetch_kib": 72917.8, "write_kib": 133332.3},
         "k_frame": {"src": ['paper_2504_05611_amd/csrc/kernels/sample.hip', 'paper_2504_05611_amd/csrc/host/program.cpp'],
                     "sha256": "a995ee3c19865f8598c874400fecec85e360bbb766f1e7164d0f5f422eff8eb4",
                     "fetch_kib": 59909.7, "write_kib": 38549.7},
