@@ -164,23 +164,35 @@ __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
 }
 
 // Detector-major bit planes -> shot-major syndrome words for the chunk
-// [shot0, shot0 + nshots): one workgroup per (64-shot word, 64-detector tile),
-// a 64 x 64 bit transpose through LDS.
+// [shot0, shot0 + nshots): one workgroup per 64-shot word and group of up to
+// SYND_TILES 64-detector tiles, one 64 x 64 bit transpose through LDS per tile,
+// so a shot's syndrome words are written together.  Workgroups go to the 8
+// XCDs in turn, so the word index is remapped to give each XCD (and its L2) a
+// contiguous range of words: a detector row's cache lines are then fetched by
+// one L2, not eight.  gridDim.x is a multiple of 8, so every group of a word
+// lands on the same XCD.
+constexpr int N_XCD = 8;
+constexpr int SYND_TILES = 8;
 __global__ void __launch_bounds__(64) k_synd_transpose(const uint64_t* __restrict__ det, int32_t m, int64_t stride,
                                                        int64_t shot0, int64_t nshots, int32_t mw,
                                                        uint64_t* __restrict__ synd) {
   __shared__ uint64_t tile[64];
   const int lane = threadIdx.x;
-  const int64_t w = blockIdx.x;             // shot word within the chunk
-  const int rt = blockIdx.y;                // detector tile
-  const int row = rt * 64 + lane;
-  tile[lane] = row < m ? det[(int64_t)row * stride + (shot0 >> 6) + w] : 0ull;
-  __syncthreads();
-  uint64_t out = 0ull;
-#pragma unroll 16
-  for (int i = 0; i < 64; ++i) out |= ((tile[i] >> lane) & 1ull) << i;
+  const int64_t per_xcd = gridDim.x / N_XCD;
+  const int64_t w = (int64_t)(blockIdx.x % N_XCD) * per_xcd + blockIdx.x / N_XCD;   // shot word within the chunk
+  if (w * 64 >= nshots) return;             // padding workgroup (uniform: before any barrier)
   const int64_t s = w * 64 + lane;
-  if (s < nshots) synd[s * mw + rt] = out;
+  const int rt1 = min(mw, (int)(blockIdx.y + 1) * SYND_TILES);
+  for (int rt = blockIdx.y * SYND_TILES; rt < rt1; ++rt) {   // detector tiles of this group
+    const int row = rt * 64 + lane;
+    tile[lane] = row < m ? det[(int64_t)row * stride + (shot0 >> 6) + w] : 0ull;
+    __syncthreads();
+    uint64_t out = 0ull;
+#pragma unroll 16
+    for (int i = 0; i < 64; ++i) out |= ((tile[i] >> lane) & 1ull) << i;
+    if (s < nshots) synd[s * mw + rt] = out;
+    __syncthreads();                        // tile is refilled for the next detector tile
+  }
 }
 
 // Queue the shots of the chunk whose syndrome is non-zero.  Same-address
@@ -1495,7 +1507,9 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
     {
       const int64_t nw = (ns + 63) / 64;
       const int mt = std::max(mw, 1);
-      TMCS_LAUNCH("k_synd_transpose", k_synd_transpose, dim3((unsigned)nw, (unsigned)mt), dim3(64), 0, stream, det,
+      const int64_t gx = (nw + N_XCD - 1) / N_XCD * N_XCD;
+      TMCS_LAUNCH("k_synd_transpose", k_synd_transpose, dim3((unsigned)gx, (unsigned)((mt + SYND_TILES - 1) / SYND_TILES)),
+                  dim3(64), 0, stream, det,
                   D.rows, stride, s0, ns, mt, d->synd);
     }
     if (!full) {
