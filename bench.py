@@ -43,8 +43,8 @@ EVENT_APPLY_OPS = 4
 TRAFFIC = {
     "sc5_nlcnot": {
         "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
-                 "sha256": "ddeb05f442edcf20e2a696e46288ab92f4f7a1620d578b92d950496f5be12c0e",
-                 "fetch_kib": 72883.4, "write_kib": 133335.5},
+                 "sha256": "03be1640d29e262e7fa79b55d7c89ae35d2a88b8fc854330c6b0d2413b9f1bfa",
+                 "fetch_kib": 72915.6, "write_kib": 133335.7},
         "k_frame": {"src": ['paper_2504_05611_amd/csrc/kernels/sample.hip', 'paper_2504_05611_amd/csrc/host/program.cpp'],
                     "sha256": "a995ee3c19865f8598c874400fecec85e360bbb766f1e7164d0f5f422eff8eb4",
                     "fetch_kib": 59909.7, "write_kib": 38549.7},

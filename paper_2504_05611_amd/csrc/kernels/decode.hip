@@ -1459,8 +1459,9 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   // dense OSD-0 on a DEM wider than the prefix: prefix pass, then a full sort of the rest
   const int pfx_keys = osd_bl ? PFX_KEYS_WAVE : PFX_KEYS_WG;
   // the prefix holds at most pfx_keys - 1 columns, so at most that many pivots:
-  // its basis and pivot lists need pfx_rank rows, and with the basis in LDS
-  // more workgroups fit on a CU than for the full sort
+  // its basis and pivot lists need pfx_rank rows, and its grid follows from its
+  // own LDS (more workgroups per CU than for the full sort; a basis in HBM is
+  // sized for that grid)
   const int pfx_rank = std::min(osd_rank, pfx_keys);
   // and the one-wave variant's basis vectors carry PFX_KEYS_WAVE / 64 words of combination part
   const int W_pfx = osd_bl ? W / 2 + PFX_KEYS_WAVE / 64 : W;
@@ -1473,14 +1474,16 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int osd_per_cu = std::min(osd_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : (osd_bl ? 16 : 4));
   const int osd_grid = std::max(1, cus * osd_per_cu);
   const int pfx_fit = std::max<int>(1, (int)((160 * 1024) / (pfx_lds + 512)));
-  const int pfx_grid = osd_bl ? std::max(1, cus * std::min(pfx_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 16)) : osd_grid;
+  const int pfx_grid = std::max(1, cus * std::min(pfx_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 16));
   if ((st = grow(&d->queue, &d->cap_queue, (size_t)chunk)) != TMCS_OK) return st;
   if ((st = grow(&d->synd, &d->cap_synd, (size_t)chunk * (size_t)std::max(mw, 1))) != TMCS_OK) return st;
   if (gstate && (st = grow(&d->gstate, &d->cap_gstate, (size_t)cus * per_cu * team_bytes)) != TMCS_OK) return st;
   if (cfg.use_osd) {
     if ((st = grow(&d->osd_queue, &d->cap_osd, (size_t)chunk)) != TMCS_OK ||
         (st = grow(&d->osd_llr, &d->cap_llr, (size_t)chunk * (size_t)D.cols)) != TMCS_OK ||
-        (!osd_bl && (st = grow(&d->basis, &d->cap_basis, (size_t)osd_grid * (size_t)std::max(osd_rank, 1) * W)) != TMCS_OK))
+        (!osd_bl && (st = grow(&d->basis, &d->cap_basis,
+                               std::max((size_t)osd_grid * (size_t)std::max(osd_rank, 1) * W,
+                                        osd_pfx ? (size_t)pfx_grid * (size_t)std::max(pfx_rank, 1) * W_pfx : 0))) != TMCS_OK))
       return st;
     if (osd_pfx && (st = grow(&d->retry, &d->cap_retry, (size_t)chunk)) != TMCS_OK) return st;
     if (osd_win) {
