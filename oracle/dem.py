@@ -22,8 +22,12 @@ undetectable logical errors: they are counted and excluded.  Columns are
 sorted by (sorted detector list, observable mask) lexicographically.
 
 Parity: pinned by brute-force circuit distance of the d=3 surface-code
-operations (Table I) and by the detector marginals of sampled shots
-(tests/test_oracle_circuits.py, tests/test_oracle_sampler.py).
+operations (Table I), by the detector marginals of sampled shots, and by exact
+enumeration: the independent mechanisms of each channel reproduce the
+channel's Pauli distribution, the merge rule equals the XOR of two Bernoulli
+variables, and the DEM of one-channel circuits gives the exact joint detector
+distribution (tests/test_oracle_circuits.py, tests/test_oracle_sampler.py,
+tests/test_oracle_pins.py).
 """
 from __future__ import annotations
 
@@ -43,6 +47,13 @@ def component_prob(name: str, p: float) -> float:
     if name == "DEPOLARIZE2":
         return (1.0 - math.sqrt(math.sqrt(math.sqrt(1.0 - 16.0 * p / 15.0)))) / 2.0
     raise ValueError(name)
+
+
+def merge_prob(pa: float, pb: float) -> float:
+    """Probability that exactly one of two independent events (probabilities pa,
+    pb) happens: two mechanisms with the same symptom flip it together iff an odd
+    number of them fires."""
+    return pa + pb - 2.0 * pa * pb
 
 
 def site_table(circuit):
@@ -125,8 +136,7 @@ def build_dem(circuit, chunk: int = 65536) -> DEM:
             key = (d, om)
             q = fp[a + j]
             if key in merged:
-                pa = merged[key]
-                merged[key] = pa + q - 2.0 * pa * q
+                merged[key] = merge_prob(merged[key], q)
             else:
                 merged[key] = q
     cols = []
