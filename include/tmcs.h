@@ -43,8 +43,8 @@ typedef enum {
   TMCS_ENOMEM = 2,            /* host or device allocation failed */
   TMCS_EDEVICE = 3,           /* a HIP call failed (possibly an earlier async fault) */
   TMCS_EUNSUPPORTED = 4,      /* valid request outside what this build supports */
-  TMCS_ENONDETERMINISTIC = 5, /* reserved: a detector is random in the noiseless circuit */
-  TMCS_ENOTINSPAN = 6         /* reserved: OSD found a syndrome outside H's column space */
+  TMCS_ENONDETERMINISTIC = 5  /* tmcs_build_dem: a detector or observable is random in the
+                                 noiseless circuit (the message names it) */
 } tmcs_status;
 
 enum { TMCS_SC = 0, TMCS_BB = 1 };                                  /* code family */
@@ -125,7 +125,10 @@ tmcs_status tmcs_circuit_text(const tmcs_circuit* c, char* buf, size_t cap, size
  * site is propagated to the detectors and observables it flips (a backward
  * sensitivity sweep over the circuit); identical symptoms are merged with
  * p <- pa + pb - 2 pa pb in circuit order; columns are sorted by (detector
- * list, observable mask).  Host only; device copies are made on first use. */
+ * list, observable mask).  Host only; device copies are made on first use.
+ * The same sweep checks that every detector and observable has a fixed value
+ * in the noiseless circuit (detectors compare stabilizer measurements, Methods
+ * "Simulation"); otherwise the call fails with TMCS_ENONDETERMINISTIC. */
 tmcs_status tmcs_build_dem(const tmcs_circuit* c, tmcs_dem** out);
 void tmcs_free_dem(tmcs_dem* d);
 tmcs_status tmcs_dem_info(const tmcs_dem* d, int64_t info[TMCS_DEM_INFO_LEN]);
@@ -218,6 +221,7 @@ typedef struct {
 } tmcs_decoder_cfg;
 
 /* Decode statistics, accumulated on the device (caller zeroes them). */
+#define TMCS_BP_HIST_BINS 65
 typedef struct {
   uint64_t shots;        /* shots decoded */
   uint64_t nontrivial;   /* shots with a non-zero syndrome */
@@ -231,6 +235,9 @@ typedef struct {
                                 else 1023) did not span the syndrome and that were decoded
                                 again with a full sort; the result is the dense OSD-0's
                                 either way */
+  uint64_t bp_iter_hist[TMCS_BP_HIST_BINS]; /* shots by BP iteration count: bin t < 64 counts
+                                shots that ran exactly t iterations (0: all-zero syndrome),
+                                bin 64 those that ran 64 or more */
 } tmcs_decode_stats;
 
 /* Decode det_dev ([rows][ceil(n/64)], as written by tmcs_sample) and write the
@@ -247,6 +254,9 @@ tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg,
 
 /* Whole-operation logical error rate (Methods, "Decoding": a shot fails when
  * any of the k observables is predicted wrongly).  Synchronises the stream.
+ * The count is accumulated in a one-word device counter that the library
+ * allocates once per device on the first call and reuses; calls are serialised
+ * by a host lock held until the result is read.
  * n_errors_host receives the failing-shot count, ler = errors / n_shots and
  * sigma = sqrt(ler (1 - ler) / n_shots) (binomial standard deviation). */
 tmcs_status tmcs_logical_error_rate(const uint64_t* pred_obs_dev, const uint64_t* obs_dev,

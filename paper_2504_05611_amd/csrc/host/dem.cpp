@@ -24,8 +24,22 @@
 // p <- pa + pb - 2 pa pb; empty symptoms are dropped and observable-only
 // symptoms (undetectable logical errors) are counted and excluded.  Columns are
 // sorted by (detector list, observable mask) lexicographically.
+//
+// The same sweep checks that every detector and observable is deterministic in
+// the noiseless circuit (Methods, "Simulation": detectors compare stabilizer
+// measurements whose noiseless values agree).  Read backwards, an output is the
+// outcome of a Pauli P times records; sensX[q] holds the outputs whose P
+// anticommutes with X_q (a Z or Y on q) and sensZ[q] those whose P has an X or
+// Y on q.  The output is random when P anticommutes with the operator that a
+// reset prepares or a measurement measures at that point:
+//   R q / M q (Z basis)  : outputs in sensZ[q];   RX q / MX q : outputs in sensX[q]
+//   Bell pair (a, b)     : P restricted to (a, b) must lie in {II, XX, YY, ZZ},
+//                          so sensX[a] = sensX[b] and sensZ[a] = sensZ[b]
+//   start (all |0>)      : outputs in sensZ[q]
+// Such a circuit is rejected with TMCS_ENONDETERMINISTIC.
 #include <algorithm>
 #include <cmath>
+#include <string>
 #include <unordered_map>
 
 #include "internal.h"
@@ -120,6 +134,10 @@ tmcs_status build_dem(const Circuit& c, Dem* d) {
     chans.push_back({k, p});
     return (int)chans.size() - 1;
   };
+  // outputs (detectors, then observables) found random in the noiseless circuit
+  std::vector<char> nondet((size_t)nd + (size_t)std::max(c.num_obs, 0), 0);
+  auto mark = [&](const Set& s) { for (int32_t x : s) nondet[x] = 1; };
+  auto mark_diff = [&](const Set& a, const Set& b) { Set t = a; sym_into(t, b); mark(t); };
   std::unordered_map<Set, int32_t, SetHash> index;
   std::vector<Set> symptoms;
   std::vector<std::vector<uint16_t>> contrib;  // per symptom: channel ids, reverse circuit order
@@ -142,15 +160,32 @@ tmcs_status build_dem(const Circuit& c, Dem* d) {
         for (size_t i = 0; i + 1 < op.t.size(); i += 2) sym_into(rec[op.t[i]], sz[op.t[i + 1]]);
         break;
       case OP_M:
-        for (size_t i = 0; i < op.t.size(); ++i) sym_into(sx[op.t[i]], rec[first_rec[ii] + i]);
+        for (size_t i = 0; i < op.t.size(); ++i) {
+          mark(sz[op.t[i]]);
+          sym_into(sx[op.t[i]], rec[first_rec[ii] + i]);
+        }
         break;
       case OP_MX:
-        for (size_t i = 0; i < op.t.size(); ++i) sym_into(sz[op.t[i]], rec[first_rec[ii] + i]);
+        for (size_t i = 0; i < op.t.size(); ++i) {
+          mark(sx[op.t[i]]);
+          sym_into(sz[op.t[i]], rec[first_rec[ii] + i]);
+        }
         break;
       case OP_R:
       case OP_RX:
+        for (int32_t q : op.t) {
+          mark(op.kind == OP_R ? sz[q] : sx[q]);
+          sx[q].clear();
+          sz[q].clear();
+        }
+        break;
       case OP_BELL:
-        for (int32_t q : op.t) { sx[q].clear(); sz[q].clear(); }
+        for (size_t i = 0; i + 1 < op.t.size(); i += 2) {
+          const int32_t a = op.t[i], b = op.t[i + 1];
+          mark_diff(sx[a], sx[b]);
+          mark_diff(sz[a], sz[b]);
+          sx[a].clear(); sz[a].clear(); sx[b].clear(); sz[b].clear();
+        }
         break;
       case OP_H:
         for (int32_t q : op.t) sx[q].swap(sz[q]);
@@ -203,6 +238,14 @@ tmcs_status build_dem(const Circuit& c, Dem* d) {
         break;
     }
   }
+  for (int q = 0; q < Q; ++q) mark(sz[q]);      // every qubit starts in |0>
+  for (size_t x = 0; x < nondet.size(); ++x)
+    if (nondet[x]) {
+      const bool det = (int)x < nd;
+      return fail(TMCS_ENONDETERMINISTIC, std::string(det ? "detector " : "observable ") +
+                                             std::to_string(det ? (int)x : (int)x - nd) +
+                                             " is not deterministic in the noiseless circuit");
+    }
   if (chans.size() > 65535) return fail(TMCS_EUNSUPPORTED, "too many distinct noise channels");
 
   struct Col { Set dets; uint64_t om; double p; };

@@ -43,7 +43,7 @@ struct Item {
   uint64_t* det = nullptr;
   uint64_t* obs = nullptr;
   uint64_t* pred = nullptr;
-  // device block: [0] block offset, [1] errors, [2] overflow flag (u32), [3..10] stats
+  // device block: [0] block offset, [1] errors, [2] overflow flag (u32), [3..] stats
   uint64_t* dev = nullptr;
   // private sampler / decoder states: a captured graph keeps pointing at their
   // scratch, which calls on the circuit and DEM handles may reallocate
@@ -63,7 +63,7 @@ struct Plan {
   hipGraphExec_t exec = nullptr;
 };
 
-static constexpr int DEV_WORDS = 16;
+static constexpr int DEV_WORDS = 3 + (int)(sizeof(tmcs_decode_stats) / sizeof(uint64_t));
 
 static tmcs_status enqueue_batch(Plan& p, hipStream_t s) {
   for (Item& it : p.items) {

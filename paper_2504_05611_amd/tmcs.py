@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 TMCS_SC, TMCS_BB = 0, 1
 TMCS_MEMORY, TMCS_NONLOCAL_CNOT, TMCS_TELEPORT, TMCS_PAULI_STRING = 0, 1, 2, 3
 STATUS = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "EUNSUPPORTED",
-          5: "ENONDETERMINISTIC", 6: "ENOTINSPAN"}
+          5: "ENONDETERMINISTIC"}
 INFO_KEYS = ["qubits", "gates_1q", "gates_2q", "meas", "meas_final", "detectors",
              "observables", "noise_sites", "instructions", "code_n", "code_k", "events_per_mshot"]
 DEM_KEYS = ["rows", "cols", "obs", "edges", "rank", "undetectable", "max_row_deg", "max_col_deg"]
@@ -63,7 +63,11 @@ class DecodeStats(ctypes.Structure):
     _fields_ = [("shots", ctypes.c_uint64), ("nontrivial", ctypes.c_uint64),
                 ("converged", ctypes.c_uint64), ("osd", ctypes.c_uint64),
                 ("not_in_span", ctypes.c_uint64), ("bp_iters", ctypes.c_uint64),
-                ("osd_incomplete", ctypes.c_uint64), ("osd_prefix_retry", ctypes.c_uint64)]
+                ("osd_incomplete", ctypes.c_uint64), ("osd_prefix_retry", ctypes.c_uint64),
+                ("bp_iter_hist", ctypes.c_uint64 * 65)]
+
+
+STATS_WORDS = 8 + 65          # tmcs_decode_stats: 8 counters and the 65-bin BP iteration histogram
 
 
 class PlanItem(ctypes.Structure):
@@ -345,7 +349,7 @@ class Plan:
         return dict(shots=shots.value, errors=errs.value, nontrivial=st.nontrivial, converged=st.converged,
                     osd=st.osd, not_in_span=st.not_in_span, bp_iters=st.bp_iters,
                     osd_incomplete=st.osd_incomplete, osd_prefix_retry=st.osd_prefix_retry,
-                    stat_shots=st.shots)
+                    stat_shots=st.shots, bp_iter_hist=[int(x) for x in st.bp_iter_hist])
 
 
 def count_errors(pred, obs, k, n_shots, counter, stream=None):
@@ -382,11 +386,11 @@ def timing_report() -> dict:
 
 def new_stats(device="cuda"):
     import torch
-    return torch.zeros(8, dtype=torch.int64, device=device)
+    return torch.zeros(STATS_WORDS, dtype=torch.int64, device=device)
 
 
 def read_stats(t) -> dict:
     v = t.cpu().numpy().astype(np.uint64)
     return dict(shots=int(v[0]), nontrivial=int(v[1]), converged=int(v[2]), osd=int(v[3]),
                 not_in_span=int(v[4]), bp_iters=int(v[5]), osd_incomplete=int(v[6]),
-                osd_prefix_retry=int(v[7]))
+                osd_prefix_retry=int(v[7]), bp_iter_hist=[int(x) for x in v[8:8 + 65]])

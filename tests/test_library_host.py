@@ -120,3 +120,32 @@ def test_distance_search_matches_table1(lib, key, op):
     spec = sc(int(key[2:]), NLCNOT if op == "nlcnot" else TELEPORT, 4, 3)
     d = lib.DEM(lib.Circuit(spec))
     assert d.distance(max_active=6, max_weight=12, max_states=5_000_000) == t1[op][key]
+
+
+def test_nondeterministic_outputs_are_rejected(tmp_path):
+    """The DEM builder's noiseless-determinism check (ENONDETERMINISTIC = 5) on
+    hand-written circuits whose answer is textbook stabilizer algebra: a |+>
+    measured in Z, H on a fresh qubit, one half of a Bell pair and an
+    uncorrected teleportation are random; repeated measurements, the ZZ and XX
+    parities of a Bell pair and a corrected teleportation are deterministic."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    csrc = os.path.join(ROOT, "paper_2504_05611_amd", "csrc")
+    exe = str(tmp_path / "nondet_check")
+    subprocess.run([gxx, "-std=c++17", "-O1", "-I" + os.path.join(ROOT, "include"), "-I" + csrc,
+                    os.path.join(ROOT, "tests", "native", "nondet_check.cpp"),
+                    os.path.join(csrc, "host", "dem.cpp"), os.path.join(csrc, "host", "codes.cpp"),
+                    "-o", exe], check=True, capture_output=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.splitlines()
+    got = {line.split()[0]: (int(line.split()[1]), " ".join(line.split()[2:])) for line in out}
+    det = ["reset_measure", "repeat_measure", "bell_zz", "bell_xx", "teleport_corrected"]
+    rand = ["rx_measure_z", "start_h_measure", "bell_half", "bell_zx", "teleport_uncorrected", "random_observable"]
+    for name in det:
+        assert got[name][0] == 0, (name, got[name])
+    for name in rand:
+        assert got[name][0] == 5, (name, got[name])
+    assert got["random_observable"][1].startswith("observable 0")
+    assert got["bell_half"][1].startswith("detector 0")
