@@ -174,6 +174,25 @@ tmcs_status tmcs_sample_async(const tmcs_circuit* c, uint64_t seed, uint32_t ins
                               uint64_t shot_begin, uint64_t n_shots, uint64_t* det_dev,
                               uint64_t* obs_dev, uint32_t* overflow_dev, void* stream);
 
+/* tmcs_sample_async for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * shots and outputs, but the event scratch (per-(block, site) counts and offsets,
+ * scan partials, the event buffer) lives in a fixed 64 MiB device array of the
+ * library, one per GPU, held until the process ends; the call allocates nothing
+ * and never waits.  Shot ranges are processed in chunks of 4096-shot blocks that
+ * fit that array.  Requirements and errors:
+ *  - the circuit's program must already be on the current device (any earlier
+ *    tmcs_sample / tmcs_sample_async call there uploads it); otherwise TMCS_EINVAL;
+ *  - overflow_dev as for tmcs_sample_async (NULL: TMCS_EINVAL);
+ *  - a circuit whose event scratch for one 4096-shot block exceeds 64 MiB
+ *    (roughly > 1.5e3 expected noise events per shot): TMCS_EUNSUPPORTED.
+ * All calls on one GPU share the array, which keeps the last call's contents
+ * (every call overwrites what it reads): calls that overlap in time on one GPU
+ * (different streams, or several host threads) race and give invalid outputs. */
+tmcs_status tmcs_sample_noalloc(const tmcs_circuit* c, uint64_t seed, uint32_t instance,
+                                uint64_t shot_begin, uint64_t n_shots, uint64_t* det_dev,
+                                uint64_t* obs_dev, uint32_t* overflow_dev, void* stream);
+
 /* Decoder configuration: flooding min-sum BP over the DEM with an OSD-0 fallback
  * (Supplementary Note 7 names BP-OSD).  With priors lambda_v = ln((1-p_v)/p_v):
  *   m_{c->v} = (-1)^{s_c} prod_{v' != v} sgn(q_{v'->c}) * alpha * min_{v' != v} |q_{v'->c}|,

@@ -147,6 +147,16 @@ tmcs_status tmcs_sample_async(const tmcs_circuit* c, uint64_t seed, uint32_t ins
   })
 }
 
+tmcs_status tmcs_sample_noalloc(const tmcs_circuit* c, uint64_t seed, uint32_t instance, uint64_t shot_begin,
+                                uint64_t n_shots, uint64_t* det_dev, uint64_t* obs_dev, uint32_t* overflow_dev,
+                                void* stream) {
+  if (!c) return fail(TMCS_EINVAL, "null circuit");
+  TMCS_TRY({
+    return sample_noalloc_run(c->c, seed, instance, shot_begin, n_shots, det_dev, obs_dev, overflow_dev,
+                              (hipStream_t)stream);
+  })
+}
+
 tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg, const uint64_t* det_dev,
                         uint64_t n_shots, uint64_t* pred_obs_dev, tmcs_decode_stats* stats_dev,
                         void* stream) {

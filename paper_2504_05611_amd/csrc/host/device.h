@@ -13,10 +13,17 @@ tmcs_status hip_check(hipError_t e, const char* what);
 // blk_off (device, nullable): added to every block index of the noise streams;
 // overflow_out (device, nullable): sticky event-buffer overflow flag owned by the
 // caller, in which case the call neither clears nor checks it and never waits.
+// fixed (device, nullable): event scratch of fixed_bytes bytes to use instead of
+// the state's growing buffers (chunks are sized to fit it).
 tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint64_t shot_begin,
                        uint64_t n_shots, uint64_t* det, uint64_t* obs, hipStream_t stream,
                        const uint64_t* blk_off = nullptr, uint32_t* overflow_out = nullptr,
-                       void* state = nullptr);
+                       void* state = nullptr, unsigned char* fixed = nullptr, size_t fixed_bytes = 0);
+// tmcs_sample_noalloc: the sampler on the library's static device scratch; the
+// circuit's program must already be on the current device.
+tmcs_status sample_noalloc_run(const Circuit& c, uint64_t seed, uint32_t instance, uint64_t shot_begin,
+                               uint64_t n_shots, uint64_t* det, uint64_t* obs, uint32_t* overflow,
+                               hipStream_t stream);
 // A private device state (program, tables, scratch) for callers whose launches
 // must keep pointing at the same buffers, e.g. a captured graph; state = nullptr
 // in sample_run uses the state cached on the circuit handle.

@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <string>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 
@@ -574,11 +576,34 @@ tmcs_status launch_frame(const FrameArgs& a, int64_t nwg, size_t lds, hipStream_
   return hip_check(hipGetLastError(), "k_frame launch");
 }
 
+// Scratch of the no-allocation sampler (tmcs_sample_noalloc): a file-scope
+// device array, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel: it uses the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[64] = {};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Bytes of event scratch for a chunk of nblk blocks: counts and offsets
+// (n + 1 each), scan partials, and the event buffer (its capacity as below).
+size_t chunk_scratch_bytes(int64_t nsites, int64_t nblk, double events_per_shot, size_t* cap_out) {
+  const int64_t n = nblk * nsites;
+  const double mean = events_per_shot * (double)(nblk * SB);
+  const size_t cap = (size_t)(mean * 1.25 + 16.0 * std::sqrt(mean) + 65536.0);
+  const int64_t ntiles = (n + 1 + SCAN_TILE - 1) / SCAN_TILE;
+  if (cap_out) *cap_out = cap;
+  return 2 * align256((size_t)(n + 1) * 4) + align256((size_t)(ntiles + 1) * 4) + align256(cap * 8);
+}
+
 }  // namespace
 
 tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint64_t shot_begin,
                        uint64_t n_shots, uint64_t* det, uint64_t* obs, hipStream_t stream,
-                       const uint64_t* blk_off, uint32_t* overflow_out, void* state) {
+                       const uint64_t* blk_off, uint32_t* overflow_out, void* state,
+                       unsigned char* fixed, size_t fixed_bytes) {
   if (shot_begin % 64) return fail(TMCS_EINVAL, "shot_begin must be a multiple of 64");
   if (n_shots == 0) return TMCS_OK;
   if ((c.num_dets && !det) || (c.num_obs && !obs)) return fail(TMCS_EINVAL, "null output buffer");
@@ -602,6 +627,16 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
   const int64_t blk_first = (int64_t)(shot_begin / SB);
   const int64_t blk_last = (int64_t)((shot_end - 1) / SB);
   int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(256, (64ll << 20) / std::max<int64_t>(nsites, 1)));
+  if (fixed) {
+    // the largest chunk whose scratch fits the caller-provided area
+    if (chunk_scratch_bytes(nsites, 1, P.events_per_shot, nullptr) > fixed_bytes)
+      return fail(TMCS_EUNSUPPORTED, "this circuit needs " +
+                  std::to_string(chunk_scratch_bytes(nsites, 1, P.events_per_shot, nullptr)) +
+                  " bytes of event scratch per 4096-shot block; the no-allocation scratch holds " +
+                  std::to_string(fixed_bytes));
+    while (chunk > 1 && chunk_scratch_bytes(nsites, chunk, P.events_per_shot, nullptr) > fixed_bytes)
+      chunk = std::max<int64_t>(1, chunk / 2);
+  }
   for (int64_t b0 = blk_first; b0 <= blk_last; b0 += chunk) {
     const int64_t b1 = std::min(blk_last + 1, b0 + chunk);
     const int64_t nblk = b1 - b0;
@@ -612,29 +647,42 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
     const size_t cap = (size_t)(mean * 1.25 + 16.0 * std::sqrt(mean) + 65536.0);
     if (cap >= 0xFFFFFFF0ull) return fail(TMCS_EUNSUPPORTED, "too many noise events per chunk");
     const int64_t ntiles = (n + 1 + SCAN_TILE - 1) / SCAN_TILE;
-    if ((st = grow(&d->counts, &d->cap_counts, (size_t)n + 1)) != TMCS_OK ||
-        (st = grow(&d->offsets, &d->cap_offsets, (size_t)n + 1)) != TMCS_OK ||
-        (st = grow(&d->partial, &d->cap_partial, (size_t)ntiles + 1)) != TMCS_OK ||
-        (st = grow(&d->events, &d->cap_events, cap)) != TMCS_OK)
-      return st;
+    uint32_t *counts, *offsets, *partial;
+    uint64_t* events;
+    size_t cap_events;
+    if (fixed) {
+      counts = (uint32_t*)fixed;
+      offsets = (uint32_t*)(fixed + align256((size_t)(n + 1) * 4));
+      partial = (uint32_t*)(fixed + 2 * align256((size_t)(n + 1) * 4));
+      events = (uint64_t*)(fixed + 2 * align256((size_t)(n + 1) * 4) + align256((size_t)(ntiles + 1) * 4));
+      cap_events = cap;
+    } else {
+      if ((st = grow(&d->counts, &d->cap_counts, (size_t)n + 1)) != TMCS_OK ||
+          (st = grow(&d->offsets, &d->cap_offsets, (size_t)n + 1)) != TMCS_OK ||
+          (st = grow(&d->partial, &d->cap_partial, (size_t)ntiles + 1)) != TMCS_OK ||
+          (st = grow(&d->events, &d->cap_events, cap)) != TMCS_OK)
+        return st;
+      counts = d->counts; offsets = d->offsets; partial = d->partial; events = d->events;
+      cap_events = d->cap_events;
+    }
     if (nsites > 0) {
       const int thr = 256;
       const int64_t grid = std::min<int64_t>((n + thr - 1) / thr, 1 << 20);
       TMCS_LAUNCH("k_event_count", k_event_count, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
-                         instance, d->site_kind, d->site_tab, d->tabs, d->tab_inv, d->counts, blk_off);
-      TMCS_LAUNCH("k_scan_partials", k_scan_partials, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial);
-      TMCS_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, stream, d->partial, ntiles);
-      TMCS_LAUNCH("k_scan_final", k_scan_final, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, d->counts, n, d->partial, d->offsets);
+                         instance, d->site_kind, d->site_tab, d->tabs, d->tab_inv, counts, blk_off);
+      TMCS_LAUNCH("k_scan_partials", k_scan_partials, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, counts, n, partial);
+      TMCS_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, stream, partial, ntiles);
+      TMCS_LAUNCH("k_scan_final", k_scan_final, dim3((unsigned)ntiles), dim3(SCAN_THREADS), 0, stream, counts, n, partial, offsets);
       TMCS_LAUNCH("k_event_write", k_event_write, dim3((unsigned)grid), dim3(thr), 0, stream, nsites, nblk, b0, k0, k1,
-                         instance, d->site_kind, d->site_tab, d->tabs, d->tab_inv, d->site_q, d->offsets, d->events,
-                         (uint32_t)d->cap_events, flag, blk_off);
+                         instance, d->site_kind, d->site_tab, d->tabs, d->tab_inv, d->site_q, offsets, events,
+                         (uint32_t)cap_events, flag, blk_off);
       if ((st = hip_check(hipGetLastError(), "event kernels")) != TMCS_OK) return st;
     }
     FrameArgs a;
     a.layers = d->layers; a.data = d->data; a.mslots = d->mslots;
     a.nlayers = P.num_layers; a.Q = c.num_qubits; a.nslots = P.nslots; a.nsites = (int32_t)nsites;
     a.nnoise = d->nnoise; a.noise_s0 = d->noise_s0; a.noise_cnt = d->noise_cnt;
-    a.offsets = d->offsets; a.events = d->events; a.capacity = (uint32_t)d->cap_events;
+    a.offsets = offsets; a.events = events; a.capacity = (uint32_t)cap_events;
     a.blk0 = b0;
     a.word_lo = (int64_t)(s_lo / 64);
     a.word_hi = (int64_t)((s_hi + 63) / 64);
@@ -661,6 +709,32 @@ tmcs_status sample_run(const Circuit& c, uint64_t seed, uint32_t instance, uint6
   if ((st = hip_check(hipStreamSynchronize(stream), "sample synchronize")) != TMCS_OK) return st;
   if (hflag) return fail(TMCS_EDEVICE, "noise event buffer overflow");
   return TMCS_OK;
+}
+
+tmcs_status sample_noalloc_run(const Circuit& c, uint64_t seed, uint32_t instance, uint64_t shot_begin,
+                               uint64_t n_shots, uint64_t* det, uint64_t* obs, uint32_t* overflow, hipStream_t stream) {
+  if (!overflow) return fail(TMCS_EINVAL, "null overflow flag");
+  int dev = 0;
+  tmcs_status st = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (st != TMCS_OK) return st;
+  if (dev < 0 || dev >= 64) return fail(TMCS_EUNSUPPORTED, "device index beyond 63");
+  const SampleDevice* d = (const SampleDevice*)c.device;
+  if (!d || d->device != dev)
+    return fail(TMCS_EINVAL, "the circuit's program is not on this device: call tmcs_sample or "
+                             "tmcs_sample_async once on it first (the no-allocation call uploads nothing)");
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      if ((st = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress (scratch)")) != TMCS_OK)
+        return st;
+      g_scratch_ptr[dev] = (unsigned char*)ptr;
+    }
+    base = g_scratch_ptr[dev];
+  }
+  return sample_run(c, seed, instance, shot_begin, n_shots, det, obs, stream, nullptr, overflow,
+                    const_cast<SampleDevice*>(d), base, NOALLOC_BYTES);
 }
 
 void* sample_state_new(const Circuit& c, tmcs_status* st) {

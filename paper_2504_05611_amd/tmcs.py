@@ -88,6 +88,7 @@ _SIGS = {
     "tmcs_dem_distance": [_vp, _i32, _i32, ctypes.c_int64, ctypes.POINTER(_i32)],
     "tmcs_sample": [_vp, _u64, _u32, _u64, _u64, _vp, _vp, _vp],
     "tmcs_sample_async": [_vp, _u64, _u32, _u64, _u64, _vp, _vp, _vp, _vp],
+    "tmcs_sample_noalloc": [_vp, _u64, _u32, _u64, _u64, _vp, _vp, _vp, _vp],
     "tmcs_count_errors": [_vp, _vp, _u32, _u64, _vp, _vp],
     "tmcs_decode": [_vp, ctypes.POINTER(DecoderCfg), _vp, _u64, _vp, _vp, _vp],
     "tmcs_logical_error_rate": [_vp, _vp, _u32, _u64, ctypes.POINTER(_u64),
@@ -201,6 +202,12 @@ class Circuit:
         `overflow` (int32 tensor of one element, zeroed by the caller)."""
         _check(_lib.tmcs_sample_async(self._h, seed, instance, shot_begin, n_shots, _ptr(det), _ptr(obs),
                                       _ptr(overflow), _stream(stream)))
+
+    def sample_noalloc(self, seed, instance, shot_begin, n_shots, det, obs, overflow, stream=None):
+        """sample_async() on the library's fixed device scratch (no allocation); the
+        program must already be on the device (an earlier sample/sample_async call)."""
+        _check(_lib.tmcs_sample_noalloc(self._h, seed, instance, shot_begin, n_shots, _ptr(det), _ptr(obs),
+                                        _ptr(overflow), _stream(stream)))
 
     def alloc_outputs(self, n_shots, device="cuda"):
         import torch
