@@ -55,7 +55,7 @@ struct DecodeDevice {
   int32_t E4 = 0;
   int32_t max_row_deg = 0;
   // per-lane BP schedules, one per team size used so far
-  struct Sched { int P = 0; bool contig = false; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr; };
+  struct Sched { int P = 0; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr; };
   std::vector<Sched> scheds;
   // scratch
   int32_t* counters = nullptr;     // [0] queue len, [1] bp next, [2] osd len, [3] osd next
@@ -520,38 +520,16 @@ int lpt_assign(const std::vector<int>& size, int P, std::vector<std::vector<int>
   return (int)kmax;
 }
 
-// Contiguous assignment: lane l gets the items of one index range, the ranges
-// cut where the running size passes l * total / P.  A lane then walks its
-// checks (or columns) and, in a DEM whose detectors and columns are numbered
-// in space-time order, their neighbours in ascending address order, so a cache
-// line it fetches serves its next steps too.  Returns the max load.
-int contig_assign(const std::vector<int>& size, int P, std::vector<std::vector<int>>* lanes) {
-  lanes->assign(P, {});
-  long total = 0;
-  for (int x : size) total += x;
-  long run = 0, kmax = 0, load = 0;
-  int l = 0;
-  for (size_t i = 0; i < size.size(); ++i) {
-    if (size[i] == 0) continue;
-    // move on once this lane has its share (never past the last lane)
-    while (l < P - 1 && run >= (total * (long)(l + 1) + P - 1) / P) { kmax = std::max(kmax, load); load = 0; ++l; }
-    (*lanes)[l].push_back((int)i);
-    run += size[i];
-    load += size[i];
-  }
-  return (int)std::max(kmax, load);
-}
-
-// Schedules of the check and variable passes for team size P (cached per P and
-// assignment): longest-processing-time for state in LDS, contiguous ranges for
-// state in device memory.
-tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, bool contig, DecodeDevice::Sched* out) {
+// Schedules of the check and variable passes for team size P (cached per P).
+// Longest-processing-time lists, also for state in device memory: contiguous
+// per-lane ranges put the lanes of a step a fixed stride apart in memory and
+// were 7x slower there (HBM channel conflicts).
+tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, DecodeDevice::Sched* out) {
   for (const auto& q : d->scheds)
-    if (q.P == P && q.contig == contig) { *out = q; return TMCS_OK; }
+    if (q.P == P) { *out = q; return TMCS_OK; }
   DecodeDevice::Sched q;
   q.P = P;
-  q.contig = contig;
-  auto assign = contig ? contig_assign : lpt_assign;
+  auto assign = lpt_assign;
   std::vector<std::vector<int>> lanes;
   std::vector<int> rdeg(std::max(D.rows, 0)), cdeg(std::max(D.cols, 0));
   for (int c = 0; c < D.rows; ++c) rdeg[c] = D.row_ptr[c + 1] - D.row_ptr[c];
@@ -665,7 +643,7 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   }
   P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
   DecodeDevice::Sched sch;
-  if ((st = get_sched(D, d, P, gstate, &sch)) != TMCS_OK) return st;
+  if ((st = get_sched(D, d, P, &sch)) != TMCS_OK) return st;
   if (!gstate && bp_lds > 64 * 1024 &&
       (hipFuncSetAttribute((const void*)k_bp<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
        hipFuncSetAttribute((const void*)k_bp<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess))
