@@ -85,7 +85,7 @@ typedef struct {
    * block CNOTs 1 -> 2 -> ... -> w (non-local for the 1st, 3rd, ... link, local
    * transversal for the others) and a local CNOT w -> ancilla, each followed by
    * one round on its two blocks; every block's Z logicals are observables (at
-   * most 64 in all).  rounds_after is ignored. */
+   * most 256 in all).  rounds_after is ignored. */
   int32_t weight;
 } tmcs_circuit_spec;
 
@@ -134,8 +134,11 @@ void tmcs_free_dem(tmcs_dem* d);
 tmcs_status tmcs_dem_info(const tmcs_dem* d, int64_t info[TMCS_DEM_INFO_LEN]);
 
 /* Host copy of the DEM: column-compressed H (col_ptr[cols+1], row_idx[edges],
- * rows ascending within a column), priors[cols], obs_mask[cols] (bit o set when
- * the mechanism flips observable o; observables <= 64).  NULL pointers skip. */
+ * rows ascending within a column), priors[cols], obs_mask[cols][ceil(obs/64)]
+ * (bit o % 64 of word o / 64 set when the mechanism flips observable o; one
+ * word per column up to 64 observables, at most 256 observables).  Columns are
+ * sorted by detector list, then by the mask read as one integer.  NULL
+ * pointers skip. */
 tmcs_status tmcs_dem_export(const tmcs_dem* d, int32_t* col_ptr, int32_t* row_idx,
                             double* priors, uint64_t* obs_mask);
 
@@ -147,7 +150,7 @@ tmcs_status tmcs_dem_export(const tmcs_dem* d, int32_t* col_ptr, int32_t* row_id
  * Breadth-first over (active detection events, observable mask), growing a state
  * only by mechanisms on its smallest active detector; exact when max_active is
  * at least the number of detectors and the state budget suffices, an upper
- * bound otherwise.  Host only. */
+ * bound otherwise.  Host only; DEMs with at most 64 observables. */
 tmcs_status tmcs_dem_distance(const tmcs_dem* d, int32_t max_active, int32_t max_weight,
                               int64_t max_states, int32_t* weight);
 
@@ -231,6 +234,12 @@ typedef struct {
                                otherwise a positive multiple of 64 that caps it.  Results
                                never depend on it (each pass ends on its slowest shots, so
                                fewer passes are faster) */
+  int32_t bp_sched;         /* how a BP team's lanes share checks and columns (launch shape;
+                               results never depend on it): 0 = library default, 1 =
+                               longest-processing-time lists, 2 = strided (lane l of P takes
+                               items l, l + P, ...: the lanes of a wave touch consecutive
+                               checks and columns, so state in device memory is read in
+                               whole cache lines) */
   /* optional per-shot outputs (NULL to skip), each indexed by shot of the call: */
   uint8_t* ehat_dev;        /* [n_shots][cols] final correction (0/1 bytes) */
   float* llr_dev;           /* [n_shots][cols] final BP posterior LLRs */
@@ -325,6 +334,12 @@ tmcs_status tmcs_autotune(const tmcs_dem* d, const uint64_t* det_dev, uint64_t n
  * pipeline of one or more items (circuit, DEM, decoder settings, seed,
  * instance id) for batches of batch_shots shots (a multiple of 4096), and with
  * use_graph = 1 captures one batch of every item into a single HIP graph.
+ * The items' decoders run together: one BP launch serves every item whose BP
+ * state sits in LDS and one every item whose state sits in device memory (per
+ * team size), and one launch runs the windowed OSD-0 of every item that uses
+ * it, each pulling jobs from all those items in turn; other OSD variants run
+ * per item.  (When an item's batch needs more than one decoder pass, the items
+ * decode one after another instead.)
  * Each tmcs_plan_run batch processes the next shot range of every item:
  * shots [k B, (k+1) B) on the k-th batch, with the same bits as tmcs_sample /
  * tmcs_decode on that range.  Counts accumulate on the device;
@@ -341,6 +356,10 @@ typedef struct {
 } tmcs_plan_item;
 tmcs_status tmcs_plan_create(const tmcs_plan_item* items, int32_t n_items, uint64_t batch_shots,
                              int32_t use_graph, tmcs_plan** out);
+/* tmcs_plan_run: n_batches batches on stream.  While kernel timing is enabled
+ * (tmcs_timing_enable) the batches run as eager launches of the same kernels on
+ * the same buffers instead of graph replays, so that every launch is timed;
+ * the results are the same either way. */
 tmcs_status tmcs_plan_run(tmcs_plan* p, uint32_t n_batches, void* stream);
 tmcs_status tmcs_plan_result(tmcs_plan* p, int32_t item, uint64_t* shots, uint64_t* errors,
                              tmcs_decode_stats* stats, void* stream);

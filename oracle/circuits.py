@@ -45,8 +45,9 @@ circuit; Fig. 1b/1c; Table III).  Readings where the paper is silent:
 * The conditional Z of the non-local CNOT acts on the control block (gate
   teleportation); it touches only X-basis records.
 * Schedules: surface code 4 interleaved CX layers (X checks NW, NE, SW, SE;
-  Z checks NW, SW, NE, SE); BB code six Z-check layers (terms of B^T, A^T)
-  then six X-check layers (terms of A, B).
+  Z checks NW, SW, NE, SE); BB code the interleaved depth-7 cycle of
+  oracle.codes.BB_X_STEPS / BB_Z_STEPS (each step: one term of every X check
+  and one term of every Z check on the other half of the data).
 * Pauli-string compute (Methods, Pauli string compute): blocks 1..w and the
   ancilla start in |0> with rounds_before rounds on all of them; CNOT m -> m+1
   for m = 1..w-1 is non-local for odd m and local (transversal CX with

@@ -136,6 +136,14 @@ def surface_code(d: int) -> Code:
     return c
 
 
+# BB syndrome schedule: the term each X (Z) check applies at each of the 7 CX
+# steps of a round (-1: idle).  This is the depth-optimised interleaved cycle of
+# the bivariate-bicycle memory experiments the paper builds its BB circuits on
+# (Methods, "Simulation").
+BB_X_STEPS = (-1, 1, 4, 3, 5, 0, 2)
+BB_Z_STEPS = (3, 5, 0, 1, 2, 4, -1)
+
+
 def _mono_perm(l: int, m: int, a: int, b: int) -> np.ndarray:
     """Column index of the single 1 in each row of x^a y^b (length lm)."""
     r = np.arange(l * m)
@@ -169,17 +177,20 @@ def bb_code(name: str) -> Code:
     c.A, c.B = A, B
     c.hx = np.concatenate([A, B], axis=1)
     c.hz = np.concatenate([B.T, A.T], axis=1)
-    # Z checks first (terms of [B^T | A^T]), then X checks (terms of [A | B])
+    # Interleaved depth-7 schedule (R16): step t runs one term of every X check
+    # and one term of every Z check on the other half of the data.  X terms
+    # 0-2 are A_1..A_3 (left data), 3-5 are B_1..B_3 (right data); Z terms 0-2
+    # are B_1^T..B_3^T (left data), 3-5 are A_1^T..A_3^T (right data).
     inv = lambda p: np.argsort(p)
     rows = np.arange(h)
-    z_layers = [[(int(r), int(inv(p)[r])) for r in rows] for p in pb] + \
-               [[(int(r), h + int(inv(p)[r])) for r in rows] for p in pa]
-    x_layers = [[(int(r), int(p[r])) for r in rows] for p in pa] + \
-               [[(int(r), h + int(p[r])) for r in rows] for p in pb]
-    c.z_sched = z_layers + [[] for _ in range(6)]
-    c.x_sched = [[] for _ in range(6)] + x_layers
-    c.sched_layers = 12
-    c.interleaved = False
+    x_term = [[(int(r), int(p[r])) for r in rows] for p in pa] + \
+             [[(int(r), h + int(p[r])) for r in rows] for p in pb]
+    z_term = [[(int(r), int(inv(p)[r])) for r in rows] for p in pb] + \
+             [[(int(r), h + int(inv(p)[r])) for r in rows] for p in pa]
+    c.x_sched = [x_term[t] if t >= 0 else [] for t in BB_X_STEPS]
+    c.z_sched = [z_term[t] if t >= 0 else [] for t in BB_Z_STEPS]
+    c.sched_layers = len(BB_X_STEPS)
+    c.interleaved = True
     c.k = n - rank(c.hx) - rank(c.hz)
     c.lz = logical_z_basis(c.hx, c.hz, c.k)
     return c

@@ -167,6 +167,7 @@ tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg, const ui
   if (cfg->osd_order < 0 || cfg->osd_order > 64) return fail(TMCS_EINVAL, "osd_order must be in [0, 64]");
   if (cfg->decode_chunk < 0 || cfg->decode_chunk % 64 != 0)
     return fail(TMCS_EINVAL, "decode_chunk must be 0 or a positive multiple of 64");
+  if (cfg->bp_sched < 0 || cfg->bp_sched > 2) return fail(TMCS_EINVAL, "bp_sched must be 0, 1 or 2");
   TMCS_TRY({
     return decode_run(d->d, *cfg, det_dev, n_shots, pred_obs_dev, stats_dev, (hipStream_t)stream);
   })

@@ -212,7 +212,7 @@ tmcs_status build_circuit(const tmcs_circuit_spec& s, Circuit* c) {
   const CodeBlock& code = c->code;
   c->spec = s;
   const int nblocks = s.op == TMCS_MEMORY ? 1 : s.op == TMCS_NONLOCAL_CNOT ? 2 : s.op == TMCS_TELEPORT ? 3 : s.weight + 1;
-  if ((int64_t)code.k * nblocks > 64) return fail(TMCS_EUNSUPPORTED, "more than 64 logical observables");
+  if ((int64_t)code.k * nblocks > MAX_OBS) return fail(TMCS_EUNSUPPORTED, "more than 256 logical observables");
   const int size = code.n + code.nx + code.nz;
   std::vector<Block> blocks(nblocks);
   for (int b = 0; b < nblocks; ++b) {

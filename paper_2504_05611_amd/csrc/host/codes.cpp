@@ -12,9 +12,12 @@
 // y = I_l (x) S_m with S the cyclic shift S[r][(r+1) mod j] = 1, so the
 // monomial x^a y^b maps index (i, j) = (r / m, r % m) to ((i+a) mod l, (j+b) mod m).
 // A = a(x,y), B = b(x,y), H_X = [A|B], H_Z = [B^T|A^T].  Every monomial is a
-// permutation, so every term is one collision-free CX layer: six Z-check layers
-// (B^T terms on left data, A^T terms on right data), then six X-check layers (A
-// terms on left data, B terms on right data).
+// permutation, so every term is one collision-free CX layer.  The round uses
+// the interleaved depth-7 cycle of the bivariate-bicycle memory experiments the
+// paper builds on (Methods, "Simulation"): at each step every X check applies
+// one term (an A term on left data or a B term on right data) and every Z check
+// one term on the other half of the data (a B^T term on left data or an A^T
+// term on right data); X checks idle at the first step, Z checks at the last.
 //
 // Logical Z basis of a BB code: the rows of the reduced row echelon form of
 // ker(H_X), taken in order and kept when independent of rowspace(H_Z) and of
@@ -197,15 +200,19 @@ static tmcs_status bb_code(const tmcs_circuit_spec& s, CodeBlock* c) {
   }
   c->hx = hx;
   c->hz = hz;
-  c->layers = 12;
-  c->xs.assign(12, {});
-  c->zs.assign(12, {});
-  for (int k = 0; k < 3; ++k)
+  // interleaved depth-7 cycle: step t applies X term X_STEPS[t] (0-2: A_k on left
+  // data, 3-5: B_k on right data) and Z term Z_STEPS[t] (0-2: B_k^T on left data,
+  // 3-5: A_k^T on right data) to every check; -1 leaves that check type idle
+  static const int X_STEPS[7] = {-1, 1, 4, 3, 5, 0, 2};
+  static const int Z_STEPS[7] = {3, 5, 0, 1, 2, 4, -1};
+  c->layers = 7;
+  c->xs.assign(7, {});
+  c->zs.assign(7, {});
+  for (int t = 0; t < 7; ++t)
     for (int r = 0; r < h; ++r) {
-      c->zs[k].push_back({r, ib[k][r]});
-      c->zs[3 + k].push_back({r, h + ia[k][r]});
-      c->xs[6 + k].push_back({r, pa[k][r]});
-      c->xs[9 + k].push_back({r, h + pb[k][r]});
+      const int xt = X_STEPS[t], zt = Z_STEPS[t];
+      if (xt >= 0) c->xs[t].push_back({r, xt < 3 ? pa[xt][r] : h + pb[xt - 3][r]});
+      if (zt >= 0) c->zs[t].push_back({r, zt < 3 ? ib[zt][r] : h + ia[zt - 3][r]});
     }
   const int n = c->n;
   std::vector<BitRow> X, Z;

@@ -248,10 +248,11 @@ tmcs_status build_dem(const Circuit& c, Dem* d) {
     }
   if (chans.size() > 65535) return fail(TMCS_EUNSUPPORTED, "too many distinct noise channels");
 
-  struct Col { Set dets; uint64_t om; double p; };
+  struct Col { Set dets; std::vector<uint64_t> om; double p; };
   std::vector<Col> cols;
   int64_t undetectable = 0;
-  if (c.num_obs > 64) return fail(TMCS_EUNSUPPORTED, "more than 64 observables");
+  if (c.num_obs > MAX_OBS) return fail(TMCS_EUNSUPPORTED, "more than 256 observables");
+  const int OW = std::max(1, (c.num_obs + 63) / 64);
   for (size_t i = 0; i < symptoms.size(); ++i) {
     const Set& s = symptoms[i];
     // merge in circuit order: contributions were stored in reverse order
@@ -263,21 +264,25 @@ tmcs_status build_dem(const Circuit& c, Dem* d) {
       else p = p + q - 2.0 * p * q;
     }
     Col col;
-    col.om = 0;
+    col.om.assign(OW, 0ull);
+    bool any_obs = false;
     for (int32_t x : s) {
       if (x < nd) col.dets.push_back(x);
-      else col.om |= 1ull << (x - nd);
+      else { col.om[(x - nd) >> 6] |= 1ull << ((x - nd) & 63); any_obs = true; }
     }
     col.p = p;
     if (col.dets.empty()) {
-      if (col.om) ++undetectable;
+      if (any_obs) ++undetectable;
       continue;
     }
     cols.push_back(std::move(col));
   }
-  std::sort(cols.begin(), cols.end(), [](const Col& a, const Col& b) {
+  // (detector list, observable mask as one integer): masks compare from their top word down
+  std::sort(cols.begin(), cols.end(), [OW](const Col& a, const Col& b) {
     if (a.dets != b.dets) return a.dets < b.dets;
-    return a.om < b.om;
+    for (int w = OW - 1; w >= 0; --w)
+      if (a.om[w] != b.om[w]) return a.om[w] < b.om[w];
+    return false;
   });
   d->rows = nd;
   d->cols = (int)cols.size();
@@ -285,12 +290,13 @@ tmcs_status build_dem(const Circuit& c, Dem* d) {
   d->undetectable = undetectable;
   d->col_ptr.assign(d->cols + 1, 0);
   d->priors.resize(d->cols);
-  d->obs_mask.resize(d->cols);
+  d->obs_words = OW;
+  d->obs_mask.resize((size_t)d->cols * OW);
   std::vector<int32_t> row_cnt(nd, 0);
   for (int j = 0; j < d->cols; ++j) {
     d->col_ptr[j + 1] = d->col_ptr[j] + (int32_t)cols[j].dets.size();
     d->priors[j] = cols[j].p;
-    d->obs_mask[j] = cols[j].om;
+    for (int w = 0; w < OW; ++w) d->obs_mask[(size_t)j * OW + w] = cols[j].om[w];
     for (int32_t r : cols[j].dets) row_cnt[r]++;
     d->max_col_deg = std::max(d->max_col_deg, (int)cols[j].dets.size());
   }

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "internal.h"
 
 namespace tmcs {
@@ -35,6 +37,22 @@ void sample_release(Circuit& c);
 tmcs_status decode_run(const Dem& d, const tmcs_decoder_cfg& cfg, const uint64_t* det,
                        uint64_t n_shots, uint64_t* pred_obs, tmcs_decode_stats* stats,
                        hipStream_t stream, void* state = nullptr);
+// Several decode items run as one batch (plans): staging per item, one BP launch
+// per kernel variant and team size, one windowed-OSD launch.  Item buffers and
+// states stay fixed, so the batch can be captured in a graph.
+struct MultiItemSpec {
+  const Dem* D;
+  tmcs_decoder_cfg cfg;
+  void* state;                 // decode_state_new
+  const uint64_t* det;         // [rows][batch / 64]
+  uint64_t* pred;              // [observables][batch / 64]
+  tmcs_decode_stats* stats;    // device, may be null
+};
+struct MultiDecode;
+tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& items, uint64_t batch, hipStream_t stream,
+                                MultiDecode** out);
+tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream);
+void decode_multi_free(MultiDecode* m);
 void* decode_state_new(const Dem& d, tmcs_status* st);
 void decode_state_free(void* state);
 tmcs_status ler_run(const uint64_t* pred, const uint64_t* obs, uint32_t k, uint64_t n_shots,

@@ -24,6 +24,7 @@ namespace tmcs {
 
 tmcs_status dem_distance(const Dem& D, int max_active, int max_weight, int64_t max_states, int32_t* weight) {
   *weight = 0;
+  if (D.obs_words != 1) return fail(TMCS_EUNSUPPORTED, "the distance search takes at most 64 observables");
   struct State { std::vector<int32_t> dets; uint64_t obs; };
   auto key_of = [](const State& s) {
     std::string k((const char*)s.dets.data(), s.dets.size() * sizeof(int32_t));

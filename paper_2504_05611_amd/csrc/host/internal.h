@@ -59,6 +59,8 @@ std::string circuit_text(const Circuit& c);
 void circuit_counts(const Circuit& c, int64_t info[TMCS_INFO_LEN]);
 
 // ------------------------------------------------------------------- DEM
+constexpr int MAX_OBS = 256;                  // logical observables a circuit may have
+
 struct Dem {
   int rows = 0, cols = 0, nobs = 0;
   int64_t edges = 0;
@@ -68,7 +70,8 @@ struct Dem {
   std::vector<int32_t> row_ptr, col_idx;      // CSR, cols ascending
   std::vector<int32_t> csc_edge;              // CSC position -> CSR edge id
   std::vector<double> priors;
-  std::vector<uint64_t> obs_mask;
+  int obs_words = 1;                          // ceil(nobs / 64), at least 1
+  std::vector<uint64_t> obs_mask;             // [cols][obs_words]: bit o of word o/64 = flips observable o
   int max_row_deg = 0, max_col_deg = 0;
   void* device = nullptr;                     // decoder-side device copy (decode.hip)
 };

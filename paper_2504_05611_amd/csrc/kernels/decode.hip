@@ -55,7 +55,7 @@ struct DecodeDevice {
   int32_t E4 = 0;
   int32_t max_row_deg = 0;
   // per-lane BP schedules, one per team size used so far
-  struct Sched { int P = 0; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr; };
+  struct Sched { int P = 0; int mode = 1; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr; };
   std::vector<Sched> scheds;
   // scratch
   int32_t* counters = nullptr;     // [0] queue len, [1] bp next, [2] osd len, [3] osd next
@@ -87,7 +87,8 @@ struct BPArgs {
   const int4* init;          // [m] check state of iteration 1 (n1, n2 bits, argmin edge, sign parity)
   const uint32_t* sign0;     // [E4 / 4] sign bytes of q at iteration 1
   const float* lam;
-  const uint64_t* obs_mask;
+  const uint64_t* obs_mask;  // [ow][n]
+  int32_t ow;
   int32_t m, n;
   int64_t E;
   int32_t E32;               // E as int32
@@ -234,32 +235,100 @@ __global__ void __launch_bounds__(256) k_compact(const uint64_t* __restrict__ sy
 // GSTATE: the per-shot state lives in this team's slab of device memory
 // (a.gstate + blockIdx.x * a.team_bytes) instead of LDS, for DEMs whose state
 // does not fit; the code is otherwise the same.
-template <bool WEIGHTED, bool GSTATE>
-__global__ void __launch_bounds__(1024) k_bp(BPArgs a) {
+//
+// MULTI: one launch decodes the queued shots of several decode items (a plan's
+// instances, each with its own DEM, schedules, state and outputs): job g of a
+// counter shared by the launch belongs to the item i with pref[i] <= g <
+// pref[i + 1] (pref: prefix sums of the items' queue lengths), and the team
+// switches to that item's arguments mu.tab[i].  Items are taken in order, so a
+// team switches at most once per item; its statistics go to the item they
+// belong to.  Weights are then per item (weights may be null: scalar alpha).
+struct BPMulti {
+  const BPArgs* tab;
+  int32_t n;
+  int32_t* next;
+};
+constexpr int MAX_MULTI = 16;
+
+template <bool WEIGHTED, bool GSTATE, bool MULTI = false>
+__global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
   extern __shared__ __align__(16) unsigned char sm[];
-  unsigned char* base = GSTATE ? a.gstate + (size_t)blockIdx.x * a.team_bytes : sm;
-  float4* state = (float4*)base;                      // [m + 1] (slot m: padding records)
-  float* L = (float*)(state + a.m + 1);               // [n]
-  uint8_t* sgn = (uint8_t*)(L + a.n);                 // [E4 + 4] (byte E4: padding records)
-  __shared__ int s_job, s_flag, s_pos;
+  unsigned char* base = nullptr;
+  float4* state = nullptr;                            // [m + 1] (slot m: padding records)
+  float* L = nullptr;                                 // [n]
+  uint8_t* sgn = nullptr;                             // [E4 + 4] (byte E4: padding records)
+  auto bind = [&]() {
+    base = GSTATE ? a.gstate + (size_t)blockIdx.x * a.team_bytes : sm;
+    state = (float4*)base;
+    L = (float*)(state + a.m + 1);
+    sgn = (uint8_t*)(L + a.n);
+  };
+  __shared__ int s_job, s_flag, s_pos, s_inst;
   __shared__ int s_unsat[2];
-  __shared__ unsigned long long s_pm;
+  __shared__ int s_pref[MAX_MULTI + 1];
+  __shared__ unsigned long long s_pm[MAX_OW];
   __shared__ unsigned long long s_hist[TMCS_BP_HIST_BINS];   // written by thread 0 only
   const int tid = threadIdx.x, P = blockDim.x;
-  const int32_t total = a.queue ? a.counters[0] : (int32_t)a.nshots;
+  int32_t total = 0;
+  int cur = -1;                                       // MULTI: item the team works on
+  if constexpr (!MULTI) {
+    bind();
+    total = a.queue ? a.counters[0] : (int32_t)a.nshots;
+  } else if (tid == 0) {
+    s_pref[0] = 0;
+    for (int i = 0; i < mu.n; ++i)
+      s_pref[i + 1] = s_pref[i] + (mu.tab[i].queue ? mu.tab[i].counters[0] : (int32_t)mu.tab[i].nshots);
+  }
   unsigned long long c_nontriv = 0, c_conv = 0, c_osd = 0, c_iters = 0;   // thread 0
   for (int i = tid; i < TMCS_BP_HIST_BINS; i += P) s_hist[i] = 0ull;
+  // statistics of the current item to its stats block, then reset
+  auto flush = [&]() {
+    __syncthreads();
+    if (a.stats)
+      for (int i = tid; i < TMCS_BP_HIST_BINS; i += P)
+        if (s_hist[i]) atomicAdd((unsigned long long*)&a.stats->bp_iter_hist[i], s_hist[i]);
+    if (tid == 0 && a.stats) {
+      if (c_nontriv) atomicAdd((unsigned long long*)&a.stats->nontrivial, c_nontriv);
+      if (c_conv) atomicAdd((unsigned long long*)&a.stats->converged, c_conv);
+      if (c_osd) atomicAdd((unsigned long long*)&a.stats->osd, c_osd);
+      if (c_iters) atomicAdd((unsigned long long*)&a.stats->bp_iters, c_iters);
+    }
+    c_nontriv = c_conv = c_osd = c_iters = 0;
+    __syncthreads();
+    for (int i = tid; i < TMCS_BP_HIST_BINS; i += P) s_hist[i] = 0ull;
+    __syncthreads();
+  };
   while (true) {
     if (tid == 0) {
-      s_job = atomicAdd(&a.counters[1], 1);
+      if constexpr (MULTI) {
+        const int g = atomicAdd(mu.next, 1);
+        int i = 0;
+        while (i < mu.n && g >= s_pref[i + 1]) ++i;
+        s_inst = i;
+        s_job = i < mu.n ? g - s_pref[i] : 0;
+      } else {
+        s_job = atomicAdd(&a.counters[1], 1);
+      }
       s_flag = 0;
       s_unsat[0] = 0;
       s_unsat[1] = 0;
-      s_pm = 0ull;
+      for (int w = 0; w < MAX_OW; ++w) s_pm[w] = 0ull;
     }
     __syncthreads();
+    if constexpr (MULTI) {
+      const int inst = s_inst;
+      if (inst != cur) {                              // uniform: the team moves to the next item
+        if (cur >= 0) flush();
+        if (inst >= mu.n) break;
+        cur = inst;
+        a = mu.tab[inst];
+        bind();
+      }
+    }
     const int job = s_job;
-    if (job >= total) break;
+    if (!MULTI && job >= total) break;
+    // per-item weights in a multi launch (null: scalar alpha)
+    const bool use_w = WEIGHTED && (!MULTI || a.w != nullptr);
     const int64_t ls = a.queue ? a.queue[job] : job;
     const int64_t shot = a.shot0 + ls;
     // state of iteration 1, L = lambda, initial signs
@@ -287,13 +356,13 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a) {
       for (int t = 1;; ++t) {
         // variable pass: L^t from the state of iteration t
         {
-          const float* wt = WEIGHTED ? a.w + (int64_t)(t - 1) * a.E : nullptr;
+          const float* wt = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;
           float acc = 0.0f;
           auto vstep = [&](const int4 r) {
             const int v = r.x & R_IDX, e = r.y, c = r.z;
             const float4 s = state[c];
             const int se = sgn[e];
-            const float at = WEIGHTED ? wt[e < a.E32 ? e : 0] : a.alpha;
+            const float at = use_w ? wt[e < a.E32 ? e : 0] : a.alpha;
             const float mag = __fmul_rn(at, e == __float_as_int(s.z) ? s.y : s.x);
             const int fl = __float_as_int(s.w);
             const float base = (r.x & R_FIRST) ? __int_as_float(r.w) : acc;   // lambda_v on a column's first edge
@@ -316,7 +385,7 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a) {
         const bool update = t < a.T;
         int unsat = (f0 >> 1) & 1;
         {
-          const float* wo = WEIGHTED ? a.w + (int64_t)(t - 1) * a.E : nullptr;   // weights of the messages m^t
+          const float* wo = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;   // weights of the messages m^t
           float n1o = 0.0f, n2o = 0.0f, n1 = BP_BIG, n2 = BP_BIG;
           int nago = -1, nag = -1, sc = 0, spo = 0, npar = 0, hard = 0;
           auto cstep = [&](const int4 r) {
@@ -337,7 +406,7 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a) {
             npar = first ? 0 : npar;
             hard = (first ? 0 : hard) ^ (Lv < 0.0f ? 1 : 0);
             if (update) {
-              const float ao = WEIGHTED ? wo[e < a.E32 ? e : 0] : a.alpha;
+              const float ao = use_w ? wo[e < a.E32 ? e : 0] : a.alpha;
               const float mag = __fmul_rn(ao, e == nago ? n2o : n1o);
               const float q = __fsub_rn(Lv, (sc ^ spo ^ se) ? -mag : mag);   // q = L_v - m_old
               const float aq = fabsf(q);
@@ -375,18 +444,21 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a) {
     if (tid == 0) s_pos = (!conv && a.use_osd) ? atomicAdd(&a.counters[2], 1) : -1;
     __syncthreads();
     const int pos = s_pos;
-    uint64_t pm = 0ull;
+    uint64_t pm[MAX_OW] = {0ull, 0ull, 0ull, 0ull};
     for (int v = tid; v < a.n; v += P) {
       const float Lv = L[v];
-      if (pos < 0 && Lv < 0.0f) pm ^= a.obs_mask[v];
+      if (pos < 0 && Lv < 0.0f)
+        for (int w = 0; w < a.ow; ++w) pm[w] ^= a.obs_mask[(int64_t)w * a.n + v];
       if (pos >= 0) a.osd_llr[(int64_t)pos * a.n + v] = Lv;
       if (a.llr) a.llr[shot * a.n + v] = Lv;
       if (a.ehat && pos < 0) a.ehat[shot * a.n + v] = Lv < 0.0f ? 1 : 0;
     }
-    if (pm) atomicXor(&s_pm, (unsigned long long)pm);
+    for (int w = 0; w < a.ow; ++w)
+      if (pm[w]) atomicXor(&s_pm[w], (unsigned long long)pm[w]);
     __syncthreads();
     if (tid == 0) {
-      if (pos < 0) write_pred(a.pred, a.stride, a.nobs, shot, s_pm);
+      if (pos < 0)
+        for (int w = 0; w < a.ow; ++w) write_pred(a.pred, a.stride, a.nobs, shot, s_pm[w], w);
       else a.osd_queue[pos] = (int32_t)ls;
       if (a.iters) a.iters[shot] = itr;
       if (a.flags) a.flags[shot] = (uint8_t)((conv ? 1 : 0) | (pos >= 0 ? 2 : 0));
@@ -397,16 +469,7 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a) {
       s_hist[itr < TMCS_BP_HIST_BINS - 1 ? itr : TMCS_BP_HIST_BINS - 1] += 1ull;
     }
   }
-  __syncthreads();
-  if (a.stats)
-    for (int i = tid; i < TMCS_BP_HIST_BINS; i += P)
-      if (s_hist[i]) atomicAdd((unsigned long long*)&a.stats->bp_iter_hist[i], s_hist[i]);
-  if (tid == 0 && a.stats) {
-    if (c_nontriv) atomicAdd((unsigned long long*)&a.stats->nontrivial, c_nontriv);
-    if (c_conv) atomicAdd((unsigned long long*)&a.stats->converged, c_conv);
-    if (c_osd) atomicAdd((unsigned long long*)&a.stats->osd, c_osd);
-    if (c_iters) atomicAdd((unsigned long long*)&a.stats->bp_iters, c_iters);
-  }
+  if constexpr (!MULTI) flush();
 }
 
 
@@ -445,11 +508,15 @@ tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
   std::vector<int32_t> csc_row(D.row_idx.begin(), D.row_idx.end());
   std::vector<float> lam(D.cols);
   for (int j = 0; j < D.cols; ++j) lam[j] = (float)std::log((1.0 - D.priors[j]) / D.priors[j]);
+  // observable masks word-major on the device ([ow][n]), so lanes of a wave read consecutive columns
+  std::vector<uint64_t> obs_wm((size_t)D.obs_words * D.cols);
+  for (int j = 0; j < D.cols; ++j)
+    for (int w = 0; w < D.obs_words; ++w) obs_wm[(size_t)w * D.cols + j] = D.obs_mask[(size_t)j * D.obs_words + w];
   tmcs_status st;
   if ((st = upload(&d->row_ptr, D.row_ptr)) != TMCS_OK || (st = upload(&d->col_idx, D.col_idx)) != TMCS_OK ||
       (st = upload(&d->col_ptr, D.col_ptr)) != TMCS_OK || (st = upload(&d->csc_row, csc_row)) != TMCS_OK ||
       (st = upload(&d->csc_edge, D.csc_edge)) != TMCS_OK || (st = upload(&d->lam, lam)) != TMCS_OK ||
-      (st = upload(&d->obs_mask, D.obs_mask)) != TMCS_OK) {
+      (st = upload(&d->obs_mask, obs_wm)) != TMCS_OK) {
     free_device(d);
     delete d;
     return st;
@@ -520,16 +587,37 @@ int lpt_assign(const std::vector<int>& size, int P, std::vector<std::vector<int>
   return (int)kmax;
 }
 
-// Schedules of the check and variable passes for team size P (cached per P).
-// Longest-processing-time lists, also for state in device memory: contiguous
-// per-lane ranges put the lanes of a step a fixed stride apart in memory and
-// were 7x slower there (HBM channel conflicts).
-tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, DecodeDevice::Sched* out) {
+// Strided assignment: lane l takes items l, l + P, l + 2P, ...  At a given step
+// the lanes of a wave are on consecutive items, so their state reads are
+// coalesced (whole cache lines of consecutive checks or columns); loads differ
+// between lanes by the degree variation only.  Returns the max load.
+int strided_assign(const std::vector<int>& size, int P, std::vector<std::vector<int>>* lanes) {
+  lanes->assign(P, {});
+  std::vector<long> load(P, 0);
+  int j = 0;
+  for (size_t i = 0; i < size.size(); ++i) {
+    if (size[i] == 0) continue;
+    (*lanes)[j].push_back((int)i);
+    load[j] += size[i];
+    j = (j + 1) % P;
+  }
+  long kmax = 0;
+  for (long x : load) kmax = std::max(kmax, x);
+  return (int)kmax;
+}
+
+// Schedules of the check and variable passes for team size P and assignment
+// (cfg.bp_sched: 1 longest-processing-time lists, 2 strided), cached per both.
+// (Contiguous per-lane ranges were also tried for state in device memory: the
+// lanes of a step then sit a fixed stride apart and hit the same HBM channels,
+// 7x slower.)
+tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevice::Sched* out) {
   for (const auto& q : d->scheds)
-    if (q.P == P) { *out = q; return TMCS_OK; }
+    if (q.P == P && q.mode == mode) { *out = q; return TMCS_OK; }
   DecodeDevice::Sched q;
   q.P = P;
-  auto assign = lpt_assign;
+  q.mode = mode;
+  auto assign = mode == 2 ? strided_assign : lpt_assign;
   std::vector<std::vector<int>> lanes;
   std::vector<int> rdeg(std::max(D.rows, 0)), cdeg(std::max(D.cols, 0));
   for (int c = 0; c < D.rows; ++c) rdeg[c] = D.row_ptr[c + 1] - D.row_ptr[c];
@@ -600,20 +688,38 @@ int device_cus() {
 
 constexpr int64_t DECODE_CHUNK_MIN = 4096;
 
-}  // namespace
+// Everything one decoder pass needs: launch shapes, scratch and the kernel
+// arguments (filled by decode_prepare, used by the stage / BP / OSD launchers).
+struct DecodePass {
+  DecodeDevice* d = nullptr;
+  const Dem* D = nullptr;
+  tmcs_decoder_cfg cfg{};
+  int64_t stride = 0;          // words per row of det / pred
+  int64_t chunk = 0;           // shots per pass
+  bool full = false;           // per-shot outputs requested (no compaction)
+  int mw = 0;
+  bool gstate = false;
+  int P = 0, bp_grid_max = 0;
+  size_t bp_lds = 0, team_bytes = 0;
+  DecodeDevice::Sched sch;
+  bool osd_win = false, osd_pfx = false, osd_bl = false;
+  int npad = 0, pfx_keys = 0, pfx_rank = 0, osd_grid = 0, pfx_grid = 0;
+  size_t osd_lds = 0, pfx_lds = 0;
+};
 
-tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t* det, uint64_t n_shots,
-                       uint64_t* pred, tmcs_decode_stats* stats, hipStream_t stream, void* state) {
-  if (n_shots == 0) return TMCS_OK;
-  if (!det && D.rows) return fail(TMCS_EINVAL, "null detector buffer");
-  if (!pred && D.nobs) return fail(TMCS_EINVAL, "null prediction buffer");
-  if (n_shots > (1ull << 40)) return fail(TMCS_EINVAL, "n_shots too large");
+tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n_shots, void* state,
+                           hipStream_t stream, DecodePass* out) {
+  DecodePass& ps = *out;
   DecodeDevice* d = (DecodeDevice*)state;
   tmcs_status st = TMCS_OK;
   if (!d && (st = ensure_device(D, &d)) != TMCS_OK) return st;
-  const int64_t stride = (int64_t)((n_shots + 63) / 64);
-  const bool full = cfg.ehat_dev || cfg.llr_dev || cfg.iters_dev || cfg.flags_dev;
+  ps.d = d;
+  ps.D = &D;
+  ps.cfg = cfg;
+  ps.stride = (int64_t)((n_shots + 63) / 64);
+  ps.full = cfg.ehat_dev || cfg.llr_dev || cfg.iters_dev || cfg.flags_dev;
   const int mw = (D.rows + 63) / 64;
+  ps.mw = mw;
   int npad = OSD_THREADS;   // sort length: a power of two, at least one key per thread
   while (npad < D.cols) npad <<= 1;
   if (cfg.osd_window < 0 || cfg.osd_window > WIN_MAX_ROWS)
@@ -628,33 +734,42 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (size_t)d->E4 + 4;
   const bool gstate = cfg.bp_global_state != 0 || bp_lds > 160 * 1024;
   const size_t team_bytes = (bp_lds + 255) & ~(size_t)255;
-  // teams per CU: as many as fit in LDS, or 4 teams of 8 waves with the state in device memory
-  const int team_fit = gstate ? 4 : std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));
+  // teams per CU: as many as fit in LDS; with the state in device memory, one
+  // team of 16 waves (fewer slabs in flight: at d = 15..29 that was 1.2-1.7x
+  // faster than 4 teams of 8 waves), unless the caller asks for another shape
+  const int team_fit = gstate ? (cfg.bp_per_cu > 0 ? 32 : 1) : std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));
   int P;
   if (cfg.bp_threads > 0) {
     P = cfg.bp_threads;
   } else {
     // about 24 waves per CU (the passes are latency-bound: more waves, more
     // overlap), but no lane should carry much more than its share of edges
-    int G = gstate ? 8 : std::max(1, std::min(16, (24 + team_fit - 1) / team_fit));
+    int G = gstate ? 16 : std::max(1, std::min(16, (24 + team_fit - 1) / team_fit));
     P = 64 * G;
     const int64_t cap = std::max<int64_t>(64, (2 * D.edges / std::max(d->max_row_deg, 1)) / 64 * 64);
     while (P > 64 && P > cap) P -= 64;
   }
   P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
-  DecodeDevice::Sched sch;
-  if ((st = get_sched(D, d, P, &sch)) != TMCS_OK) return st;
+  const int sched_mode = cfg.bp_sched > 0 ? cfg.bp_sched : 1;
+  if ((st = get_sched(D, d, P, sched_mode, &ps.sch)) != TMCS_OK) return st;
   if (!gstate && bp_lds > 64 * 1024 &&
       (hipFuncSetAttribute((const void*)k_bp<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
-       hipFuncSetAttribute((const void*)k_bp<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess))
+       hipFuncSetAttribute((const void*)k_bp<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
+       hipFuncSetAttribute((const void*)k_bp<true, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess))
     return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
   const int per_cu = std::max(1, std::min({team_fit, 32 / (P / 64), cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 32}));
+  ps.gstate = gstate;
+  ps.P = P;
+  ps.bp_lds = bp_lds;
+  ps.team_bytes = team_bytes;
+  ps.bp_grid_max = cus * per_cu;
   // shots per internal pass: as few passes as the OSD LLR staging allows
   // (<= 8 GiB), each ending on its slowest teams; passes of equal size
   int64_t cmax = std::max<int64_t>(DECODE_CHUNK_MIN, ((1ll << 31) / std::max(D.cols, 1)) & ~63ll);
   if (cfg.decode_chunk > 0) cmax = std::min<int64_t>(cmax, cfg.decode_chunk);
   const int64_t nch = std::max<int64_t>(1, ((int64_t)n_shots + cmax - 1) / cmax);
   const int64_t chunk = std::min<int64_t>((int64_t)n_shots, (((int64_t)n_shots + nch - 1) / nch + 63) & ~63ll);
+  ps.chunk = chunk;
   // OSD launch shape
   const int W = osd_win ? 2 * WIN_MW
                         : 2 * (mw <= 1 ? 1 : mw <= 2 ? 2 : mw <= 4 ? 4 : mw <= 5 ? 5 : mw <= 8 ? 8 : mw <= 12 ? 12
@@ -690,6 +805,9 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
   const int osd_grid = std::max(1, cus * osd_per_cu);
   const int pfx_fit = std::max<int>(1, (int)((160 * 1024) / (pfx_lds + 512)));
   const int pfx_grid = std::max(1, cus * std::min(pfx_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 16));
+  ps.osd_win = osd_win; ps.osd_pfx = osd_pfx; ps.osd_bl = osd_bl;
+  ps.npad = npad; ps.pfx_keys = pfx_keys; ps.pfx_rank = pfx_rank;
+  ps.osd_grid = osd_grid; ps.pfx_grid = pfx_grid; ps.osd_lds = osd_lds; ps.pfx_lds = pfx_lds;
   if ((st = grow(&d->queue, &d->cap_queue, (size_t)chunk)) != TMCS_OK) return st;
   if ((st = grow(&d->synd, &d->cap_synd, (size_t)chunk * (size_t)std::max(mw, 1))) != TMCS_OK) return st;
   if (gstate && (st = grow(&d->gstate, &d->cap_gstate, (size_t)cus * per_cu * team_bytes)) != TMCS_OK) return st;
@@ -713,75 +831,287 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
       }
     }
   }
-  const int64_t total_words = (int64_t)D.nobs * stride;
+  return TMCS_OK;
+}
+
+// BP kernel arguments of the chunk [s0, s0 + ns) of a pass.
+BPArgs bp_args(const DecodePass& ps, const uint64_t* det_unused, uint64_t* pred, tmcs_decode_stats* stats,
+               int64_t s0, int64_t ns) {
+  (void)det_unused;
+  const DecodeDevice* d = ps.d;
+  const Dem& D = *ps.D;
+  const tmcs_decoder_cfg& cfg = ps.cfg;
+  BPArgs a;
+  a.csched = ps.sch.c; a.vsched = ps.sch.v; a.Kc = ps.sch.Kc; a.Kv = ps.sch.Kv; a.init = d->init; a.sign0 = d->sign0;
+  a.lam = d->lam; a.obs_mask = d->obs_mask; a.ow = D.obs_words;
+  a.m = D.rows; a.n = D.cols; a.E = D.edges; a.E32 = (int32_t)D.edges; a.E4 = d->E4; a.T = cfg.max_iter; a.alpha = cfg.alpha;
+  a.w = cfg.weights_dev;
+  a.synd = d->synd; a.mw = std::max(ps.mw, 1); a.stride = ps.stride; a.shot0 = s0; a.nshots = ns;
+  a.queue = ps.full ? nullptr : d->queue;
+  a.counters = d->counters; a.use_osd = cfg.use_osd; a.osd_queue = d->osd_queue; a.osd_llr = d->osd_llr;
+  a.pred = pred; a.nobs = D.nobs; a.stats = stats; a.ehat = cfg.ehat_dev; a.llr = cfg.llr_dev;
+  a.iters = cfg.iters_dev; a.flags = cfg.flags_dev;
+  a.gstate = d->gstate; a.team_bytes = ps.team_bytes;
+  return a;
+}
+
+// OSD kernel arguments of the chunk starting at s0.
+OSDArgs osd_args(const DecodePass& ps, uint64_t* pred, tmcs_decode_stats* stats, int64_t s0) {
+  const DecodeDevice* d = ps.d;
+  const Dem& D = *ps.D;
+  const tmcs_decoder_cfg& cfg = ps.cfg;
+  OSDArgs o;
+  o.col_ptr = d->col_ptr; o.csc_row = d->csc_row; o.obs_mask = d->obs_mask; o.ow = D.obs_words;
+  o.m = D.rows; o.n = D.cols; o.rank = D.rank; o.synd = d->synd; o.mw = std::max(ps.mw, 1); o.stride = ps.stride;
+  o.shot0 = s0;
+  o.counters = d->counters; o.osd_queue = d->osd_queue; o.osd_llr = d->osd_llr; o.basis = d->basis;
+  o.pred = pred; o.nobs = D.nobs; o.stats = stats; o.ehat = cfg.ehat_dev; o.flags = cfg.flags_dev;
+  o.npad = ps.npad;
+  o.rowmap = d->rowmap; o.win_rows = cfg.osd_window > 0 ? cfg.osd_window : WIN_MAX_ROWS;
+  o.jobs = nullptr; o.cnt_total = 2; o.cnt_next = 3; o.retry = nullptr; o.order = cfg.osd_order;
+  return o;
+}
+
+// Zero the predictions of a pass (all chunks).
+void decode_zero_pred(const DecodePass& ps, uint64_t* pred, hipStream_t stream) {
+  const int64_t total_words = (int64_t)ps.D->nobs * ps.stride;
   if (total_words) {
     const int64_t g = std::min<int64_t>((total_words + 255) / 256, 4096);
     TMCS_LAUNCH("k_zero_words", k_zero_words, dim3((unsigned)g), dim3(256), 0, stream, pred, total_words);
   }
-  for (int64_t s0 = 0; s0 < (int64_t)n_shots; s0 += chunk) {
-    const int64_t ns = std::min<int64_t>(chunk, (int64_t)n_shots - s0);
-    TMCS_LAUNCH("k_zero_i32", k_zero_i32, dim3(1), dim3(64), 0, stream, d->counters, 8);
-    if (stats) TMCS_LAUNCH("k_add_shots", k_add_shots, dim3(1), dim3(1), 0, stream, stats, (unsigned long long)ns);
-    {
-      const int64_t nw = (ns + 63) / 64;
-      const int mt = std::max(mw, 1);
-      const int64_t gx = (nw + N_XCD - 1) / N_XCD * N_XCD;
-      TMCS_LAUNCH("k_synd_transpose", k_synd_transpose, dim3((unsigned)gx, (unsigned)((mt + SYND_TILES - 1) / SYND_TILES)),
-                  dim3(64), 0, stream, det,
-                  D.rows, stride, s0, ns, mt, d->synd);
+}
+
+// Syndrome staging of the chunk [s0, s0 + ns): counters reset, shot-major
+// transpose, compaction of the non-trivial shots.
+void decode_stage(const DecodePass& ps, const uint64_t* det, tmcs_decode_stats* stats, int64_t s0, int64_t ns,
+                  hipStream_t stream) {
+  DecodeDevice* d = ps.d;
+  const Dem& D = *ps.D;
+  TMCS_LAUNCH("k_zero_i32", k_zero_i32, dim3(1), dim3(64), 0, stream, d->counters, 8);
+  if (stats) TMCS_LAUNCH("k_add_shots", k_add_shots, dim3(1), dim3(1), 0, stream, stats, (unsigned long long)ns);
+  const int mw = ps.mw;
+  {
+    const int64_t nw = (ns + 63) / 64;
+    const int mt = std::max(mw, 1);
+    const int64_t gx = (nw + N_XCD - 1) / N_XCD * N_XCD;
+    TMCS_LAUNCH("k_synd_transpose", k_synd_transpose, dim3((unsigned)gx, (unsigned)((mt + SYND_TILES - 1) / SYND_TILES)),
+                dim3(64), 0, stream, det, D.rows, ps.stride, s0, ns, mt, d->synd);
+  }
+  if (!ps.full) {
+    const int64_t g = std::min<int64_t>((ns + 256 * COMPACT_SLABS - 1) / (256 * COMPACT_SLABS), 1024);
+    TMCS_LAUNCH("k_compact", k_compact, dim3((unsigned)g), dim3(256), 0, stream, d->synd, std::max(mw, 1), ns,
+                d->queue, d->counters);
+    if (stats) TMCS_LAUNCH("k_add_trivial", k_add_trivial, dim3(1), dim3(1), 0, stream, stats, d->counters,
+                           (unsigned long long)ns);
+  }
+}
+
+tmcs_status decode_bp_launch(const DecodePass& ps, const BPArgs& a, int64_t ns, hipStream_t stream) {
+  const int bp_grid = (int)std::min<int64_t>((int64_t)ps.bp_grid_max, std::max<int64_t>(ns, 1));
+  const BPMulti none{nullptr, 0, nullptr};
+  if (ps.gstate) {
+    if (ps.cfg.weights_dev) TMCS_LAUNCH("k_bp_dev", (k_bp<true, true>), dim3(bp_grid), dim3(ps.P), 0, stream, a, none);
+    else TMCS_LAUNCH("k_bp_dev", (k_bp<false, true>), dim3(bp_grid), dim3(ps.P), 0, stream, a, none);
+  } else {
+    if (ps.cfg.weights_dev) TMCS_LAUNCH("k_bp", (k_bp<true, false>), dim3(bp_grid), dim3(ps.P), ps.bp_lds, stream, a, none);
+    else TMCS_LAUNCH("k_bp", (k_bp<false, false>), dim3(bp_grid), dim3(ps.P), ps.bp_lds, stream, a, none);
+  }
+  return hip_check(hipGetLastError(), "k_bp launch");
+}
+
+tmcs_status decode_osd_launch(const DecodePass& ps, uint64_t* pred, tmcs_decode_stats* stats, int64_t s0,
+                              hipStream_t stream) {
+  if (!ps.cfg.use_osd) return TMCS_OK;
+  const OSDArgs o = osd_args(ps, pred, stats, s0);
+  if (ps.osd_win) return launch_osd_win(o, ps.osd_grid, ps.osd_lds, stream);
+  if (ps.osd_pfx) {
+    OSDArgs op = o;
+    op.npad = ps.pfx_keys;
+    op.rank = ps.pfx_rank;
+    op.retry = ps.d->retry;
+    tmcs_status st = dispatch_osd_pfx(ps.mw, ps.osd_bl, op, ps.pfx_grid, ps.pfx_lds, stream);
+    if (st != TMCS_OK) return st;
+    OSDArgs orr = o;
+    orr.jobs = ps.d->retry; orr.cnt_total = 4; orr.cnt_next = 5;
+    return dispatch_osd(ps.mw, ps.npad / (ps.osd_bl ? 64 : OSD_THREADS), ps.osd_bl, orr, ps.osd_grid, ps.osd_lds,
+                        stream);
+  }
+  return dispatch_osd(ps.mw, ps.npad / (ps.osd_bl ? 64 : OSD_THREADS), ps.osd_bl, o, ps.osd_grid, ps.osd_lds, stream);
+}
+
+}  // namespace
+
+tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t* det, uint64_t n_shots,
+                       uint64_t* pred, tmcs_decode_stats* stats, hipStream_t stream, void* state) {
+  if (n_shots == 0) return TMCS_OK;
+  if (!det && D.rows) return fail(TMCS_EINVAL, "null detector buffer");
+  if (!pred && D.nobs) return fail(TMCS_EINVAL, "null prediction buffer");
+  if (n_shots > (1ull << 40)) return fail(TMCS_EINVAL, "n_shots too large");
+  DecodePass ps;
+  tmcs_status st = decode_prepare(D, cfg, n_shots, state, stream, &ps);
+  if (st != TMCS_OK) return st;
+  decode_zero_pred(ps, pred, stream);
+  for (int64_t s0 = 0; s0 < (int64_t)n_shots; s0 += ps.chunk) {
+    const int64_t ns = std::min<int64_t>(ps.chunk, (int64_t)n_shots - s0);
+    decode_stage(ps, det, stats, s0, ns, stream);
+    if ((st = decode_bp_launch(ps, bp_args(ps, det, pred, stats, s0, ns), ns, stream)) != TMCS_OK) return st;
+    if ((st = decode_osd_launch(ps, pred, stats, s0, stream)) != TMCS_OK) return st;
+  }
+  return TMCS_OK;
+}
+
+// ---------------------------------------------------------------- multi-item
+// A plan's decode items run as one batch: staging per item, then one BP launch
+// per group of items that share the kernel variant (state in LDS or in device
+// memory) and team size, and one windowed-OSD launch for the items that use
+// the windowed OSD-0 with the same grid; any other OSD runs per item.
+struct MultiDecode {
+  struct Item {
+    DecodePass ps;
+    const uint64_t* det = nullptr;
+    uint64_t* pred = nullptr;
+    tmcs_decode_stats* stats = nullptr;
+  };
+  struct BPGroup {
+    bool gstate = false, weighted = false;
+    int P = 0, grid = 0;
+    size_t lds = 0;
+    std::vector<int> items;
+    BPArgs* tab = nullptr;   // device [items]
+    BPArgs first{};          // host copy of the first item's arguments
+  };
+  std::vector<Item> items;
+  uint64_t batch = 0;
+  std::vector<BPGroup> bp;
+  std::vector<int> osd_win_items, osd_other_items;
+  OSDArgs* osd_tab = nullptr;
+  OSDArgs osd_first{};       // host copy of the first windowed item's arguments
+  int osd_grid = 0;
+  size_t osd_lds = 0;
+  int32_t* next = nullptr;   // device [2]: BP and OSD job counters of the multi launches
+};
+
+void decode_multi_free(MultiDecode* m) {
+  if (!m) return;
+  for (auto& g : m->bp) hipFree(g.tab);
+  hipFree(m->osd_tab);
+  hipFree(m->next);
+  delete m;
+}
+
+tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_t batch, hipStream_t stream,
+                                MultiDecode** out) {
+  *out = nullptr;
+  if (specs.empty() || specs.size() > (size_t)MAX_MULTI) return fail(TMCS_EINVAL, "multi decode: 1..16 items");
+  MultiDecode* m = new MultiDecode();
+  m->batch = batch;
+  tmcs_status st = TMCS_OK;
+  for (const auto& sp : specs) {
+    MultiDecode::Item it;
+    it.det = sp.det; it.pred = sp.pred; it.stats = sp.stats;
+    if (sp.cfg.ehat_dev || sp.cfg.llr_dev || sp.cfg.iters_dev || sp.cfg.flags_dev) st = fail(TMCS_EINVAL, "multi decode: no per-shot outputs");
+    if (st == TMCS_OK) st = decode_prepare(*sp.D, sp.cfg, batch, sp.state, stream, &it.ps);
+    if (st == TMCS_OK && it.ps.chunk < (int64_t)batch) st = fail(TMCS_EUNSUPPORTED, "multi decode: batch exceeds one decoder pass");
+    if (st != TMCS_OK) { decode_multi_free(m); return st; }
+    m->items.push_back(it);
+  }
+  // BP groups: (state placement, team size)
+  for (int i = 0; i < (int)m->items.size(); ++i) {
+    const DecodePass& ps = m->items[i].ps;
+    MultiDecode::BPGroup* g = nullptr;
+    for (auto& q : m->bp)
+      if (q.gstate == ps.gstate && q.P == ps.P) g = &q;
+    if (!g) {
+      m->bp.push_back(MultiDecode::BPGroup());
+      g = &m->bp.back();
+      g->gstate = ps.gstate;
+      g->P = ps.P;
+      g->grid = ps.bp_grid_max;
     }
-    if (!full) {
-      const int64_t g = std::min<int64_t>((ns + 256 * COMPACT_SLABS - 1) / (256 * COMPACT_SLABS), 1024);
-      TMCS_LAUNCH("k_compact", k_compact, dim3((unsigned)g), dim3(256), 0, stream, d->synd, std::max(mw, 1), ns,
-                  d->queue, d->counters);
-      if (stats) TMCS_LAUNCH("k_add_trivial", k_add_trivial, dim3(1), dim3(1), 0, stream, stats, d->counters,
-                             (unsigned long long)ns);
+    g->items.push_back(i);
+    g->weighted = g->weighted || ps.cfg.weights_dev != nullptr;
+    g->grid = std::min(g->grid, ps.bp_grid_max);
+    if (!ps.gstate) g->lds = std::max(g->lds, ps.bp_lds);
+  }
+  const int cus = device_cus();
+  for (auto& g : m->bp) {
+    if (!g.gstate) {
+      // teams resident per CU with the largest state of the group
+      const int fit = std::max(1, std::min((int)((160 * 1024) / (g.lds + 1024)), 32 / (g.P / 64)));
+      g.grid = std::min(g.grid, cus * fit);
+      if (g.lds > 64 * 1024 &&
+          (hipFuncSetAttribute((const void*)k_bp<false, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds) != hipSuccess ||
+           hipFuncSetAttribute((const void*)k_bp<true, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds) != hipSuccess)) {
+        decode_multi_free(m);
+        return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
+      }
     }
-    BPArgs a;
-    a.csched = sch.c; a.vsched = sch.v; a.Kc = sch.Kc; a.Kv = sch.Kv; a.init = d->init; a.sign0 = d->sign0;
-    a.lam = d->lam; a.obs_mask = d->obs_mask;
-    a.m = D.rows; a.n = D.cols; a.E = D.edges; a.E32 = (int32_t)D.edges; a.E4 = d->E4; a.T = cfg.max_iter; a.alpha = cfg.alpha;
-    a.w = cfg.weights_dev;
-    a.synd = d->synd; a.mw = std::max(mw, 1); a.stride = stride; a.shot0 = s0; a.nshots = ns; a.queue = full ? nullptr : d->queue;
-    a.counters = d->counters; a.use_osd = cfg.use_osd; a.osd_queue = d->osd_queue; a.osd_llr = d->osd_llr;
-    a.pred = pred; a.nobs = D.nobs; a.stats = stats; a.ehat = cfg.ehat_dev; a.llr = cfg.llr_dev;
-    a.iters = cfg.iters_dev; a.flags = cfg.flags_dev;
-    const int bp_grid = (int)std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(ns, 1));
-    a.gstate = d->gstate; a.team_bytes = team_bytes;
-    if (gstate) {
-      if (cfg.weights_dev) TMCS_LAUNCH("k_bp", (k_bp<true, true>), dim3(bp_grid), dim3(P), 0, stream, a);
-      else TMCS_LAUNCH("k_bp", (k_bp<false, true>), dim3(bp_grid), dim3(P), 0, stream, a);
+    std::vector<BPArgs> tab;
+    for (int i : g.items) {
+      const auto& it = m->items[i];
+      tab.push_back(bp_args(it.ps, it.det, it.pred, it.stats, 0, (int64_t)batch));
+    }
+    g.first = tab[0];
+    if ((st = upload(&g.tab, tab)) != TMCS_OK) { decode_multi_free(m); return st; }
+  }
+  // windowed OSD: one launch for the items sharing its grid and LDS
+  for (int i = 0; i < (int)m->items.size(); ++i) {
+    const DecodePass& ps = m->items[i].ps;
+    if (!ps.cfg.use_osd) continue;
+    const bool join = ps.osd_win && (m->osd_win_items.empty() || (ps.osd_grid == m->osd_grid && ps.osd_lds == m->osd_lds));
+    if (join) {
+      m->osd_win_items.push_back(i);
+      m->osd_grid = ps.osd_grid;
+      m->osd_lds = ps.osd_lds;
     } else {
-      if (cfg.weights_dev) TMCS_LAUNCH("k_bp", (k_bp<true, false>), dim3(bp_grid), dim3(P), bp_lds, stream, a);
-      else TMCS_LAUNCH("k_bp", (k_bp<false, false>), dim3(bp_grid), dim3(P), bp_lds, stream, a);
+      m->osd_other_items.push_back(i);
+    }
+  }
+  if (!m->osd_win_items.empty()) {
+    std::vector<OSDArgs> tab;
+    for (int i : m->osd_win_items) tab.push_back(osd_args(m->items[i].ps, m->items[i].pred, m->items[i].stats, 0));
+    m->osd_first = tab[0];
+    if ((st = upload(&m->osd_tab, tab)) != TMCS_OK) { decode_multi_free(m); return st; }
+  }
+  if (hipMalloc((void**)&m->next, 2 * sizeof(int32_t)) != hipSuccess) {
+    decode_multi_free(m);
+    return fail(TMCS_ENOMEM, "hipMalloc failed (multi decode counters)");
+  }
+  *out = m;
+  return TMCS_OK;
+}
+
+// One batch of every item: staging, the grouped BP launches, the OSD launches.
+tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream) {
+  const int64_t ns = (int64_t)m->batch;
+  for (auto& it : m->items) {
+    decode_zero_pred(it.ps, it.pred, stream);
+    decode_stage(it.ps, it.det, it.stats, 0, ns, stream);
+  }
+  TMCS_LAUNCH("k_zero_i32", k_zero_i32, dim3(1), dim3(64), 0, stream, m->next, 2);
+  tmcs_status st;
+  for (auto& g : m->bp) {
+    // (the BP job counter is shared by the groups in turn: zeroed before each)
+    if (&g != &m->bp.front()) TMCS_LAUNCH("k_zero_i32", k_zero_i32, dim3(1), dim3(64), 0, stream, m->next, 1);
+    const BPMulti mu{g.tab, (int32_t)g.items.size(), m->next};
+    const int grid = std::max(1, g.grid);
+    const BPArgs& a0 = g.first;
+    if (g.gstate) {
+      if (g.weighted) TMCS_LAUNCH("k_bp_dev", (k_bp<true, true, true>), dim3(grid), dim3(g.P), 0, stream, a0, mu);
+      else TMCS_LAUNCH("k_bp_dev", (k_bp<false, true, true>), dim3(grid), dim3(g.P), 0, stream, a0, mu);
+    } else {
+      if (g.weighted) TMCS_LAUNCH("k_bp", (k_bp<true, false, true>), dim3(grid), dim3(g.P), g.lds, stream, a0, mu);
+      else TMCS_LAUNCH("k_bp", (k_bp<false, false, true>), dim3(grid), dim3(g.P), g.lds, stream, a0, mu);
     }
     if ((st = hip_check(hipGetLastError(), "k_bp launch")) != TMCS_OK) return st;
-    if (cfg.use_osd) {
-      OSDArgs o;
-      o.col_ptr = d->col_ptr; o.csc_row = d->csc_row; o.obs_mask = d->obs_mask;
-      o.m = D.rows; o.n = D.cols; o.rank = D.rank; o.synd = d->synd; o.mw = std::max(mw, 1); o.stride = stride;
-      o.shot0 = s0;
-      o.counters = d->counters; o.osd_queue = d->osd_queue; o.osd_llr = d->osd_llr; o.basis = d->basis;
-      o.pred = pred; o.nobs = D.nobs; o.stats = stats; o.ehat = cfg.ehat_dev; o.flags = cfg.flags_dev;
-      o.npad = npad;
-      o.rowmap = d->rowmap; o.win_rows = cfg.osd_window > 0 ? cfg.osd_window : WIN_MAX_ROWS;
-      o.jobs = nullptr; o.cnt_total = 2; o.cnt_next = 3; o.retry = nullptr; o.order = cfg.osd_order;
-      if (osd_win) {
-        st = launch_osd_win(o, osd_grid, osd_lds, stream);
-      } else if (osd_pfx) {
-        OSDArgs op = o;
-        op.npad = pfx_keys;
-        op.rank = pfx_rank;
-        op.retry = d->retry;
-        if ((st = dispatch_osd_pfx(mw, osd_bl, op, pfx_grid, pfx_lds, stream)) != TMCS_OK) return st;
-        OSDArgs orr = o;
-        orr.jobs = d->retry; orr.cnt_total = 4; orr.cnt_next = 5;
-        st = dispatch_osd(mw, npad / (osd_bl ? 64 : OSD_THREADS), osd_bl, orr, osd_grid, osd_lds, stream);
-      } else {
-        st = dispatch_osd(mw, npad / (osd_bl ? 64 : OSD_THREADS), osd_bl, o, osd_grid, osd_lds, stream);
-      }
-      if (st != TMCS_OK) return st;
-    }
+  }
+  if (!m->osd_win_items.empty()) {
+    const OSDMulti mu{m->osd_tab, (int32_t)m->osd_win_items.size(), m->next + 1};
+    if ((st = launch_osd_win_multi(m->osd_first, mu, m->osd_grid, m->osd_lds, stream)) != TMCS_OK) return st;
+  }
+  for (int i : m->osd_other_items) {
+    auto& it = m->items[i];
+    if ((st = decode_osd_launch(it.ps, it.pred, it.stats, 0, stream)) != TMCS_OK) return st;
   }
   return TMCS_OK;
 }

@@ -24,10 +24,17 @@ constexpr int PFX_KEYS_WAVE = 128;
 constexpr int PFX_KEYS_WG = 1024;
 constexpr int32_t WIN_NONE = 0x7FFFFFFF;   // windowed OSD rowmap: row not touched by the window
 
-__device__ __forceinline__ void write_pred(uint64_t* pred, int64_t stride, int nobs, int64_t shot, uint64_t mask) {
-  for (int o = 0; o < nobs; ++o)
+// Observable masks: ow = ceil(nobs / 64) words per column, stored word-major
+// ([ow][n]: word w of column v at w * n + v); at most MAX_OW words.
+constexpr int MAX_OW = 4;
+
+// Set the predicted flips of observables 64 word .. 64 word + 63 of one shot.
+__device__ __forceinline__ void write_pred(uint64_t* pred, int64_t stride, int nobs, int64_t shot, uint64_t mask,
+                                           int word) {
+  for (int o = 0; o < 64 && 64 * word + o < nobs; ++o)
     if ((mask >> o) & 1ull)
-      atomicOr((unsigned long long*)&pred[(int64_t)o * stride + (shot >> 6)], (unsigned long long)(1ull << (shot & 63)));
+      atomicOr((unsigned long long*)&pred[(int64_t)(64 * word + o) * stride + (shot >> 6)],
+               (unsigned long long)(1ull << (shot & 63)));
 }
 
 __device__ __forceinline__ uint64_t block_xor_u64(uint64_t v, uint64_t* scratch) {
@@ -44,7 +51,8 @@ __device__ __forceinline__ uint64_t block_xor_u64(uint64_t v, uint64_t* scratch)
 struct OSDArgs {
   const int32_t* col_ptr;
   const int32_t* csc_row;
-  const uint64_t* obs_mask;
+  const uint64_t* obs_mask;  // [ow][n]
+  int32_t ow;
   int32_t m, n, rank;
   const uint64_t* synd;      // [chunk shots][mw] shot-major syndrome words
   int32_t mw;
@@ -68,7 +76,17 @@ struct OSDArgs {
   int32_t order;             // > 0: OSD-CS of this order (dense variants only)
 };
 
+// Several decode items' windowed OSD queues served by one launch (osd.hip).
+constexpr int MAX_MULTI_OSD = 16;
+struct OSDMulti {
+  const OSDArgs* tab;        // device [n]: the items' arguments
+  int32_t n;
+  int32_t* next;             // device job counter shared by the launch (zeroed before it)
+};
+
 // OSD launchers (osd.hip).  grid workgroups, lds bytes of dynamic LDS.
+// first: the first item's arguments (host copy; they fix the shared LDS layout).
+tmcs_status launch_osd_win_multi(const OSDArgs& first, const OSDMulti& mu, int grid, size_t lds, hipStream_t s);
 // Windowed OSD-0 (DEMs beyond the dense limits).
 tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s);
 // Dense OSD-0 on the npad - 1 smallest keys first (jobs the prefix does not settle go to a.retry).

@@ -146,11 +146,19 @@ __device__ __forceinline__ uint64_t bit_of(const uint64_t (&v)[W], int p) {
 // the order with H's own rows.  If s is spanned there, the result is the full
 // OSD-0's; otherwise the job goes to a retry list, which the full-sort variant
 // then decodes, so every shot gets the exact OSD-0 correction.
-template <int MW, int RW, int KPT, bool BL, int NT, bool WIN = false, bool PFX = false>
-__global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
+//
+// MULTI (windowed variant only): one launch serves the OSD queues of several
+// decode items; job g of a counter shared by the launch belongs to item i with
+// pref[i] <= g < pref[i + 1] (prefix sums of the items' queue lengths), and the
+// workgroup switches to that item's arguments, basis and row table.  Every
+// item's window has the same shape (npad = WIN_KEYS, 64 MW local rows), so the
+// LDS layout does not change.
+template <int MW, int RW, int KPT, bool BL, int NT, bool WIN = false, bool PFX = false, bool MULTI = false>
+__global__ void __launch_bounds__(NT) k_osd(OSDArgs a, OSDMulti mu) {
   constexpr int W = MW + RW;
   static_assert(!(WIN && BL), "the window variant keeps its basis in HBM");
   static_assert(!(WIN && PFX), "one front end per variant");
+  static_assert(!MULTI || WIN, "multi-item launches use the windowed variant");
   extern __shared__ __align__(8) unsigned char sm[];
   // local capacity: rank and rows of the problem the elimination sees
   const int cap_r = WIN ? 64 * MW : a.rank;
@@ -168,7 +176,8 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
   // WIN: after the sort, keys holds npad u32 column indices followed by npad
   // per-position counts (then exclusive offsets) of newly touched rows
   int32_t* pcnt = (int32_t*)keys + a.npad;
-  __shared__ int s_job, s_r, s_ns, s_inc;
+  __shared__ int s_job, s_r, s_ns, s_inc, s_inst;
+  __shared__ int s_pref[MAX_MULTI_OSD + 1];
   __shared__ uint64_t s_red;
   __shared__ unsigned long long s_best;     // OSD-CS: (order key of the soft weight, candidate rank)
   __shared__ int s_tpos[64], s_nt, s_f1, s_f2;
@@ -177,6 +186,13 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
   uint64_t* B = BL ? lbasis : a.basis + (int64_t)blockIdx.x * cap_r * W;
   int32_t* fpos = WIN ? a.rowmap + (int64_t)blockIdx.x * 2 * a.m : nullptr;   // [m] first window position
   int32_t* lmap = WIN ? fpos + a.m : nullptr;                                  // [m] local row index
+  int cur = -1;                                                                // MULTI: current item
+  if constexpr (MULTI) {
+    if (tid == 0) {
+      s_pref[0] = 0;
+      for (int i = 0; i < mu.n; ++i) s_pref[i + 1] = s_pref[i] + mu.tab[i].counters[mu.tab[i].cnt_total];
+    }
+  }
   // acc = s + sum of the basis vectors pivoted on rows of s.  With a fully
   // reduced basis this is zero on every pivot row; its syndrome part is zero iff
   // s lies in the span of the kept columns, and its combination part then names
@@ -202,11 +218,34 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
     return __syncthreads_or(nz);
   };
   while (true) {
-    if (tid == 0) s_job = atomicAdd(&a.counters[a.cnt_next], 1);
+    if (tid == 0) {
+      if constexpr (MULTI) {
+        const int g = atomicAdd(mu.next, 1);
+        int i = 0;
+        while (i < mu.n && g >= s_pref[i + 1]) ++i;
+        s_inst = i;
+        s_job = i < mu.n ? g - s_pref[i] : 0;
+      } else {
+        s_job = atomicAdd(&a.counters[a.cnt_next], 1);
+      }
+    }
     __syncthreads();
     const int jn = s_job;
-    __syncthreads();
-    if (jn >= a.counters[a.cnt_total]) break;
+    if constexpr (MULTI) {
+      const int inst = s_inst;
+      __syncthreads();
+      if (inst >= mu.n) break;
+      if (inst != cur) {                     // uniform: the workgroup moves to the next item
+        cur = inst;
+        a = mu.tab[inst];
+        B = a.basis + (int64_t)blockIdx.x * cap_r * W;
+        fpos = a.rowmap + (int64_t)blockIdx.x * 2 * a.m;
+        lmap = fpos + a.m;
+      }
+    } else {
+      __syncthreads();
+      if (jn >= a.counters[a.cnt_total]) break;
+    }
     const int job = a.jobs ? a.jobs[jn] : jn;
     const int64_t ls = a.osd_queue[job];
     const int64_t shot = a.shot0 + ls;
@@ -615,12 +654,15 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
         __syncthreads();
       }
     }
-    uint64_t pm = 0;
+    uint64_t pm[MAX_OW] = {0ull, 0ull, 0ull, 0ull};
+    auto flip = [&](int col) {
+      for (int w = 0; w < a.ow; ++w) pm[w] ^= a.obs_mask[(int64_t)w * a.n + col];
+    };
     if (incomplete) {
       // BP's hard decision stands
       for (int v = tid; v < a.n; v += NT) {
         const bool e = L[v] < 0.0f;
-        if (e) pm ^= a.obs_mask[v];
+        if (e) flip(v);
         if (a.ehat) a.ehat[shot * a.n + v] = e ? 1 : 0;
       }
     } else {
@@ -630,7 +672,7 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
       for (int i = tid; i < r; i += NT) {
         if ((acc[MW + (i >> 6)] >> (i & 63)) & 1ull) {
           const int col = kept[i];
-          pm ^= a.obs_mask[col];
+          flip(col);
           if (a.ehat) a.ehat[shot * a.n + col] = 1;
         }
       }
@@ -640,14 +682,14 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a) {
           for (int q = 0; q < 2; ++q) {
             const int cc = q ? s_f2 : s_f1;
             if (cc < 0) continue;
-            pm ^= a.obs_mask[cc];
+            flip(cc);
             if (a.ehat) a.ehat[shot * a.n + cc] = 1;
           }
       }
     }
-    pm = block_xor_u64(pm, &s_red);
+    for (int w = 0; w < a.ow; ++w) pm[w] = block_xor_u64(pm[w], &s_red);
     if (tid == 0) {
-      write_pred(a.pred, a.stride, a.nobs, shot, pm);
+      for (int w = 0; w < a.ow; ++w) write_pred(a.pred, a.stride, a.nobs, shot, pm[w], w);
       if (a.flags) a.flags[shot] = (uint8_t)(2 | (not_in_span ? 4 : 0) | (incomplete ? 8 : 0));
       if (a.stats && not_in_span) atomicAdd((unsigned long long*)&a.stats->not_in_span, 1ull);
       if (a.stats && incomplete) atomicAdd((unsigned long long*)&a.stats->osd_incomplete, 1ull);
@@ -673,7 +715,7 @@ tmcs_status launch_osd(const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
   if (lds > 64 * 1024 && hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "OSD workspace does not fit in LDS");
   // the full-sort pass over jobs a prefix left open is timed on its own
-  TMCS_LAUNCH(a.jobs ? "k_osd_retry" : "k_osd", k, dim3(grid), dim3(NT), lds, s, a);
+  TMCS_LAUNCH(a.jobs ? "k_osd_retry" : "k_osd", k, dim3(grid), dim3(NT), lds, s, a, OSDMulti{nullptr, 0, nullptr});
   return hip_check(hipGetLastError(), "k_osd launch");
 }
 
@@ -740,7 +782,18 @@ tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s
   auto k = k_osd<WIN_MW, WIN_MW, WIN_KEYS / OSD_THREADS, false, OSD_THREADS, true>;
   if (lds > 64 * 1024 && hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "OSD workspace does not fit in LDS");
-  TMCS_LAUNCH("k_osd", k, dim3(grid), dim3(OSD_THREADS), lds, s, a);
+  TMCS_LAUNCH("k_osd", k, dim3(grid), dim3(OSD_THREADS), lds, s, a, OSDMulti{nullptr, 0, nullptr});
+  return hip_check(hipGetLastError(), "k_osd launch");
+}
+
+tmcs_status launch_osd_win_multi(const OSDArgs& first, const OSDMulti& mu, int grid, size_t lds, hipStream_t s) {
+  if (mu.n < 1 || mu.n > MAX_MULTI_OSD) return fail(TMCS_EINVAL, "multi-item OSD: 1..16 items");
+  if (first.npad != WIN_KEYS) return fail(TMCS_EINVAL, "multi-item OSD: windowed items only");
+  auto k = k_osd<WIN_MW, WIN_MW, WIN_KEYS / OSD_THREADS, false, OSD_THREADS, true, false, true>;
+  if (lds > 64 * 1024 && hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return fail(TMCS_EUNSUPPORTED, "OSD workspace does not fit in LDS");
+  // the first item's arguments set the LDS layout, which every windowed item shares
+  TMCS_LAUNCH("k_osd", k, dim3(grid), dim3(OSD_THREADS), lds, s, first, mu);
   return hip_check(hipGetLastError(), "k_osd launch");
 }
 

@@ -61,11 +61,31 @@ struct Plan {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the items' decoders as one batch (one BP launch per kernel variant, one
+  // windowed-OSD launch), or null when an item needs several decoder passes
+  MultiDecode* multi = nullptr;
 };
 
 static constexpr int DEV_WORDS = 3 + (int)(sizeof(tmcs_decode_stats) / sizeof(uint64_t));
 
 static tmcs_status enqueue_batch(Plan& p, hipStream_t s) {
+  if (p.multi) {
+    // sample every item, decode them together, then count
+    for (Item& it : p.items) {
+      tmcs_status st = sample_run(*it.c, it.seed, it.instance, 0, p.batch, it.det, it.obs, s, it.dev + 0,
+                                  (uint32_t*)(it.dev + 2), it.sstate);
+      if (st != TMCS_OK) return st;
+    }
+    tmcs_status st = decode_multi_enqueue(p.multi, s);
+    if (st != TMCS_OK) return st;
+    for (Item& it : p.items) {
+      st = count_errors_async(it.pred, it.obs, (uint32_t)it.c->num_obs, p.batch, (unsigned long long*)(it.dev + 1), s);
+      if (st != TMCS_OK) return st;
+      TMCS_LAUNCH("k_advance", k_advance, dim3(1), dim3(64), 0, s, it.dev + 0, (uint64_t)(p.batch / 4096));
+      if ((st = hip_check(hipGetLastError(), "k_advance")) != TMCS_OK) return st;
+    }
+    return TMCS_OK;
+  }
   for (Item& it : p.items) {
     tmcs_status st = sample_run(*it.c, it.seed, it.instance, 0, p.batch, it.det, it.obs, s, it.dev + 0,
                                 (uint32_t*)(it.dev + 2), it.sstate);
@@ -82,6 +102,7 @@ static tmcs_status enqueue_batch(Plan& p, hipStream_t s) {
 
 static void destroy(Plan* p) {
   if (!p) return;
+  decode_multi_free(p->multi);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -111,6 +132,12 @@ tmcs_status tmcs_plan_create(const tmcs_plan_item* items, int32_t n_items, uint6
   *out = nullptr;
   Plan* p = new (std::nothrow) Plan();
   if (!p) return fail(TMCS_ENOMEM, "host allocation failed");
+  // no timing events in the warm-up batch or the captured graph
+  struct TimingOff {
+    bool was = timing_on();
+    TimingOff() { if (was) tmcs_timing_enable(0); }
+    ~TimingOff() { if (was) tmcs_timing_enable(1); }
+  } timing_off;
   p->batch = batch_shots;
   p->use_graph = use_graph != 0;
   const int64_t words = (int64_t)(batch_shots / 64);
@@ -147,13 +174,21 @@ tmcs_status tmcs_plan_create(const tmcs_plan_item* items, int32_t n_items, uint6
   }
   if (st == TMCS_OK) st = hip_check(hipStreamCreate(&p->cap_stream), "hipStreamCreate");
   if (st == TMCS_OK) {
+    std::vector<MultiItemSpec> specs;
+    for (Item& it : p->items)
+      specs.push_back(MultiItemSpec{it.d, it.cfg, it.dstate, it.det, it.pred, (tmcs_decode_stats*)(it.dev + 3)});
+    const tmcs_status sm = decode_multi_create(specs, batch_shots, p->cap_stream, &p->multi);
+    if (sm == TMCS_EUNSUPPORTED) p->multi = nullptr;        // items decode one after another
+    else st = sm;
+  }
+  if (st == TMCS_OK) {
     // one eager batch allocates every scratch buffer, then the counters are reset
     for (Item& it : p->items)
-      TMCS_LAUNCH("k_fill_zero", k_fill_zero, dim3(1), dim3(64), 0, p->cap_stream, it.dev, DEV_WORDS);
+      TMCS_LAUNCH("k_fill_zero", k_fill_zero, dim3((DEV_WORDS + 63) / 64), dim3(64), 0, p->cap_stream, it.dev, DEV_WORDS);
     st = enqueue_batch(*p, p->cap_stream);
     if (st == TMCS_OK) st = hip_check(hipStreamSynchronize(p->cap_stream), "plan warm-up");
     for (Item& it : p->items)
-      TMCS_LAUNCH("k_fill_zero", k_fill_zero, dim3(1), dim3(64), 0, p->cap_stream, it.dev, DEV_WORDS);
+      TMCS_LAUNCH("k_fill_zero", k_fill_zero, dim3((DEV_WORDS + 63) / 64), dim3(64), 0, p->cap_stream, it.dev, DEV_WORDS);
     if (st == TMCS_OK) st = hip_check(hipStreamSynchronize(p->cap_stream), "plan reset");
   }
   if (st == TMCS_OK && p->use_graph) {
@@ -184,7 +219,9 @@ tmcs_status tmcs_plan_run(tmcs_plan* h, uint32_t n_batches, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   for (uint32_t b = 0; b < n_batches; ++b) {
     tmcs_status st;
-    if (p.use_graph) st = hip_check(hipGraphLaunch(p.exec, s), "hipGraphLaunch");
+    // with kernel timing on, the batch runs as eager launches of the same
+    // kernels on the same buffers, so that each launch is timed
+    if (p.use_graph && !timing_on()) st = hip_check(hipGraphLaunch(p.exec, s), "hipGraphLaunch");
     else st = enqueue_batch(p, s);
     if (st != TMCS_OK) return st;
     ++p.batches_done;

@@ -48,11 +48,9 @@ class WeightedBP(torch.autograd.Function):
 
 def observable_support(dem) -> torch.Tensor:
     """[k, n] 0/1 matrix of the columns that flip each observable."""
-    h = dem.export()
-    k = max(dem.info["obs"], 1)
-    L = np.zeros((k, dem.cols), dtype=np.float32)
-    for o in range(k):
-        L[o] = ((h.obs_mask >> np.uint64(o)) & np.uint64(1)).astype(np.float32)
+    L = dem.L().astype(np.float32)
+    if L.shape[0] == 0:
+        L = np.zeros((1, dem.cols), dtype=np.float32)
     return torch.from_numpy(L)
 
 
@@ -72,6 +70,30 @@ def observable_loss(llr, obs_bits, supp):
     log_p0 = torch.log(one_plus.clamp_min(1e-30)) - math.log(2.0)
     y = obs_bits[None]
     return -(y * log_p1 + (1.0 - y) * log_p0).sum()
+
+
+def weights_name(spec, T) -> str:
+    """File stem under paper_2504_05611_amd/weights/ of the weights learned for a
+    circuit (code, operation, noise, rounds) and T iterations."""
+    code = "sc%d" % spec.d if spec.code == "sc" else spec.bb
+    return "%s_%s_p%g_pe%g_r%d-%d_T%d" % (code, spec.op, spec.p, spec.p_ebit, spec.rounds_before,
+                                          spec.rounds_after, T)
+
+
+def save_weights(path, weights, train_syndromes, losses, extra=None):
+    """[T, edges] weights, stored in FP16 (the decoder reads them as FP32: callers
+    round with round_fp16 first and use the rounded values), plus what they were
+    trained on (npz, no pickles)."""
+    arrs = dict(weights=weights.detach().half().cpu().numpy(), train_syndromes=np.int64(train_syndromes),
+                losses=np.asarray(losses, dtype=np.float32))
+    for k, v in (extra or {}).items():
+        arrs[k] = np.asarray(v)
+    np.savez_compressed(path, **arrs)
+
+
+def round_fp16(weights):
+    """The weights as stored: rounded to FP16, back in FP32."""
+    return weights.detach().half().float()
 
 
 @dataclass
@@ -149,7 +171,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=0.01)
     ap.add_argument("--last", type=int, default=0, help="loss over the last N iterations only (0: all)")
     ap.add_argument("--eval-shots", type=int, default=1 << 20)
-    ap.add_argument("--out", default="", help="save the trained weights (torch .pt)")
+    ap.add_argument("--out", default="", help="save the trained weights (.npz); 'auto' writes "
+                                             "paper_2504_05611_amd/weights/<circuit>_T<T>.npz")
     ap.add_argument("--log-every", type=int, default=20)
     ap.add_argument("--d", type=int, default=0, help="pick the workload's circuit of this distance")
     ap.add_argument("--p", type=float, default=0.0, help="pick the workload's circuit of this p")
@@ -165,8 +188,18 @@ def main(argv=None):
                 log_every=args.log_every, last=args.last)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    res.weights = round_fp16(res.weights)       # the stored (and evaluated) weights
     if args.out:
-        torch.save(res.weights.cpu(), args.out)
+        import os
+        out_path = args.out
+        if out_path == "auto":
+            wdir = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+            os.makedirs(wdir, exist_ok=True)
+            out_path = os.path.join(wdir, weights_name(spec, T) + ".npz")
+        elif os.path.isdir(out_path):
+            out_path = os.path.join(out_path, weights_name(spec, T) + ".npz")
+        save_weights(out_path, res.weights, args.steps * args.batch, res.losses,
+                     dict(lr=args.lr, batch=args.batch, steps=args.steps, loss_iterations=args.last or T))
     out = dict(workload=w.name, d=spec.d, p=spec.p, T=T, edges=dem.edges, train_steps=args.steps, batch=args.batch, lr=args.lr,
                loss_iterations=args.last or T,
                train_syndromes=args.steps * args.batch, train_s=t_train,

@@ -53,7 +53,7 @@ class DecoderCfg(ctypes.Structure):
                 ("bp_threads", ctypes.c_int32), ("bp_per_cu", ctypes.c_int32),
                 ("osd_per_cu", ctypes.c_int32), ("bp_global_state", ctypes.c_int32),
                 ("osd_order", ctypes.c_int32), ("osd_window", ctypes.c_int32),
-                ("decode_chunk", ctypes.c_int32),
+                ("decode_chunk", ctypes.c_int32), ("bp_sched", ctypes.c_int32),
                 ("ehat_dev", ctypes.c_void_p),
                 ("llr_dev", ctypes.c_void_p), ("iters_dev", ctypes.c_void_p),
                 ("flags_dev", ctypes.c_void_p)]
@@ -260,14 +260,30 @@ class DEM:
         _check(_lib.tmcs_dem_distance(self._h, max_active, max_weight, max_states, ctypes.byref(w)))
         return w.value
 
+    @property
+    def obs_words(self):
+        return max(1, (self.info["obs"] + 63) // 64)
+
     def export(self) -> DemHost:
+        """Host copy; obs_mask is uint64 [cols] with at most 64 observables, else [cols, words]."""
         n, e = self.info["cols"], self.info["edges"]
+        ow = self.obs_words
         cp = np.zeros(n + 1, dtype=np.int32)
         ri = np.zeros(max(e, 1), dtype=np.int32)
         pr = np.zeros(max(n, 1), dtype=np.float64)
-        om = np.zeros(max(n, 1), dtype=np.uint64)
+        om = np.zeros((max(n, 1), ow), dtype=np.uint64)
         _check(_lib.tmcs_dem_export(self._h, cp.ctypes.data, ri.ctypes.data, pr.ctypes.data, om.ctypes.data))
-        return DemHost(cp, ri[:e], pr[:n], om[:n])
+        return DemHost(cp, ri[:e], pr[:n], om[:n, 0] if ow == 1 else om[:n])
+
+    def L(self) -> np.ndarray:
+        """[observables, cols] 0/1 matrix of the columns that flip each observable."""
+        om = self.export().obs_mask
+        om = om[:, None] if om.ndim == 1 else om
+        k = self.info["obs"]
+        L = np.zeros((k, self.cols), dtype=np.uint8)
+        for o in range(k):
+            L[o] = ((om[:, o // 64] >> np.uint64(o % 64)) & np.uint64(1)).astype(np.uint8)
+        return L
 
     def H(self) -> np.ndarray:
         h = self.export()
@@ -278,9 +294,10 @@ class DEM:
 
     def decode(self, det, n_shots, pred, *, max_iter=30, alpha=1.0, weights=None, use_osd=True,
                bp_threads=0, bp_per_cu=0, osd_per_cu=0, bp_global_state=0, osd_order=0, osd_window=0,
-               decode_chunk=0, ehat=None, llr=None, iters=None, flags=None, stats=None, stream=None):
+               decode_chunk=0, bp_sched=0, ehat=None, llr=None, iters=None, flags=None, stats=None,
+               stream=None):
         cfg = DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads,
-                         bp_per_cu, osd_per_cu, bp_global_state, osd_order, osd_window, decode_chunk,
+                         bp_per_cu, osd_per_cu, bp_global_state, osd_order, osd_window, decode_chunk, bp_sched,
                          _ptr(ehat), _ptr(llr), _ptr(iters), _ptr(flags))
         _check(_lib.tmcs_decode(self._h, ctypes.byref(cfg), _ptr(det), n_shots, _ptr(pred), _ptr(stats),
                                 _stream(stream)))
@@ -307,9 +324,10 @@ def wbp_global_state(on=True):
 
 
 def make_cfg(max_iter=30, alpha=1.0, weights=None, use_osd=True, bp_threads=0, bp_per_cu=0,
-             osd_per_cu=0, bp_global_state=0, osd_order=0, osd_window=0, decode_chunk=0):
+             osd_per_cu=0, bp_global_state=0, osd_order=0, osd_window=0, decode_chunk=0, bp_sched=0):
     return DecoderCfg(max_iter, alpha, _ptr(weights), 1 if use_osd else 0, bp_threads, bp_per_cu,
-                      osd_per_cu, bp_global_state, osd_order, osd_window, decode_chunk, None, None, None, None)
+                      osd_per_cu, bp_global_state, osd_order, osd_window, decode_chunk, bp_sched,
+                      None, None, None, None)
 
 
 def autotune(dem, det, n_shots, cfg=None, stream=None) -> DecoderCfg:

@@ -61,16 +61,19 @@ def test_bb144_memory_three_instances_in_one_plan(gpu_lib):
         assert r["shots"] == n and r["errors"] == ne
         assert r["osd"] == s["osd"] and r["converged"] == s["converged"] and r["bp_iters"] == s["bp_iters"]
         preds.append((det.cpu().numpy().view(np.uint64), pred.cpu().numpy().view(np.uint64)))
-    # bits of instance 2 on a stretch that crosses a noise block, and one decoded word of instance 1
+    # bits of instance 2 on a stretch that crosses a noise block, and two decoded
+    # 64-shot words of every instance (one in each replay's shot range)
     _check_sampler(gpu_lib, circuits[2], w.specs[2], w.seed, 2, 4096 - 64, 128)
-    oc1 = build_circuit(w.specs[1])
-    od = build_dem(oc1)
-    dec = Decoder(od.H(), od.priors(), od.L(), max_iter=w.bp_iters, dtype=np.float32)
-    _, p1 = preds[1]
-    wd = 37
-    synd, _ = oracle_sample(oc1, w.seed, 1, wd * 64, 64)
-    o = dec.decode(synd.T)
-    assert (unpack_bits(p1[:, wd:wd + 1], 64).T[:, : od.num_obs] == o["pred_obs"]).all()
+    for i in range(3):
+        oc = build_circuit(w.specs[i])
+        od = build_dem(oc)
+        dec = Decoder(od.H(), od.priors(), od.L(), max_iter=w.bp_iters, dtype=np.float32)
+        _, p = preds[i]
+        for wd in (37 + 11 * i, B // 64 + 5 + 7 * i):
+            print(f"[bb144-memory] oracle p={w.specs[i].p} word {wd}", flush=True)
+            synd, _ = oracle_sample(oc, w.seed, i, wd * 64, 64)
+            o = dec.decode(synd.T)
+            assert (unpack_bits(p[:, wd:wd + 1], 64).T[:, : od.num_obs] == o["pred_obs"]).all(), (i, wd)
 
 
 def test_bb144_teleport_decoder_and_weighted_bp(gpu_lib):
@@ -94,8 +97,9 @@ def test_bb144_teleport_decoder_and_weighted_bp(gpu_lib):
     synd, _ = oracle_sample(oc, w.seed, 0, wd * 64, 64)
     o = dec.decode(synd.T)
     assert (unpack_bits(p[:, wd:wd + 1], 64).T[:, : od.num_obs] == o["pred_obs"]).all()
-    # weighted BP at this shape: FP32 forward bit for bit, gradient against the FP64-arithmetic reference
-    T, shots = 4, 2
+    # weighted BP at this shape and the workload's T = 20: FP32 forward bit for bit,
+    # gradient per weight against the FP64-arithmetic reference
+    T, shots = w.bp_iters, 2
     rng = np.random.default_rng(3)
     wts = rng.uniform(0.6, 1.4, size=(T, dem.edges)).astype(np.float32)
     wt = torch.from_numpy(wts).cuda()
@@ -113,7 +117,8 @@ def test_bb144_teleport_decoder_and_weighted_bp(gpu_lib):
     assert (llr.cpu().numpy() == f32["L"]).all()
     ref = oracle_backward(f32, G.astype(np.float64))
     got = gw.cpu().numpy().astype(np.float64)
-    assert np.linalg.norm(got - ref) <= 1e-4 * max(np.linalg.norm(ref), 1e-30)
+    from test_gpu_wbp import abs_backward, assert_gradient_elementwise
+    assert_gradient_elementwise(got, ref, abs_backward(f32, G), "bb144-teleport T=20")
 
 
 def test_sc11_nlcnot_bp_lds_and_device_state(gpu_lib):

@@ -27,6 +27,8 @@ CASES = [
     # OSD basis widths of the prefix pass not covered above: 156 detectors (3 words) and 336 (6 words)
     ("sc5-teleport", sc(5, TELEPORT, 3, 3, 3e-3, 1e-2), 1024 + 9, 30),
     ("sc7-nlcnot", sc(7, NLCNOT, 3, 3, 2e-3, 1e-2), 512 + 3, 30),
+    # 68 observables (17 blocks of [[18,4,4]]): predictions span two observable words
+    ("bb18-pstring16", pstring(bb("bb18", p=4e-3), 16, rounds=1), 512 + 3, 30),
 ]
 
 
@@ -96,19 +98,86 @@ def test_decoder_parity(gpu_lib, name, spec, shots, T):
     st = r["stats"]
     assert st["shots"] == shots and st["osd"] == int(osd.sum())
     assert st["converged"] == int(conv.sum())
-    # FP64 reference LLRs.  Min-sum is piecewise linear; as iterations accumulate, a
-    # near-tie in an argmin or a sign lets FP32 and FP64 follow different (equally
-    # valid) trajectories, so the FP64 tolerance applies to shots both precisions
-    # decode within 8 iterations: |L32 - L64| <= 1e-4 max(|L64|, 1), and hard
-    # decisions agree wherever |L64| >= 1e-3.
-    dec64 = Decoder(od.H(), od.priors(), od.L(), max_iter=T, dtype=np.float64, use_osd=False)
-    o64 = dec64.decode(synd, chunk=64)
-    early = (o64["iters"] == r["iters"]) & o64["converged"] & conv & (r["iters"] <= 8)
-    a64 = o64["llr"][early]
-    a32 = r["llr"][early].astype(np.float64)
-    assert np.all(np.abs(a32 - a64) <= 1e-4 * np.maximum(np.abs(a64), 1.0))
-    big = np.abs(a64) >= 1e-3
-    assert not ((a32 < 0) != (a64 < 0))[big].any()
+    check_fp64(r, od, synd, T, name)
+
+
+def fp64_along(f32, priors):
+    """FP64 arithmetic along a given FP32 trajectory: every iteration's argmin edges
+    and signs are those FP32 took (oracle.wbp forward with unit weights saves them),
+    the magnitudes and sums are recomputed in FP64.  Returns L [T, S, n]."""
+    from oracle.bp import BIG, prior_llr
+    g = f32["graph"]
+    lam = prior_llr(priors)
+    S = f32["L"].shape[1]
+    q = np.broadcast_to(lam[g.ev], (S, g.E)).astype(np.float64).copy()
+    out = []
+    for sv in f32["saved"]:
+        amin = sv["amin"]
+        ok = amin >= 0
+        mu = np.full((S, g.E), BIG)
+        rows = np.nonzero(ok)
+        mu[rows] = np.abs(q[rows[0], amin[rows]])
+        m = mu * sv["sigma"].astype(np.float64)
+        L = lam[None, :].repeat(S, axis=0)
+        np.add.at(L, (slice(None), g.ev), m)
+        q = L[:, g.ev] - m
+        out.append(L)
+    return np.stack(out)
+
+
+FP64_ITERS = 8
+
+
+def check_fp64(r, od, synd, T, name):
+    """FP64 reference LLRs (R21).  L64 is FP64 arithmetic along the FP32 run's
+    own argmin and sign decisions.  On every non-trivial shot that stops within
+    FP64_ITERS iterations: |L32 - L64| <= 1e-4 max(|L64|, 1) for every column, and
+    hard decisions identical except where |L64| < 1e-3 (those columns are flagged:
+    counted and printed).  Min-sum on a loopy graph amplifies a rounding
+    difference about twofold every one or two iterations (the printed profile
+    measures it: on these DEMs the FP32/FP64 difference along one trajectory
+    reaches 1e-4 between iteration 7 (BB codes) and 14 (surface codes)), so the
+    1e-4 bound is checked on shots that stop within 8 iterations; shots that run
+    longer are listed with their fraction and are compared bit for bit with the
+    FP32 oracle above.  Pure FP64 (its own decisions and stopping point) is
+    reported beside."""
+    from oracle.wbp import forward as wbp_forward
+    nontriv = np.nonzero(r["iters"] > 0)[0]
+    if len(nontriv) == 0:
+        return
+    H, pri = od.H(), od.priors()
+    E = int(H.sum())
+    it = r["iters"][nontriv]
+    Tmax = int(it.max())
+    f32 = wbp_forward(H, pri, synd[nontriv], np.ones((Tmax, E), dtype=np.float32), dtype=np.float32)
+    L64 = fp64_along(f32, pri)
+    idx = np.arange(len(nontriv))
+    # the FP32 forward (no early stop) reproduces the decoder's FP32 LLRs at the stopping iteration
+    assert (f32["L"][it - 1, idx] == r["llr"][nontriv]).all()
+    prof = []
+    for t in range(Tmax):
+        running = it > t
+        e = np.abs(f32["L"][t][running].astype(np.float64) - L64[t][running]) / \
+            np.maximum(np.abs(L64[t][running]), 1.0)
+        prof.append(float(e.max()) if e.size else 0.0)
+    ok = it <= FP64_ITERS
+    ref = L64[it - 1, idx][ok]
+    got = r["llr"][nontriv][ok].astype(np.float64)
+    rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    small = np.abs(ref) < 1e-3
+    flipped = (got < 0) != (ref < 0)
+    longer = nontriv[~ok]
+    o64 = Decoder(H, pri, od.L(), max_iter=T, dtype=np.float64, use_osd=False).decode(synd, chunk=64)
+    other = nontriv[o64["iters"][nontriv] != r["iters"][nontriv]]
+    print(f"[fp64] {name}: {int(ok.sum())} of {len(nontriv)} non-trivial shots checked, max rel err "
+          f"{rel.max() if rel.size else 0.0:.2e}; flagged |L64| < 1e-3 columns {int(small.sum())}, of which "
+          f"{int((small & flipped).sum())} take the other hard decision; {len(longer)} shots "
+          f"({100 * len(longer) / len(nontriv):.1f} %) run more than {FP64_ITERS} iterations: "
+          f"{longer[:12].tolist()}{' ...' if len(longer) > 12 else ''}; max rel err by iteration "
+          f"{' '.join('%.0e' % x for x in prof)}; pure FP64 stops at another iteration on {len(other)} shots",
+          flush=True)
+    assert np.all(rel <= 1e-4), float(rel.max())
+    assert not (flipped & ~small).any()
 
 
 def test_decoder_alpha_and_no_osd(gpu_lib):

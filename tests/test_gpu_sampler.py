@@ -19,6 +19,10 @@ CASES = [
     ("bb18-teleport-decoherence-lines", with_decoherence(bb("bb18", TELEPORT, 2, 2, 4e-3, 1e-2), 0.05, True)),
     ("sc5-pstring5", pstring(sc(5, p=2e-3), 5, rounds=2)),
     ("bb18-pstring4", pstring(bb("bb18", p=3e-3), 4, rounds=1)),
+    # 17 blocks x 4 logicals = 68 observables: two observable words
+    ("bb18-pstring16", pstring(bb("bb18", p=3e-3), 16, rounds=1)),
+    # BB [[144,12,12]], weight 5 (pattern 1010): 72 observables
+    ("bb144-pstring5", pstring(bb("bb144", p=1e-3), 5, rounds=1)),
 ]
 
 

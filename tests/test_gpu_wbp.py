@@ -12,6 +12,46 @@ from workloads import NLCNOT, bb, sc
 pytestmark = pytest.mark.gpu
 
 
+def abs_backward(fwd, G):
+    """Per-weight sum of the magnitudes of every term that enters dLoss/dw: the
+    oracle's reverse recursion (oracle/wbp.py backward) with each factor replaced
+    by its absolute value.  FP32 rounding in the kernel's sums is bounded by a
+    small multiple of eps32 times this scale, also where terms cancel."""
+    from oracle.bp import BIG
+    g = fwd["graph"]
+    W = np.abs(np.asarray(fwd["weights"], dtype=np.float64))
+    T, S, n = G.shape
+    A = np.zeros((T, g.E))
+    gq = np.zeros((S, g.E))
+    for t in range(T - 1, -1, -1):
+        sv = fwd["saved"][t]
+        gL = np.abs(np.asarray(G[t], dtype=np.float64))
+        np.add.at(gL, (slice(None), g.ev), gq)
+        gm = gL[:, g.ev] + gq
+        mu = sv["mu"].astype(np.float64)
+        finite = mu < BIG / 2
+        A[t] = np.sum(np.where(finite, gm * mu, 0.0), axis=0)
+        contrib = np.where(finite, gm * W[t][None, :], 0.0)
+        gq = np.zeros((S, g.E))
+        for s_ in range(S):
+            tgt = sv["amin"][s_]
+            ok = tgt >= 0
+            np.add.at(gq[s_], tgt[ok], contrib[s_, ok])
+    return A
+
+
+def assert_gradient_elementwise(got, ref, scale, label=""):
+    """|g - g_ref| <= 1e-4 max(|g_ref|, 0.1 A) for every weight, A = abs_backward's
+    scale (so the floor is 1e-5 A: the FP32 sums over shots and checks of a
+    weight's terms carry ~K eps32 A error for K summands, K <= a few hundred)."""
+    tol = 1e-4 * np.maximum(np.abs(ref), 0.1 * scale)
+    bad = np.abs(got - ref) > tol
+    worst = float(np.max(np.abs(got - ref) / np.maximum(tol, 1e-300)))
+    print(f"[wbp-grad] {label} worst |g - ref| / tol = {worst:.3g} over {ref.size} weights, "
+          f"{int((np.abs(ref) < 0.1 * scale).sum())} on the scale floor", flush=True)
+    assert not bad.any(), (label, int(bad.sum()), worst)
+
+
 def _setup(gpu_lib, spec, shots, T, seed=4):
     import torch
     c = gpu_lib.Circuit(spec)
@@ -46,9 +86,9 @@ def test_forward_and_gradient(gpu_lib, name, spec):
     assert (llr.cpu().numpy() == f32["L"]).all()                    # FP32 forward, bit for bit
     ref = oracle_backward(f32, G.astype(np.float64))                # FP64 arithmetic, same decisions
     got = gw.cpu().numpy().astype(np.float64)
-    err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
-    assert err < 1e-4, err
-    # and against the all-FP64 reference gradient
+    assert_gradient_elementwise(got, ref, abs_backward(f32, G), name)
+    # against the all-FP64 reference gradient: FP64 can take other argmin and sign
+    # decisions on near-ties (R19), which moves whole terms, so this is a norm check
     f64 = oracle_forward(od.H(), od.priors(), synd, w.astype(np.float64))
     ref64 = oracle_backward(f64, G.astype(np.float64))
     err64 = np.linalg.norm(got - ref64) / max(np.linalg.norm(ref64), 1e-30)
@@ -78,7 +118,10 @@ def test_unit_weights_match_plain_decoder(gpu_lib):
 
 
 def test_training_lowers_the_loss_and_bp_failures(gpu_lib):
-    """Weights trained on sampled syndromes beat plain min-sum (alpha = 1) on fresh shots."""
+    """Weights trained on sampled syndromes beat plain min-sum (alpha = 1) on fresh
+    shots, judged by plain BP-OSD: the learned weights send fewer shots to OSD
+    (by more than 3 binomial sigma) and do not raise the BP-OSD logical error
+    rate by more than 3 sigma."""
     import torch
     from paper_2504_05611_amd import neural_bp
     spec = sc(5, NLCNOT, 3, 3, 5e-3, 2e-2)
@@ -97,6 +140,16 @@ def test_training_lowers_the_loss_and_bp_failures(gpu_lib):
           f"non-converged plain {1 - plain['converged']:.4e} learned {1 - learned['converged']:.4e}", flush=True)
     assert learned["ler"] < plain["ler"]
     assert learned["converged"] > plain["converged"]
+    # the judge: BP-OSD on the same fresh shots
+    po = neural_bp.evaluate(c, dem, n_shots=n, T=T, use_osd=True, seed=99)
+    lo = neural_bp.evaluate(c, dem, n_shots=n, T=T, weights=res.weights, use_osd=True, seed=99)
+    d_osd = po["osd_rate"] - lo["osd_rate"]
+    s_osd = np.sqrt((po["osd_rate"] * (1 - po["osd_rate"]) + lo["osd_rate"] * (1 - lo["osd_rate"])) / n)
+    s_ler = np.sqrt((po["ler"] * (1 - po["ler"]) + lo["ler"] * (1 - lo["ler"])) / n)
+    print(f"[train] BP-OSD LER plain {po['ler']:.4e} learned {lo['ler']:.4e} (sigma {s_ler:.1e}); "
+          f"OSD rate plain {po['osd_rate']:.4f} learned {lo['osd_rate']:.4f} (sigma {s_osd:.1e})", flush=True)
+    assert d_osd > 3 * s_osd
+    assert lo["ler"] <= po["ler"] + 3 * s_ler
 
 
 def test_state_in_device_memory_matches_lds(gpu_lib):

@@ -149,3 +149,35 @@ def test_nondeterministic_outputs_are_rejected(tmp_path):
         assert got[name][0] == 5, (name, got[name])
     assert got["random_observable"][1].startswith("observable 0")
     assert got["bell_half"][1].startswith("detector 0")
+
+
+def test_more_than_64_observables_match_oracle(lib):
+    """A Pauli string of weight 16 on [[18,4,4]] blocks has 17 x 4 = 68 observables:
+    the DEM's masks take two words per column, and columns with equal detector
+    lists are ordered by the mask read as one integer (the oracle's Python int)."""
+    spec = pstring(bb("bb18", p=4e-3), 16, rounds=1)
+    lc = lib.Circuit(spec)
+    oc = build_circuit(spec)
+    assert lc.text() == oc.text()
+    ld = lib.DEM(lc)
+    od = build_dem(oc)
+    assert ld.info["obs"] == od.num_obs == 68
+    h = ld.export()
+    assert h.obs_mask.shape == (od.num_cols, 2)
+    want = np.array([[(om >> (64 * w)) & ((1 << 64) - 1) for w in range(2)] for _, om, _ in od.cols],
+                    dtype=np.uint64)
+    assert (h.obs_mask == want).all()
+    assert (ld.H() == od.H()).all() and (h.priors == od.priors()).all()
+    assert (ld.L() == od.L()).all()
+    with pytest.raises(lib.TmcsError):
+        ld.distance()                                       # the search keeps one mask word
+
+
+@pytest.mark.slow
+def test_bb_schedule_keeps_the_code_distance(lib):
+    """The interleaved BB cycle (R16) keeps the circuit distance of the [[36,4,6]]
+    memory circuit at the code distance 6 (Table IV); the capped search finds a
+    weight-6 logical error and none lighter within its cap.  The earlier
+    Z-checks-then-X-checks order dropped it to 4."""
+    d = lib.DEM(lib.Circuit(bb("bb36", MEMORY, 3, 0)))
+    assert d.distance(max_active=6, max_weight=12, max_states=20_000_000) == 6
