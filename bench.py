@@ -121,7 +121,8 @@ def _stored_oracle_dem(name):
     for j in range(n):
         H[rows[cp[j]:cp[j + 1]], j] = 1
     k = int(g["num_obs"])
-    L = ((g["obs_mask"][None, :] >> np.arange(k, dtype=np.uint64)[:, None]) & np.uint64(1)).astype(np.uint8)
+    om = g["obs_mask"][:, None] if g["obs_mask"].ndim == 1 else g["obs_mask"]
+    L = np.stack([(om[:, o // 64] >> np.uint64(o % 64)) & np.uint64(1) for o in range(k)]).astype(np.uint8)
     return H, g["priors"], L
 
 

@@ -154,6 +154,17 @@ tmcs_status tmcs_dem_export(const tmcs_dem* d, int32_t* col_ptr, int32_t* row_id
 tmcs_status tmcs_dem_distance(const tmcs_dem* d, int32_t max_active, int32_t max_weight,
                               int64_t max_states, int32_t* weight);
 
+/* The same search on the GPU, level by level with one thread per state and the
+ * visited states in a device hash table of 64-bit fingerprints (two distinct
+ * states collide with probability ~N^2 / 2^65 for N states; a collision can
+ * only hide an error, never report a false one).  max_active <= 16.  The state
+ * budget is checked per level (a level that would pass max_states ends the
+ * search with *weight = 0); with a sufficient budget the result equals
+ * tmcs_dem_distance's.  Allocates about 80 * 2 * max_states bytes of states and
+ * 16 * max_states bytes of table for the call; synchronises the stream. */
+tmcs_status tmcs_dem_distance_device(const tmcs_dem* d, int32_t max_active, int32_t max_weight,
+                                     int64_t max_states, int32_t* weight, void* stream);
+
 /* Sample n_shots shots [shot_begin, shot_begin + n_shots) of circuit c.
  * Noise: Philox4x32-10 with key (seed lo, seed hi) and counter (block, site,
  * instance, call) draws the events of each noise site per 4096-shot block; a draw

@@ -117,6 +117,12 @@ tmcs_status tmcs_dem_distance(const tmcs_dem* d, int32_t max_active, int32_t max
   TMCS_TRY({ return dem_distance(d->d, max_active, max_weight, max_states, weight); })
 }
 
+tmcs_status tmcs_dem_distance_device(const tmcs_dem* d, int32_t max_active, int32_t max_weight, int64_t max_states,
+                                     int32_t* weight, void* stream) {
+  if (!d || !weight) return fail(TMCS_EINVAL, "invalid argument");
+  TMCS_TRY({ return dem_distance_device(d->d, max_active, max_weight, max_states, weight, (hipStream_t)stream); })
+}
+
 tmcs_status tmcs_dem_export(const tmcs_dem* d, int32_t* col_ptr, int32_t* row_idx, double* priors,
                             uint64_t* obs_mask) {
   if (!d) return fail(TMCS_EINVAL, "null dem");

@@ -65,6 +65,10 @@ tmcs_status autotune_run(const Dem& d, const uint64_t* det, uint64_t n_shots, tm
                          hipStream_t stream);
 void decode_release(Dem& d);
 
+// circuit-distance search on the GPU (distance.hip)
+tmcs_status dem_distance_device(const Dem& D, int max_active, int max_weight, int64_t max_states, int32_t* weight,
+                                hipStream_t stream);
+
 // weighted BP training kernels (wbp.hip)
 size_t wbp_workspace_bytes(const Dem& d, int T, uint64_t n_shots);
 tmcs_status wbp_forward_run(const Dem& d, const float* w, int T, const uint64_t* det,

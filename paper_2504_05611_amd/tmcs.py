@@ -86,6 +86,7 @@ _SIGS = {
     "tmcs_dem_info": [_vp, ctypes.POINTER(ctypes.c_int64)],
     "tmcs_dem_export": [_vp, _vp, _vp, _vp, _vp],
     "tmcs_dem_distance": [_vp, _i32, _i32, ctypes.c_int64, ctypes.POINTER(_i32)],
+    "tmcs_dem_distance_device": [_vp, _i32, _i32, ctypes.c_int64, ctypes.POINTER(_i32), _vp],
     "tmcs_sample": [_vp, _u64, _u32, _u64, _u64, _vp, _vp, _vp],
     "tmcs_sample_async": [_vp, _u64, _u32, _u64, _u64, _vp, _vp, _vp, _vp],
     "tmcs_sample_noalloc": [_vp, _u64, _u32, _u64, _u64, _vp, _vp, _vp, _vp],
@@ -253,11 +254,16 @@ class DEM:
     def edges(self):
         return self.info["edges"]
 
-    def distance(self, max_active=8, max_weight=16, max_states=20_000_000) -> int:
+    def distance(self, max_active=8, max_weight=16, max_states=20_000_000, device=False, stream=None) -> int:
         """Fewest mechanisms found forming an undetectable logical error (0: none
-        within the limits); exact when max_active >= rows and the budget suffices."""
+        within the limits); exact when max_active >= rows and the budget suffices.
+        device=True runs the level-synchronous search on the GPU (max_active <= 16)."""
         w = ctypes.c_int32()
-        _check(_lib.tmcs_dem_distance(self._h, max_active, max_weight, max_states, ctypes.byref(w)))
+        if device:
+            _check(_lib.tmcs_dem_distance_device(self._h, max_active, max_weight, max_states, ctypes.byref(w),
+                                                 _stream(stream)))
+        else:
+            _check(_lib.tmcs_dem_distance(self._h, max_active, max_weight, max_states, ctypes.byref(w)))
         return w.value
 
     @property

@@ -48,7 +48,12 @@ def write(name):
     for dets, _, _ in od.cols:
         rows.extend(sorted(dets))
         col_ptr.append(len(rows))
-    obs = np.array([om for _, om, _ in od.cols], dtype=np.uint64)
+    # observable masks: one uint64 per column, or [cols][words] beyond 64 observables
+    ow = max(1, (od.num_obs + 63) // 64)
+    obs = np.array([[(om >> (64 * w)) & ((1 << 64) - 1) for w in range(ow)] for _, om, _ in od.cols],
+                   dtype=np.uint64)
+    if ow == 1:
+        obs = obs[:, 0]
     np.savez_compressed(path(name), num_dets=np.int64(od.num_dets), num_obs=np.int64(od.num_obs),
                         col_ptr=np.array(col_ptr, dtype=np.int32), rows=np.array(rows, dtype=np.int32),
                         priors=od.priors(), obs_mask=obs)

@@ -40,6 +40,7 @@ LARGE = [("sc21_nlcnot_r3_p1e-3", 16), ("sc29_nlcnot_r3_p1e-3", 8)]
 
 
 def stored_dem(name):
+    """(H, priors, obs_mask, npz); obs_mask is [cols] uint64, or [cols, words] beyond 64 observables."""
     g = np.load(dem_path(name))
     m, n = int(g["num_dets"]), len(g["priors"])
     H = np.zeros((m, n), dtype=np.uint8)
@@ -47,6 +48,12 @@ def stored_dem(name):
     for j in range(n):
         H[rows[cp[j]:cp[j + 1]], j] = 1
     return H, g["priors"], g["obs_mask"], g
+
+
+def obs_matrix(obs_mask, k):
+    """[k, cols] 0/1 matrix from one- or multi-word observable masks."""
+    om = obs_mask[:, None] if obs_mask.ndim == 1 else obs_mask
+    return np.stack([(om[:, o // 64] >> np.uint64(o % 64)) & np.uint64(1) for o in range(k)]).astype(np.int64)
 
 
 @pytest.mark.parametrize("name", [n for n, _ in LARGE])
@@ -112,7 +119,7 @@ def test_large_bp_and_windowed_osd(gpu_lib, name, shots):
     assert len(osd) >= 2, "no OSD shot to compare"
     cols = column_ints(H)
     rk = gf2_rank(H)
-    Lm = ((obs_mask[None, :] >> np.arange(k, dtype=np.uint64)[:, None]) & np.uint64(1)).astype(np.int64)
+    Lm = obs_matrix(obs_mask, k)
     pred = unpack_bits(full["pred"], shots).T[:, :k]
     incomplete = 0
     for i in osd:
@@ -169,8 +176,42 @@ def test_mixed_batch_plan_equals_eager_and_oracle(gpu_lib):
     shots = 16
     synd = unpack_bits(det.cpu().numpy().view(np.uint64)[:, :1], 64).T[:shots]
     k = circuits[i].num_observables
-    Lm = ((obs_mask[None, :] >> np.arange(k, dtype=np.uint64)[:, None]) & np.uint64(1)).astype(np.uint8)
+    Lm = obs_matrix(obs_mask, k).astype(np.uint8)
     from oracle.osd import Decoder
     o = Decoder(H, priors, Lm, max_iter=w.bp_iters, dtype=np.float32).decode(synd, chunk=16)
     got = unpack_bits(pred.cpu().numpy().view(np.uint64)[:, :1], 64).T[:shots, :k]
     assert (got == o["pred_obs"]).all()
+
+
+def test_bb144_pauli_string_weight5(gpu_lib):
+    """Pauli-string compute of weight 5 (pattern 1010) on BB [[144,12,12]] blocks,
+    one round first: 6 blocks x 12 logicals = 72 observables, so predictions span
+    two mask words.  Library DEM equal to the stored oracle DEM; BP-OSD
+    predictions of 48 shots equal the oracle's FP32 BP-OSD."""
+    import torch
+    from oracle.osd import Decoder
+    name = "bb144_pstring5_r1_p1e-3"
+    spec = SPECS[name]
+    T = 30
+    H, priors, obs_mask, _ = stored_dem(name)
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    k = c.num_observables
+    assert k == 72 and obs_mask.shape == (dem.cols, 2)
+    h = dem.export()
+    assert (dem.H() == H).all() and (h.priors == priors).all() and (h.obs_mask == obs_mask).all()
+    shots = 48
+    print(f"[mixed] {name}: {dem.rows} detectors, {dem.cols} columns, {shots} shots", flush=True)
+    d_or, o_or = oracle_sample(build_circuit(spec), 1, 0, 0, shots)
+    det = torch.from_numpy(pack_bits(d_or).view(np.int64)).cuda()
+    pred = torch.zeros((k, 1), dtype=torch.int64, device="cuda")
+    flags = torch.zeros(shots, dtype=torch.uint8, device="cuda")
+    dem.decode(det, shots, pred, max_iter=T, flags=flags)
+    torch.cuda.synchronize()
+    o = Decoder(H, priors, obs_matrix(obs_mask, k).astype(np.uint8), max_iter=T, dtype=np.float32).decode(
+        d_or.T, chunk=16)
+    got = unpack_bits(pred.cpu().numpy().view(np.uint64), shots).T[:, :k]
+    fl = flags.cpu().numpy()
+    complete = ~((fl & 8).astype(bool))            # windowed OSD: shots spanned inside their window
+    assert complete.sum() >= shots - 2
+    assert (got[complete] == o["pred_obs"][complete]).all()
