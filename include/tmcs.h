@@ -335,9 +335,12 @@ tmcs_status tmcs_wbp_global_state(int32_t on);
 
 /* Launch-shape autotuner: decodes the caller's syndromes (det_dev, n_shots
  * shots, as for tmcs_decode) with each candidate launch shape - BP threads and
- * workgroups per compute unit, OSD workgroups per compute unit - and writes the
- * fastest into cfg's launch fields (the other fields are kept).  Decoder output
- * never depends on these fields.  Synchronises the stream. */
+ * workgroups per compute unit, OSD workgroups per compute unit, BP lane
+ * schedule - and writes the fastest into cfg's launch fields (the other fields
+ * are kept).  Decoder output never depends on these fields.  The choice is
+ * cached per (GPU architecture and CU count, DEM shape, decoder settings) for
+ * the life of the process: a later call with the same key returns it without
+ * decoding.  Synchronises the stream (when it decodes). */
 tmcs_status tmcs_autotune(const tmcs_dem* d, const uint64_t* det_dev, uint64_t n_shots,
                           tmcs_decoder_cfg* cfg, void* stream);
 

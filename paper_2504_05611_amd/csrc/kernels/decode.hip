@@ -31,7 +31,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -116,7 +119,6 @@ struct BPArgs {
   unsigned char* gstate;     // GSTATE: [grid][team_bytes]
   size_t team_bytes;
 };
-
 
 __global__ void k_zero_words(uint64_t* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -215,6 +217,22 @@ __global__ void __launch_bounds__(256) k_compact(const uint64_t* __restrict__ sy
   }
 }
 
+// The same for wide syndromes (many detector words per shot, few shots per
+// call, as in the large surface-code CNOTs): one wave per shot, its lanes
+// reading the shot's words together, one queue slot per kept shot.  The queue
+// order differs from k_compact's; every shot is decoded on its own, so nothing
+// depends on it.
+__global__ void __launch_bounds__(256) k_compact_wide(const uint64_t* __restrict__ synd, int32_t mw, int64_t nshots,
+                                                      int32_t* __restrict__ queue, int32_t* __restrict__ counters) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * 4;
+  for (int64_t sh = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sh < nshots; sh += waves) {
+    uint64_t any = 0ull;
+    for (int k = lane; k < mw; k += 64) any |= synd[sh * mw + k];
+    if (__ballot(any != 0ull) && lane == 0) queue[atomicAdd(&counters[0], 1)] = (int32_t)sh;
+  }
+}
+
 // BP over persistent teams: one workgroup (a "team" of P = blockDim.x lanes)
 // decodes one shot at a time, with the whole per-shot state in LDS.  Work is
 // split over the lanes by static schedules built once per DEM and team size
@@ -243,6 +261,7 @@ __global__ void __launch_bounds__(256) k_compact(const uint64_t* __restrict__ sy
 // switches to that item's arguments mu.tab[i].  Items are taken in order, so a
 // team switches at most once per item; its statistics go to the item they
 // belong to.  Weights are then per item (weights may be null: scalar alpha).
+
 struct BPMulti {
   const BPArgs* tab;
   int32_t n;
@@ -391,15 +410,18 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           auto cstep = [&](const int4 r) {
             const int v = r.x & R_IDX, e = r.y, c = r.z;
             const bool first = (r.x & R_FIRST) != 0;
-            const float4 s = state[c];
+            // only lanes that start a check read its state (the others carry it)
+            if (first) {
+              const float4 s = state[c];
+              const int fl = __float_as_int(s.w);
+              n1o = s.x;
+              n2o = s.y;
+              nago = __float_as_int(s.z);
+              sc = (fl >> 1) & 1;
+              spo = fl & 1;
+            }
             const float Lv = L[v];
             const int se = sgn[e];
-            const int fl = __float_as_int(s.w);
-            n1o = first ? s.x : n1o;
-            n2o = first ? s.y : n2o;
-            nago = first ? __float_as_int(s.z) : nago;
-            sc = first ? (fl >> 1) & 1 : sc;
-            spo = first ? fl & 1 : spo;
             n1 = first ? BP_BIG : n1;
             n2 = first ? BP_BIG : n2;
             nag = first ? -1 : nag;
@@ -898,9 +920,15 @@ void decode_stage(const DecodePass& ps, const uint64_t* det, tmcs_decode_stats* 
                 dim3(64), 0, stream, det, D.rows, ps.stride, s0, ns, mt, d->synd);
   }
   if (!ps.full) {
-    const int64_t g = std::min<int64_t>((ns + 256 * COMPACT_SLABS - 1) / (256 * COMPACT_SLABS), 1024);
-    TMCS_LAUNCH("k_compact", k_compact, dim3((unsigned)g), dim3(256), 0, stream, d->synd, std::max(mw, 1), ns,
-                d->queue, d->counters);
+    if (mw >= 64) {
+      const int64_t g = std::min<int64_t>((ns + 3) / 4, 4096);
+      TMCS_LAUNCH("k_compact", k_compact_wide, dim3((unsigned)g), dim3(256), 0, stream, d->synd, mw, ns, d->queue,
+                  d->counters);
+    } else {
+      const int64_t g = std::min<int64_t>((ns + 256 * COMPACT_SLABS - 1) / (256 * COMPACT_SLABS), 1024);
+      TMCS_LAUNCH("k_compact", k_compact, dim3((unsigned)g), dim3(256), 0, stream, d->synd, std::max(mw, 1), ns,
+                  d->queue, d->counters);
+    }
     if (stats) TMCS_LAUNCH("k_add_trivial", k_add_trivial, dim3(1), dim3(1), 0, stream, stats, d->counters,
                            (unsigned long long)ns);
   }
@@ -1172,9 +1200,44 @@ tmcs_status count_errors_async(const uint64_t* pred, const uint64_t* obs, uint32
 
 // Launch-shape search: decode the caller's syndromes with every candidate shape
 // and keep the fastest.  Results never depend on the launch shape, only time.
+// The autotuner's choices, cached per (GPU, DEM shape, decoder settings):
+// a later call with the same key returns the cached launch fields at once.
+struct TuneKey {
+  std::string arch;
+  int rows, cols, rank, obs;
+  int64_t edges;
+  int max_iter, use_osd, osd_order, osd_window, weighted, global_state;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(arch, rows, cols, rank, obs, edges, max_iter, use_osd, osd_order, osd_window, weighted, global_state) <
+           std::tie(o.arch, o.rows, o.cols, o.rank, o.obs, o.edges, o.max_iter, o.use_osd, o.osd_order, o.osd_window,
+                    o.weighted, o.global_state);
+  }
+};
+struct TuneVal { int bp_threads, bp_per_cu, osd_per_cu, bp_sched; };
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune_cache;
+
 tmcs_status autotune_run(const Dem& D, const uint64_t* det, uint64_t n_shots, tmcs_decoder_cfg* cfg,
                          hipStream_t stream) {
   if (n_shots == 0) return fail(TMCS_EINVAL, "autotune needs shots");
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(TMCS_EDEVICE, "no HIP device");
+  const TuneKey key{std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount), D.rows, D.cols,
+                    D.rank, D.nobs, D.edges, cfg->max_iter, cfg->use_osd, cfg->osd_order, cfg->osd_window,
+                    cfg->weights_dev != nullptr, cfg->bp_global_state};
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      cfg->bp_threads = it->second.bp_threads;
+      cfg->bp_per_cu = it->second.bp_per_cu;
+      cfg->osd_per_cu = it->second.osd_per_cu;
+      cfg->bp_sched = it->second.bp_sched;
+      return TMCS_OK;
+    }
+  }
   uint64_t* pred = nullptr;
   const int64_t stride = (int64_t)((n_shots + 63) / 64);
   if (hipMalloc((void**)&pred, (size_t)std::max(D.nobs, 1) * stride * 8) != hipSuccess)
@@ -1189,12 +1252,14 @@ tmcs_status autotune_run(const Dem& D, const uint64_t* det, uint64_t n_shots, tm
   const int threads[] = {64, 128, 256, 512, 1024};
   const int bp_cu[] = {0, 4};
   const int osd_cu[] = {2, 4, 8};
+  const int sched[] = {1, 2};
   tmcs_status st = TMCS_OK;
   for (int th : threads)
     for (int bc : bp_cu)
-      for (int oc : osd_cu) {
+      for (int oc : osd_cu)
+        for (int sm : sched) {
         tmcs_decoder_cfg c = base;
-        c.bp_threads = th; c.bp_per_cu = bc; c.osd_per_cu = oc;
+        c.bp_threads = th; c.bp_per_cu = bc; c.osd_per_cu = oc; c.bp_sched = sm;
         if ((st = decode_run(D, c, det, n_shots, pred, nullptr, stream)) != TMCS_OK) break;   // warm
         (void)hipEventRecord(e0, stream);
         if ((st = decode_run(D, c, det, n_shots, pred, nullptr, stream)) != TMCS_OK) break;
@@ -1211,6 +1276,9 @@ tmcs_status autotune_run(const Dem& D, const uint64_t* det, uint64_t n_shots, tm
   cfg->bp_threads = best.bp_threads;
   cfg->bp_per_cu = best.bp_per_cu;
   cfg->osd_per_cu = best.osd_per_cu;
+  cfg->bp_sched = best.bp_sched;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune_cache[key] = TuneVal{best.bp_threads, best.bp_per_cu, best.osd_per_cu, best.bp_sched};
   return TMCS_OK;
 }
 

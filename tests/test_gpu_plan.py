@@ -80,10 +80,20 @@ def test_autotune_keeps_results(gpu_lib):
     c.sample(1, 0, 0, n, det, obs)
     cfg = gpu_lib.autotune(dem, det, n, gpu_lib.make_cfg(max_iter=30))
     assert cfg.bp_threads in (64, 128, 256, 512, 1024) and cfg.osd_per_cu in (2, 4, 8)
+    assert cfg.bp_sched in (1, 2)
     p1 = torch.zeros_like(obs)
     p2 = torch.zeros_like(obs)
     dem.decode(det, n, p1, max_iter=30)
     dem.decode(det, n, p2, max_iter=30, bp_threads=cfg.bp_threads, bp_per_cu=cfg.bp_per_cu,
-               osd_per_cu=cfg.osd_per_cu)
+               osd_per_cu=cfg.osd_per_cu, bp_sched=cfg.bp_sched)
     torch.cuda.synchronize()
     assert (p1.cpu().numpy() == p2.cpu().numpy()).all()
+    # the choice is cached per (GPU, DEM shape, settings): a second DEM of the same
+    # circuit gets it back at once, without decoding (no syndromes needed)
+    import time
+    dem2 = gpu_lib.DEM(c)
+    t0 = time.perf_counter()
+    cfg2 = gpu_lib.autotune(dem2, det, n, gpu_lib.make_cfg(max_iter=30))
+    assert time.perf_counter() - t0 < 0.05
+    assert (cfg2.bp_threads, cfg2.bp_per_cu, cfg2.osd_per_cu, cfg2.bp_sched) == \
+        (cfg.bp_threads, cfg.bp_per_cu, cfg.osd_per_cu, cfg.bp_sched)
