@@ -66,7 +66,7 @@ WRITE_SCALE = 1048576.0 / 1048576.0
 
 WEIGHTS_DIR = os.path.join(ROOT, "paper_2504_05611_amd", "weights")
 SAMPLE_KERNELS = ("k_event", "k_scan", "k_frame", "k_zero_u32")
-DECODE_KERNELS = ("k_bp", "k_bp_dev", "k_osd", "k_osd_retry", "k_compact", "k_zero_i32", "k_add_shots",
+DECODE_KERNELS = ("k_bp", "k_bp_dev", "k_bp_lanes", "k_osd", "k_osd_retry", "k_compact", "k_zero_i32", "k_add_shots",
                   "k_add_trivial", "k_synd_transpose", "k_zero_words", "k_fill_i32")
 
 
@@ -188,14 +188,19 @@ def decode_ms_of(kern):
 
 
 def state_bytes(dem):
-    """Per-shot BP state: 16 B per check (+1 pad), 4 B per column, 1 B per edge (x4 rounded)."""
+    """Per-shot BP state of the team kernel: 16 B per check (+1 pad), 4 B per column, 1 B per edge (x4 rounded)."""
     return 16 * (dem.rows + 1) + 4 * dem.cols + ((dem.edges + 3) // 4) * 4
+
+
+def lanes_state_bytes(dem):
+    """Per-shot BP state of the lanes kernel: 16 B per check, 4 B per column, 1 bit per edge."""
+    return 16 * dem.rows + 4 * dem.cols + dem.edges / 8.0
 
 
 def roofline(kern, parts, workload):
     """Roofline of the dominant kernel.  parts: per decoded instance (dem, stats dict, shots);
-    k_bp (state in LDS): VALU lane-ops of the 10-op model; k_bp_dev (state in device memory):
-    HBM bytes of the state read and written once per BP iteration."""
+    k_bp (state in LDS): VALU lane-ops of the 10-op model; k_bp_dev and k_bp_lanes (state in
+    device memory): HBM bytes of the state read and written once per BP iteration."""
     dominant = max(kern.items(), key=lambda kv: kv[1][1])[0]
     launches, ms = kern[dominant]
     sec = ms / 1e3
@@ -206,6 +211,13 @@ def roofline(kern, parts, workload):
         out.update(bound="alu", achieved=ach, peak=VALU_PEAK_TOPS, unit="TOP/s", frac=ach / VALU_PEAK_TOPS,
                    model=f"{BP_OPS_PER_EDGE_ITER} lane-ops per edge per BP iteration, summed over the "
                          f"instances whose BP state is in LDS ({ops:.4g} lane-ops in {launches} launches)")
+    elif dominant == "k_bp_lanes":
+        byts = sum(2 * lanes_state_bytes(d) * st["bp_iters"] for d, st, _, gs in parts if gs)
+        ach = byts / sec / 1e9
+        out.update(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                   model="per shot and BP iteration the state (16 B per check, 4 B per column, 1 bit per edge) "
+                         f"read and written once, summed over the instances whose state is in device memory "
+                         f"({byts:.4g} B in {launches} launches)")
     elif dominant == "k_bp_dev":
         byts = sum(2 * state_bytes(d) * st["bp_iters"] for d, st, _, gs in parts if gs)
         ach = byts / sec / 1e9

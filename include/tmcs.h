@@ -224,8 +224,12 @@ typedef struct {
                                at a time (multiple of 64, <= 1024) */
   int32_t bp_per_cu;        /* resident BP teams per compute unit */
   int32_t osd_per_cu;       /* resident OSD workgroups per compute unit */
-  int32_t bp_global_state;  /* 1: keep each shot's BP state in device memory instead of LDS
-                               (automatic when it exceeds the 160 KB LDS of a compute unit) */
+  int32_t bp_global_state;  /* where a shot's BP state lives.  0: LDS while it fits the 160 KB
+                               of a compute unit, otherwise device memory as for 1.  1: device
+                               memory, one team (workgroup) per shot.  2: device memory, 64
+                               shots per workgroup interleaved by lane (each wave runs one
+                               record list of the Tanner graph for all 64 shots; a lane whose
+                               shot ends takes the next one).  Other values: TMCS_EINVAL */
   int32_t osd_order;        /* 0: OSD-0.  1..64: OSD-CS of this order (combination sweep,
                                Roffe et al. 2020; the paper's BP-OSD uses order 7): after the
                                full information set S, every weight-1 flip of the other

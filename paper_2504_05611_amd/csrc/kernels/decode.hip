@@ -57,6 +57,8 @@ struct DecodeDevice {
   uint32_t* sign0 = nullptr;       // [E4 / 4] sign bytes of iteration 1
   int32_t E4 = 0;
   int32_t max_row_deg = 0;
+  uint64_t* lone = nullptr;        // [mw] checks without edges (null: none)
+  uint64_t pm_lam[MAX_OW] = {};    // observables of the hard decision of lambda
   // per-lane BP schedules, one per team size used so far
   struct Sched { int P = 0; int mode = 1; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr; };
   std::vector<Sched> scheds;
@@ -72,52 +74,6 @@ struct DecodeDevice {
   int32_t* retry = nullptr;         // OSD jobs the sorted prefix did not settle
   size_t cap_queue = 0, cap_osd = 0, cap_llr = 0, cap_basis = 0, cap_synd = 0, cap_gstate = 0, cap_rowmap = 0;
   size_t cap_retry = 0;
-};
-
-// Per-lane schedule records of the BP passes (int4 = {x, y, z, w}).
-//   check pass: x = v | flags, y = CSR edge e, z = check c (edges of a check are
-//               consecutive in one lane, in CSR order)
-//   var pass:   x = v | flags, y = CSR edge e, z = check c (entries of a column
-//               are consecutive in one lane, in CSC order)
-constexpr int32_t R_FIRST = 1 << 30;    // first edge of its check / column
-constexpr int32_t R_LAST = (int32_t)(1u << 31);
-constexpr int32_t R_IDX = (1 << 30) - 1;
-
-struct BPArgs {
-  const int4* csched;        // [Kc][P] check-pass records
-  const int4* vsched;        // [Kv][P] variable-pass records
-  int32_t Kc, Kv;
-  const int4* init;          // [m] check state of iteration 1 (n1, n2 bits, argmin edge, sign parity)
-  const uint32_t* sign0;     // [E4 / 4] sign bytes of q at iteration 1
-  const float* lam;
-  const uint64_t* obs_mask;  // [ow][n]
-  int32_t ow;
-  int32_t m, n;
-  int64_t E;
-  int32_t E32;               // E as int32
-  int32_t E4;                // E rounded up to a multiple of 4
-  int32_t T;
-  float alpha;
-  const float* w;            // nullable [T][E]
-  const uint64_t* synd;      // [chunk shots][mw] shot-major syndrome words
-  int32_t mw;
-  int64_t stride;            // words per row of pred
-  int64_t shot0;             // first shot of this chunk (within the call)
-  int64_t nshots;            // shots in this chunk
-  const int32_t* queue;      // nullable: identity
-  int32_t* counters;
-  int32_t use_osd;
-  int32_t* osd_queue;
-  float* osd_llr;            // [chunk][n]
-  uint64_t* pred;            // [k][stride]
-  int32_t nobs;
-  tmcs_decode_stats* stats;
-  uint8_t* ehat;
-  float* llr;
-  int32_t* iters;
-  uint8_t* flags;
-  unsigned char* gstate;     // GSTATE: [grid][team_bytes]
-  size_t team_bytes;
 };
 
 __global__ void k_zero_words(uint64_t* p, int64_t n) {
@@ -261,13 +217,6 @@ __global__ void __launch_bounds__(256) k_compact_wide(const uint64_t* __restrict
 // switches to that item's arguments mu.tab[i].  Items are taken in order, so a
 // team switches at most once per item; its statistics go to the item they
 // belong to.  Weights are then per item (weights may be null: scalar alpha).
-
-struct BPMulti {
-  const BPArgs* tab;
-  int32_t n;
-  int32_t* next;
-};
-constexpr int MAX_MULTI = 16;
 
 template <bool WEIGHTED, bool GSTATE, bool MULTI = false>
 __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
@@ -519,7 +468,7 @@ void free_device(DecodeDevice* d) {
   hipFree(d->row_ptr); hipFree(d->col_idx); hipFree(d->col_ptr); hipFree(d->csc_row); hipFree(d->csc_edge);
   hipFree(d->lam); hipFree(d->obs_mask); hipFree(d->counters); hipFree(d->queue); hipFree(d->osd_queue);
   hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd); hipFree(d->gstate); hipFree(d->init); hipFree(d->sign0);
-  hipFree(d->rowmap); hipFree(d->retry);
+  hipFree(d->rowmap); hipFree(d->retry); hipFree(d->lone);
   for (auto& q : d->scheds) { hipFree(q.c); hipFree(q.v); }
   *d = DecodeDevice();
 }
@@ -567,6 +516,20 @@ tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
     r.w = npar;
     init[c] = r;
     d->max_row_deg = std::max(d->max_row_deg, D.row_ptr[c + 1] - D.row_ptr[c]);
+  }
+  // checks without edges (a shot with such a detection event never satisfies
+  // H e = s) and the observables flipped by the hard decision of lambda alone
+  std::vector<uint64_t> lone((size_t)std::max((D.rows + 63) / 64, 1), 0ull);
+  bool any_lone = false;
+  for (int c = 0; c < D.rows; ++c)
+    if (D.row_ptr[c + 1] == D.row_ptr[c]) { lone[c >> 6] |= 1ull << (c & 63); any_lone = true; }
+  for (int j = 0; j < D.cols; ++j)
+    if (lam[j] < 0.0f)
+      for (int w = 0; w < D.obs_words && w < MAX_OW; ++w) d->pm_lam[w] ^= D.obs_mask[(size_t)j * D.obs_words + w];
+  if (any_lone && (st = upload(&d->lone, lone)) != TMCS_OK) {
+    free_device(d);
+    delete d;
+    return st;
   }
   std::vector<uint32_t> sg32((size_t)d->E4 / 4);
   if (!sg32.empty()) std::memcpy(sg32.data(), sg.data(), sg.size());
@@ -632,7 +595,10 @@ int strided_assign(const std::vector<int>& size, int P, std::vector<std::vector<
 // (cfg.bp_sched: 1 longest-processing-time lists, 2 strided), cached per both.
 // (Contiguous per-lane ranges were also tried for state in device memory: the
 // lanes of a step then sit a fixed stride apart and hit the same HBM channels,
-// 7x slower.)
+// 7x slower.)  P < 64 builds the lists of the lanes kernel, one per wave, each
+// stored contiguously ([P][K + LANES_UNROLL]): their length is a multiple of
+// LANES_UNROLL, followed by LANES_UNROLL records of padding.  Team lists are
+// interleaved ([K + 2][P]): even length, two rows of padding.
 tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevice::Sched* out) {
   for (const auto& q : d->scheds)
     if (q.P == P && q.mode == mode) { *out = q; return TMCS_OK; }
@@ -647,10 +613,11 @@ tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevi
   // padding steps touch only spare LDS slots (edge E4, check m) and never
   // carry FIRST/LAST, so their results are never stored
   const int4 pad = make_int4(0, d->E4, D.rows, 0);
-  // K is rounded up to even, plus two rows of padding read by the prefetch
-  q.Kc = assign(rdeg, P, &lanes);
-  q.Kc += q.Kc & 1;
-  std::vector<int4> cs((size_t)(q.Kc + 2) * P, pad);
+  // K is rounded up to the batch (team lists: even), plus one batch of padding read by the prefetch
+  const int kb = P < 64 ? LANES_UNROLL : 2;
+  auto round_k = [&](int k) { return (k + kb - 1) / kb * kb; };
+  q.Kc = round_k(assign(rdeg, P, &lanes));
+  std::vector<int4> cs((size_t)(q.Kc + kb) * P, pad);
   for (int l = 0; l < P; ++l) {
     int k = 0;
     for (int c : lanes[l])
@@ -658,12 +625,11 @@ tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevi
         int32_t x = D.col_idx[e];
         if (e == D.row_ptr[c]) x |= R_FIRST;
         if (e == D.row_ptr[c + 1] - 1) x |= R_LAST;
-        cs[(size_t)k * P + l] = make_int4(x, e, c, 0);
+        cs[P < 64 ? (size_t)l * (q.Kc + kb) + k : (size_t)k * P + l] = make_int4(x, e, c, 0);
       }
   }
-  q.Kv = assign(cdeg, P, &lanes);
-  q.Kv += q.Kv & 1;
-  std::vector<int4> vs((size_t)(q.Kv + 2) * P, pad);
+  q.Kv = round_k(assign(cdeg, P, &lanes));
+  std::vector<int4> vs((size_t)(q.Kv + kb) * P, pad);
   for (int l = 0; l < P; ++l) {
     int k = 0;
     for (int v : lanes[l])
@@ -674,7 +640,7 @@ tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevi
         float lv = (float)std::log((1.0 - D.priors[v]) / D.priors[v]);
         int32_t lbits;
         std::memcpy(&lbits, &lv, 4);
-        vs[(size_t)k * P + l] = make_int4(x, D.csc_edge[j], D.row_idx[j], lbits);
+        vs[P < 64 ? (size_t)l * (q.Kv + kb) + k : (size_t)k * P + l] = make_int4(x, D.csc_edge[j], D.row_idx[j], lbits);
       }
   }
   tmcs_status st;
@@ -721,16 +687,29 @@ struct DecodePass {
   bool full = false;           // per-shot outputs requested (no compaction)
   int mw = 0;
   bool gstate = false;
+  bool lanes = false;          // state in device memory, 64 shots per workgroup (bp_lanes.hip)
   int P = 0, bp_grid_max = 0;
   size_t bp_lds = 0, team_bytes = 0;
   DecodeDevice::Sched sch;
   bool osd_win = false, osd_pfx = false, osd_bl = false;
-  int npad = 0, pfx_keys = 0, pfx_rank = 0, osd_grid = 0, pfx_grid = 0;
-  size_t osd_lds = 0, pfx_lds = 0;
+  bool win2 = false;           // windowed: a smaller first window, then the full one on what it leaves open
+  int npad = 0, pfx_keys = 0, pfx_rank = 0, osd_grid = 0, pfx_grid = 0, win1_grid = 0, win1_rows = 0;
+  size_t osd_lds = 0, pfx_lds = 0, win1_lds = 0;
 };
 
+// Workgroups of a lanes launch over ns shots: one per 64 shots, at most the
+// resident grid, and at most LANES_SLAB_MAX bytes of state in device memory.
+constexpr size_t LANES_SLAB_MAX = 48ull << 30;
+int lanes_grid(int grid_max, size_t slab, int64_t ns) {
+  const int64_t groups = (std::max<int64_t>(ns, 1) + 63) / 64;
+  const int64_t by_mem = std::max<int64_t>(1, (int64_t)(LANES_SLAB_MAX / std::max<size_t>(slab, 1)));
+  return (int)std::min<int64_t>({(int64_t)grid_max, groups, by_mem});
+}
+
+// shared_slab: the caller provides the lanes kernel's state (a multi launch);
+// otherwise it is allocated on the DEM's device state for the pass's grid.
 tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n_shots, void* state,
-                           hipStream_t stream, DecodePass* out) {
+                           hipStream_t stream, DecodePass* out, bool shared_slab = false) {
   DecodePass& ps = *out;
   DecodeDevice* d = (DecodeDevice*)state;
   tmcs_status st = TMCS_OK;
@@ -747,6 +726,8 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   if (cfg.osd_window < 0 || cfg.osd_window > WIN_MAX_ROWS)
     return fail(TMCS_EINVAL, "osd_window must be in [0, 2048]");
   if (cfg.osd_order < 0 || cfg.osd_order > 64) return fail(TMCS_EINVAL, "osd_order must be in [0, 64]");
+  if (cfg.bp_global_state < 0 || cfg.bp_global_state > 2)
+    return fail(TMCS_EINVAL, "bp_global_state must be 0, 1 or 2");
   // dense OSD-0 while H fits its registers and sort, windowed beyond (or on request)
   const bool osd_win = cfg.use_osd && (cfg.osd_window > 0 || npad > OSD_MAX_KEYS || mw > 32);
   if (osd_win && cfg.osd_order > 0)
@@ -755,13 +736,27 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   // BP launch shape: one team (workgroup) per shot in flight, state in LDS
   const size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (size_t)d->E4 + 4;
   const bool gstate = cfg.bp_global_state != 0 || bp_lds > 160 * 1024;
+  // state in device memory: one team per shot, or on request 64 shots per
+  // workgroup in the lanes of its waves (on the surface-code NL-CNOT at d = 15..29
+  // that layout measured 2-5x slower than the team kernel)
+  const bool lanes = gstate && cfg.bp_global_state == 2 && D.rows > 0 && D.edges > 0;
+  ps.lanes = lanes;
+  if (lanes) {
+    const int mode = cfg.bp_sched > 0 ? cfg.bp_sched : 2;
+    if ((st = get_sched(D, d, LANES_WAVES, mode, &ps.sch)) != TMCS_OK) return st;
+    ps.gstate = true;
+    ps.P = 64 * LANES_WAVES;
+    ps.team_bytes = lanes_slab_bytes(D.rows, D.cols, d->E4);
+    ps.bp_grid_max = cus * std::max(1, std::min(cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 1, 2));
+  }
   const size_t team_bytes = (bp_lds + 255) & ~(size_t)255;
   // teams per CU: as many as fit in LDS; with the state in device memory, one
   // team of 16 waves (fewer slabs in flight: at d = 15..29 that was 1.2-1.7x
   // faster than 4 teams of 8 waves), unless the caller asks for another shape
   const int team_fit = gstate ? (cfg.bp_per_cu > 0 ? 32 : 1) : std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));
-  int P;
-  if (cfg.bp_threads > 0) {
+  int P = 64;
+  if (lanes) {
+  } else if (cfg.bp_threads > 0) {
     P = cfg.bp_threads;
   } else {
     // about 24 waves per CU (the passes are latency-bound: more waves, more
@@ -773,7 +768,7 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   }
   P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
   const int sched_mode = cfg.bp_sched > 0 ? cfg.bp_sched : 1;
-  if ((st = get_sched(D, d, P, sched_mode, &ps.sch)) != TMCS_OK) return st;
+  if (!lanes && (st = get_sched(D, d, P, sched_mode, &ps.sch)) != TMCS_OK) return st;
   if (!gstate && bp_lds > 64 * 1024 &&
       (hipFuncSetAttribute((const void*)k_bp<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
        hipFuncSetAttribute((const void*)k_bp<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
@@ -781,10 +776,12 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
     return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
   const int per_cu = std::max(1, std::min({team_fit, 32 / (P / 64), cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 32}));
   ps.gstate = gstate;
-  ps.P = P;
   ps.bp_lds = bp_lds;
-  ps.team_bytes = team_bytes;
-  ps.bp_grid_max = cus * per_cu;
+  if (!lanes) {
+    ps.P = P;
+    ps.team_bytes = team_bytes;
+    ps.bp_grid_max = cus * per_cu;
+  }
   // shots per internal pass: as few passes as the OSD LLR staging allows
   // (<= 8 GiB), each ending on its slowest teams; passes of equal size
   int64_t cmax = std::max<int64_t>(DECODE_CHUNK_MIN, ((1ll << 31) / std::max(D.cols, 1)) & ~63ll);
@@ -827,22 +824,43 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   const int osd_grid = std::max(1, cus * osd_per_cu);
   const int pfx_fit = std::max<int>(1, (int)((160 * 1024) / (pfx_lds + 512)));
   const int pfx_grid = std::max(1, cus * std::min(pfx_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 16));
-  ps.osd_win = osd_win; ps.osd_pfx = osd_pfx; ps.osd_bl = osd_bl;
+  // windowed OSD-0 in two passes: a window of WIN_SMALL_ROWS local rows first
+  // (a quarter of the registers and LDS, so more workgroups per compute unit),
+  // then the full window on the shots whose early stop it does not reach.
+  // Local rows are numbered in order of first touch in both, so the smaller
+  // window's basis is a prefix of the larger's and every settled shot gets the
+  // same correction.
+  // (first window: a quarter of the full one's rows, at most WIN_SMALL_ROWS)
+  const int user_rows = cfg.osd_window > 0 ? cfg.osd_window : WIN_MAX_ROWS;
+  const int win1_rows = std::min(WIN_SMALL_ROWS, user_rows / 4);
+  const bool win2 = osd_win && win1_rows >= 2;
+  const int W1 = 2 * WIN_SMALL_MW;
+  const size_t win1_lds = (size_t)WIN_KEYS * 8 + (size_t)WIN_SMALL_ROWS * 16 + (size_t)W1 * 8 + 64;
+  const int win1_fit = std::max<int>(1, (int)((160 * 1024) / (win1_lds + 512)));
+  const int win1_grid = std::max(1, cus * std::min(win1_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 8));
+  ps.osd_win = osd_win; ps.osd_pfx = osd_pfx; ps.osd_bl = osd_bl; ps.win2 = win2;
   ps.npad = npad; ps.pfx_keys = pfx_keys; ps.pfx_rank = pfx_rank;
   ps.osd_grid = osd_grid; ps.pfx_grid = pfx_grid; ps.osd_lds = osd_lds; ps.pfx_lds = pfx_lds;
+  ps.win1_grid = win1_grid; ps.win1_lds = win1_lds; ps.win1_rows = win1_rows;
   if ((st = grow(&d->queue, &d->cap_queue, (size_t)chunk)) != TMCS_OK) return st;
   if ((st = grow(&d->synd, &d->cap_synd, (size_t)chunk * (size_t)std::max(mw, 1))) != TMCS_OK) return st;
-  if (gstate && (st = grow(&d->gstate, &d->cap_gstate, (size_t)cus * per_cu * team_bytes)) != TMCS_OK) return st;
+  if (gstate && !lanes && (st = grow(&d->gstate, &d->cap_gstate, (size_t)cus * per_cu * team_bytes)) != TMCS_OK)
+    return st;
+  if (lanes && !shared_slab &&
+      (st = grow(&d->gstate, &d->cap_gstate, (size_t)lanes_grid(ps.bp_grid_max, ps.team_bytes, chunk) * ps.team_bytes)) !=
+          TMCS_OK)
+    return st;
   if (cfg.use_osd) {
     if ((st = grow(&d->osd_queue, &d->cap_osd, (size_t)chunk)) != TMCS_OK ||
         (st = grow(&d->osd_llr, &d->cap_llr, (size_t)chunk * (size_t)D.cols)) != TMCS_OK ||
         (!osd_bl && (st = grow(&d->basis, &d->cap_basis,
-                               std::max((size_t)osd_grid * (size_t)std::max(osd_rank, 1) * W,
-                                        osd_pfx ? (size_t)pfx_grid * (size_t)std::max(pfx_rank, 1) * W_pfx : 0))) != TMCS_OK))
+                               std::max({(size_t)osd_grid * (size_t)std::max(osd_rank, 1) * W,
+                                         osd_pfx ? (size_t)pfx_grid * (size_t)std::max(pfx_rank, 1) * W_pfx : 0,
+                                         win2 ? (size_t)win1_grid * WIN_SMALL_ROWS * W1 : 0}))) != TMCS_OK))
       return st;
-    if (osd_pfx && (st = grow(&d->retry, &d->cap_retry, (size_t)chunk)) != TMCS_OK) return st;
+    if ((osd_pfx || win2) && (st = grow(&d->retry, &d->cap_retry, (size_t)chunk)) != TMCS_OK) return st;
     if (osd_win) {
-      const size_t n_map = (size_t)osd_grid * 2 * (size_t)std::max(D.rows, 1);
+      const size_t n_map = (size_t)std::max(osd_grid, win2 ? win1_grid : 0) * 2 * (size_t)std::max(D.rows, 1);
       const int32_t* before = d->rowmap;
       const size_t cap_before = d->cap_rowmap;
       if ((st = grow(&d->rowmap, &d->cap_rowmap, n_map)) != TMCS_OK) return st;
@@ -874,6 +892,8 @@ BPArgs bp_args(const DecodePass& ps, const uint64_t* det_unused, uint64_t* pred,
   a.pred = pred; a.nobs = D.nobs; a.stats = stats; a.ehat = cfg.ehat_dev; a.llr = cfg.llr_dev;
   a.iters = cfg.iters_dev; a.flags = cfg.flags_dev;
   a.gstate = d->gstate; a.team_bytes = ps.team_bytes;
+  a.lone = d->lone;
+  for (int w = 0; w < MAX_OW; ++w) a.pm_lam[w] = d->pm_lam[w];
   return a;
 }
 
@@ -937,6 +957,9 @@ void decode_stage(const DecodePass& ps, const uint64_t* det, tmcs_decode_stats* 
 tmcs_status decode_bp_launch(const DecodePass& ps, const BPArgs& a, int64_t ns, hipStream_t stream) {
   const int bp_grid = (int)std::min<int64_t>((int64_t)ps.bp_grid_max, std::max<int64_t>(ns, 1));
   const BPMulti none{nullptr, 0, nullptr};
+  if (ps.lanes)
+    return launch_bp_lanes(a, none, ps.cfg.weights_dev != nullptr, lanes_grid(ps.bp_grid_max, ps.team_bytes, ns),
+                           stream);
   if (ps.gstate) {
     if (ps.cfg.weights_dev) TMCS_LAUNCH("k_bp_dev", (k_bp<true, true>), dim3(bp_grid), dim3(ps.P), 0, stream, a, none);
     else TMCS_LAUNCH("k_bp_dev", (k_bp<false, true>), dim3(bp_grid), dim3(ps.P), 0, stream, a, none);
@@ -951,7 +974,17 @@ tmcs_status decode_osd_launch(const DecodePass& ps, uint64_t* pred, tmcs_decode_
                               hipStream_t stream) {
   if (!ps.cfg.use_osd) return TMCS_OK;
   const OSDArgs o = osd_args(ps, pred, stats, s0);
-  if (ps.osd_win) return launch_osd_win(o, ps.osd_grid, ps.osd_lds, stream);
+  if (ps.osd_win) {
+    if (!ps.win2) return launch_osd_win(o, ps.osd_grid, ps.osd_lds, stream, false);
+    OSDArgs o1 = o;
+    o1.retry = ps.d->retry;
+    o1.win_rows = ps.win1_rows;
+    tmcs_status st = launch_osd_win(o1, ps.win1_grid, ps.win1_lds, stream, true);
+    if (st != TMCS_OK) return st;
+    OSDArgs o2 = o;
+    o2.jobs = ps.d->retry; o2.cnt_total = 4; o2.cnt_next = 5;
+    return launch_osd_win(o2, ps.osd_grid, ps.osd_lds, stream, false);
+  }
   if (ps.osd_pfx) {
     OSDArgs op = o;
     op.npad = ps.pfx_keys;
@@ -1001,7 +1034,8 @@ struct MultiDecode {
     tmcs_decode_stats* stats = nullptr;
   };
   struct BPGroup {
-    bool gstate = false, weighted = false;
+    bool gstate = false, lanes = false, weighted = false;
+    unsigned char* slab = nullptr;   // lanes: the state of every workgroup, shared by the group's items
     int P = 0, grid = 0;
     size_t lds = 0;
     std::vector<int> items;
@@ -1012,7 +1046,12 @@ struct MultiDecode {
   uint64_t batch = 0;
   std::vector<BPGroup> bp;
   std::vector<int> osd_win_items, osd_other_items;
+  bool osd_win2 = false;     // the windowed items run the two-window scheme
   OSDArgs* osd_tab = nullptr;
+  OSDArgs* osd_tab2 = nullptr;   // win2: the full window's pass over the retry lists
+  OSDArgs osd_first2{};
+  int osd_grid1 = 0;
+  size_t osd_lds1 = 0;
   OSDArgs osd_first{};       // host copy of the first windowed item's arguments
   int osd_grid = 0;
   size_t osd_lds = 0;
@@ -1021,8 +1060,9 @@ struct MultiDecode {
 
 void decode_multi_free(MultiDecode* m) {
   if (!m) return;
-  for (auto& g : m->bp) hipFree(g.tab);
+  for (auto& g : m->bp) { hipFree(g.tab); hipFree(g.slab); }
   hipFree(m->osd_tab);
+  hipFree(m->osd_tab2);
   hipFree(m->next);
   delete m;
 }
@@ -1038,7 +1078,7 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
     MultiDecode::Item it;
     it.det = sp.det; it.pred = sp.pred; it.stats = sp.stats;
     if (sp.cfg.ehat_dev || sp.cfg.llr_dev || sp.cfg.iters_dev || sp.cfg.flags_dev) st = fail(TMCS_EINVAL, "multi decode: no per-shot outputs");
-    if (st == TMCS_OK) st = decode_prepare(*sp.D, sp.cfg, batch, sp.state, stream, &it.ps);
+    if (st == TMCS_OK) st = decode_prepare(*sp.D, sp.cfg, batch, sp.state, stream, &it.ps, true);
     if (st == TMCS_OK && it.ps.chunk < (int64_t)batch) st = fail(TMCS_EUNSUPPORTED, "multi decode: batch exceeds one decoder pass");
     if (st != TMCS_OK) { decode_multi_free(m); return st; }
     m->items.push_back(it);
@@ -1048,11 +1088,12 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
     const DecodePass& ps = m->items[i].ps;
     MultiDecode::BPGroup* g = nullptr;
     for (auto& q : m->bp)
-      if (q.gstate == ps.gstate && q.P == ps.P) g = &q;
+      if (q.gstate == ps.gstate && q.lanes == ps.lanes && q.P == ps.P) g = &q;
     if (!g) {
       m->bp.push_back(MultiDecode::BPGroup());
       g = &m->bp.back();
       g->gstate = ps.gstate;
+      g->lanes = ps.lanes;
       g->P = ps.P;
       g->grid = ps.bp_grid_max;
     }
@@ -1074,10 +1115,29 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
         return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
       }
     }
+    if (g.lanes) {
+      // heaviest items first (workgroups take the items in order), one state
+      // slab per workgroup sized for the largest item
+      std::stable_sort(g.items.begin(), g.items.end(), [&](int x, int y) {
+        return m->items[x].ps.D->edges > m->items[y].ps.D->edges;
+      });
+      size_t slab = 0;
+      for (int i : g.items) slab = std::max(slab, m->items[i].ps.team_bytes);
+      g.lds = slab;
+      g.grid = lanes_grid(g.grid, slab, (int64_t)batch * (int64_t)g.items.size());
+      if (hipMalloc((void**)&g.slab, (size_t)g.grid * slab) != hipSuccess) {
+        decode_multi_free(m);
+        return fail(TMCS_ENOMEM, "hipMalloc failed (BP state of the multi decode)");
+      }
+    }
     std::vector<BPArgs> tab;
     for (int i : g.items) {
       const auto& it = m->items[i];
       tab.push_back(bp_args(it.ps, it.det, it.pred, it.stats, 0, (int64_t)batch));
+      if (g.lanes) {
+        tab.back().gstate = g.slab;
+        tab.back().team_bytes = g.lds;
+      }
     }
     g.first = tab[0];
     if ((st = upload(&g.tab, tab)) != TMCS_OK) { decode_multi_free(m); return st; }
@@ -1086,22 +1146,43 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
   for (int i = 0; i < (int)m->items.size(); ++i) {
     const DecodePass& ps = m->items[i].ps;
     if (!ps.cfg.use_osd) continue;
-    const bool join = ps.osd_win && (m->osd_win_items.empty() || (ps.osd_grid == m->osd_grid && ps.osd_lds == m->osd_lds));
+    const bool join = ps.osd_win && (m->osd_win_items.empty() || (ps.osd_grid == m->osd_grid && ps.osd_lds == m->osd_lds &&
+                                                               ps.win2 == m->osd_win2 && ps.win1_grid == m->osd_grid1 &&
+                                                               ps.win1_lds == m->osd_lds1));
     if (join) {
       m->osd_win_items.push_back(i);
       m->osd_grid = ps.osd_grid;
       m->osd_lds = ps.osd_lds;
+      m->osd_win2 = ps.win2;
+      m->osd_grid1 = ps.win1_grid;
+      m->osd_lds1 = ps.win1_lds;
     } else {
       m->osd_other_items.push_back(i);
     }
   }
   if (!m->osd_win_items.empty()) {
     std::vector<OSDArgs> tab;
-    for (int i : m->osd_win_items) tab.push_back(osd_args(m->items[i].ps, m->items[i].pred, m->items[i].stats, 0));
+    std::vector<OSDArgs> tab2;
+    for (int i : m->osd_win_items) {
+      const DecodePass& ps = m->items[i].ps;
+      OSDArgs o = osd_args(ps, m->items[i].pred, m->items[i].stats, 0);
+      if (m->osd_win2) {
+        OSDArgs o2 = o;
+        o2.jobs = ps.d->retry; o2.cnt_total = 4; o2.cnt_next = 5;
+        tab2.push_back(o2);
+        o.retry = ps.d->retry;
+        o.win_rows = ps.win1_rows;
+      }
+      tab.push_back(o);
+    }
     m->osd_first = tab[0];
     if ((st = upload(&m->osd_tab, tab)) != TMCS_OK) { decode_multi_free(m); return st; }
+    if (m->osd_win2) {
+      m->osd_first2 = tab2[0];
+      if ((st = upload(&m->osd_tab2, tab2)) != TMCS_OK) { decode_multi_free(m); return st; }
+    }
   }
-  if (hipMalloc((void**)&m->next, 2 * sizeof(int32_t)) != hipSuccess) {
+  if (hipMalloc((void**)&m->next, 3 * sizeof(int32_t)) != hipSuccess) {
     decode_multi_free(m);
     return fail(TMCS_ENOMEM, "hipMalloc failed (multi decode counters)");
   }
@@ -1116,7 +1197,7 @@ tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream) {
     decode_zero_pred(it.ps, it.pred, stream);
     decode_stage(it.ps, it.det, it.stats, 0, ns, stream);
   }
-  TMCS_LAUNCH("k_zero_i32", k_zero_i32, dim3(1), dim3(64), 0, stream, m->next, 2);
+  TMCS_LAUNCH("k_zero_i32", k_zero_i32, dim3(1), dim3(64), 0, stream, m->next, 3);
   tmcs_status st;
   for (auto& g : m->bp) {
     // (the BP job counter is shared by the groups in turn: zeroed before each)
@@ -1124,6 +1205,10 @@ tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream) {
     const BPMulti mu{g.tab, (int32_t)g.items.size(), m->next};
     const int grid = std::max(1, g.grid);
     const BPArgs& a0 = g.first;
+    if (g.lanes) {
+      if ((st = launch_bp_lanes(a0, mu, g.weighted, grid, stream)) != TMCS_OK) return st;
+      continue;
+    }
     if (g.gstate) {
       if (g.weighted) TMCS_LAUNCH("k_bp_dev", (k_bp<true, true, true>), dim3(grid), dim3(g.P), 0, stream, a0, mu);
       else TMCS_LAUNCH("k_bp_dev", (k_bp<false, true, true>), dim3(grid), dim3(g.P), 0, stream, a0, mu);
@@ -1135,7 +1220,13 @@ tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream) {
   }
   if (!m->osd_win_items.empty()) {
     const OSDMulti mu{m->osd_tab, (int32_t)m->osd_win_items.size(), m->next + 1};
-    if ((st = launch_osd_win_multi(m->osd_first, mu, m->osd_grid, m->osd_lds, stream)) != TMCS_OK) return st;
+    if (m->osd_win2) {
+      if ((st = launch_osd_win_multi(m->osd_first, mu, m->osd_grid1, m->osd_lds1, stream, true)) != TMCS_OK) return st;
+      const OSDMulti mu2{m->osd_tab2, (int32_t)m->osd_win_items.size(), m->next + 2};
+      if ((st = launch_osd_win_multi(m->osd_first2, mu2, m->osd_grid, m->osd_lds, stream, false)) != TMCS_OK) return st;
+    } else if ((st = launch_osd_win_multi(m->osd_first, mu, m->osd_grid, m->osd_lds, stream, false)) != TMCS_OK) {
+      return st;
+    }
   }
   for (int i : m->osd_other_items) {
     auto& it = m->items[i];

@@ -19,6 +19,9 @@ constexpr int OSD_MAX_KEYS = 16384;
 constexpr int WIN_KEYS = 2048;
 constexpr int WIN_MW = 32;
 constexpr int WIN_MAX_ROWS = 64 * WIN_MW;
+// the smaller first window (its shots that need more rows go to the full one)
+constexpr int WIN_SMALL_MW = 8;
+constexpr int WIN_SMALL_ROWS = 64 * WIN_SMALL_MW;
 // dense OSD-0 first tries this many smallest keys (one-wave and 256-thread variants)
 constexpr int PFX_KEYS_WAVE = 128;
 constexpr int PFX_KEYS_WG = 1024;
@@ -47,6 +50,76 @@ __device__ __forceinline__ uint64_t block_xor_u64(uint64_t v, uint64_t* scratch)
   return r;
 }
 
+// ------------------------------------------------------------------ BP
+// Schedule records of the BP passes (int4 = {x, y, z, w}).
+//   check pass: x = v | flags, y = CSR edge e, z = check c (edges of a check are
+//               consecutive in one lane, in CSR order)
+//   var pass:   x = v | flags, y = CSR edge e, z = check c, w = lambda_v bits
+//               (entries of a column are consecutive in one lane, in CSC order)
+// A team kernel gives every lane its own record list; the lanes kernel gives
+// every wave one.
+constexpr int32_t R_FIRST = 1 << 30;    // first edge of its check / column
+constexpr int32_t R_LAST = (int32_t)(1u << 31);
+constexpr int32_t R_IDX = (1 << 30) - 1;
+
+struct BPArgs {
+  const int4* csched;        // [Kc][P] check-pass records
+  const int4* vsched;        // [Kv][P] variable-pass records
+  int32_t Kc, Kv;
+  const int4* init;          // [m] check state of iteration 1 (n1, n2 bits, argmin edge, sign parity)
+  const uint32_t* sign0;     // [E4 / 4] sign bytes of q at iteration 1
+  const float* lam;
+  const uint64_t* obs_mask;  // [ow][n]
+  int32_t ow;
+  int32_t m, n;
+  int64_t E;
+  int32_t E32;               // E as int32
+  int32_t E4;                // E rounded up to a multiple of 4
+  int32_t T;
+  float alpha;
+  const float* w;            // nullable [T][E]
+  const uint64_t* synd;      // [chunk shots][mw] shot-major syndrome words
+  int32_t mw;
+  int64_t stride;            // words per row of pred
+  int64_t shot0;             // first shot of this chunk (within the call)
+  int64_t nshots;            // shots in this chunk
+  const int32_t* queue;      // nullable: identity
+  int32_t* counters;
+  int32_t use_osd;
+  int32_t* osd_queue;
+  float* osd_llr;            // [chunk][n]
+  uint64_t* pred;            // [k][stride]
+  int32_t nobs;
+  tmcs_decode_stats* stats;
+  uint8_t* ehat;
+  float* llr;
+  int32_t* iters;
+  uint8_t* flags;
+  unsigned char* gstate;     // state in device memory: [grid][team_bytes]
+  size_t team_bytes;
+  const uint64_t* lone;      // nullable [mw]: checks without edges (such a check with s_c = 1 is never satisfied)
+  uint64_t pm_lam[MAX_OW];   // observables flipped by the hard decision of lambda (a shot with s = 0)
+};
+
+// Several decode items' BP queues served by one launch.
+struct BPMulti {
+  const BPArgs* tab;         // device [n]: the items' arguments
+  int32_t n;
+  int32_t* next;             // device job counter shared by the launch (zeroed before it)
+};
+constexpr int MAX_MULTI = 16;
+
+// BP with 64 shots per workgroup, one in each lane of every wave (bp_lanes.hip).
+constexpr int LANES_WAVES = 16;         // waves per workgroup: each walks its own record list
+constexpr int LANES_UNROLL = 8;         // records per batch of loads; lists are padded to a multiple
+// Device-memory bytes of one lanes workgroup's state for an m x n DEM with E4 edge slots.
+inline size_t lanes_slab_bytes(int m, int n, int E4) {
+  const size_t b = (size_t)(m + 1) * 64 * 16 + (size_t)(n + 1) * 64 * 4 + ((size_t)E4 + 1) * 8;
+  return (b + 255) & ~(size_t)255;
+}
+// mu.n > 0: a multi launch over mu's items (a is ignored); grid workgroups of LANES_WAVES waves.
+tmcs_status launch_bp_lanes(const BPArgs& a, const BPMulti& mu, bool weighted, int grid, hipStream_t s);
+
 // ------------------------------------------------------------------ OSD-0
 struct OSDArgs {
   const int32_t* col_ptr;
@@ -72,7 +145,7 @@ struct OSDArgs {
   int32_t win_rows;          // WIN: most local rows a window may hold (<= 64 * MW)
   const int32_t* jobs;       // nullable: job j is jobs[j] (a retry pass), else j
   int32_t cnt_total, cnt_next;   // counters[] holding the number of jobs and the next job
-  int32_t* retry;            // PFX: jobs whose prefix did not span s (counted in counters[4])
+  int32_t* retry;            // PFX, and WIN's first window: jobs left open (counted in counters[4])
   int32_t order;             // > 0: OSD-CS of this order (dense variants only)
 };
 
@@ -86,9 +159,11 @@ struct OSDMulti {
 
 // OSD launchers (osd.hip).  grid workgroups, lds bytes of dynamic LDS.
 // first: the first item's arguments (host copy; they fix the shared LDS layout).
-tmcs_status launch_osd_win_multi(const OSDArgs& first, const OSDMulti& mu, int grid, size_t lds, hipStream_t s);
+// small: the first window of WIN_SMALL_ROWS rows (a.retry receives what it leaves open).
+tmcs_status launch_osd_win_multi(const OSDArgs& first, const OSDMulti& mu, int grid, size_t lds, hipStream_t s,
+                                 bool small);
 // Windowed OSD-0 (DEMs beyond the dense limits).
-tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s);
+tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s, bool small);
 // Dense OSD-0 on the npad - 1 smallest keys first (jobs the prefix does not settle go to a.retry).
 tmcs_status dispatch_osd_pfx(int mw, bool bl, const OSDArgs& a, int grid, size_t lds, hipStream_t s);
 // Dense OSD-0 (or OSD-CS) with a full sort of kpt keys per thread; bl: basis in LDS, one wave per shot.

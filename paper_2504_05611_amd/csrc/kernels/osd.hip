@@ -17,6 +17,13 @@ namespace dec {
 
 
 
+// Posteriors each thread has in flight in the selection passes: 8 in the
+// windowed variant (hundreds of thousands of columns; 20-25 % faster there),
+// 1 in the prefix variant (at most 16384 columns: the registers cost it a
+// workgroup per SIMD, 50 % slower on BB [[144,12,12]] teleport).
+template <bool WIN>
+constexpr int sel_unroll() { return WIN ? 8 : 1; }
+
 // Coherent (L2) 32-bit load: rowmap entries are updated with atomics and by
 // other waves of the workgroup within one shot.
 __device__ __forceinline__ int32_t ld_l2(const int32_t* p) {
@@ -291,9 +298,19 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a, OSDMulti mu) {
           const uint32_t hmask = pass == 0 ? 0u : (0xFFFFFFFFu << (sh + 8));
           for (int i = tid; i < 256; i += NT) s_hist[i] = 0;
           __syncthreads();
-          for (int v = tid; v < a.n; v += NT) {
-            const uint32_t k = order_key(L[v]);
-            if ((k & hmask) == (pre & hmask)) atomicAdd(&s_hist[(k >> sh) & 255u], 1);
+          // SEL_UNROLL posteriors per thread in flight (unconditional loads: the
+          // last index is clamped and masked out afterwards)
+          constexpr int SEL_UNROLL = sel_unroll<WIN>();
+          for (int v0 = tid; v0 < a.n; v0 += NT * SEL_UNROLL) {
+            uint32_t k[SEL_UNROLL];
+#pragma unroll
+            for (int i = 0; i < SEL_UNROLL; ++i) {
+              const int v = v0 + i * NT;
+              k[i] = order_key(L[v < a.n ? v : a.n - 1]);
+            }
+#pragma unroll
+            for (int i = 0; i < SEL_UNROLL; ++i)
+              if (v0 + i * NT < a.n && (k[i] & hmask) == (pre & hmask)) atomicAdd(&s_hist[(k[i] >> sh) & 255u], 1);
           }
           __syncthreads();
           if (wave == 0) {
@@ -318,9 +335,19 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a, OSDMulti mu) {
         kstar = pre;
       }
       // 1b. gather and sort the window's keys
-      for (int v = tid; v < a.n; v += NT) {
-        const uint32_t k = order_key(L[v]);
-        if (all || k < kstar) keys[atomicAdd(&s_cnt, 1)] = ((uint64_t)k << 32) | (uint32_t)v;
+      constexpr int SEL_UNROLL = sel_unroll<WIN>();
+      for (int v0 = tid; v0 < a.n; v0 += NT * SEL_UNROLL) {
+        uint32_t k[SEL_UNROLL];
+#pragma unroll
+        for (int i = 0; i < SEL_UNROLL; ++i) {
+          const int v = v0 + i * NT;
+          k[i] = order_key(L[v < a.n ? v : a.n - 1]);
+        }
+#pragma unroll
+        for (int i = 0; i < SEL_UNROLL; ++i) {
+          const int v = v0 + i * NT;
+          if (v < a.n && (all || k[i] < kstar)) keys[atomicAdd(&s_cnt, 1)] = ((uint64_t)k[i] << 32) | (uint32_t)v;
+        }
       }
       __syncthreads();
       n0 = s_cnt;
@@ -558,9 +585,22 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a, OSDMulti mu) {
     // WIN: a window that does not span s says nothing about H unless it is all of H
     const bool incomplete = unspanned && !whole;
     const int not_in_span = unspanned && whole;
-    if (PFX && incomplete) {
-      // the full sort decides this one
+    // the row table of a windowed shot is left all-sentinel for the next one
+    auto reset_rows = [&]() {
+      if constexpr (WIN) {
+        const uint32_t* col32 = (const uint32_t*)keys;
+        for (int j = tid; j < n0; j += NT) {
+          const int col = (int)col32[j];
+          for (int32_t k = a.col_ptr[col]; k < a.col_ptr[col + 1]; ++k)
+            __hip_atomic_store(&fpos[a.csc_row[k]], WIN_NONE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    };
+    if ((PFX || (WIN && a.retry)) && incomplete) {
+      // PFX: the full sort decides this one; WIN with a retry list (the smaller
+      // first window): the full window does
       if (tid == 0) a.retry[atomicAdd(&a.counters[4], 1)] = job;
+      reset_rows();
       __syncthreads();
       continue;
     }
@@ -695,15 +735,7 @@ __global__ void __launch_bounds__(NT) k_osd(OSDArgs a, OSDMulti mu) {
       if (a.stats && incomplete) atomicAdd((unsigned long long*)&a.stats->osd_incomplete, 1ull);
       if (a.stats && a.jobs) atomicAdd((unsigned long long*)&a.stats->osd_prefix_retry, 1ull);
     }
-    if constexpr (WIN) {
-      // leave the row table untouched for the next shot
-      const uint32_t* col32 = (const uint32_t*)keys;
-      for (int j = tid; j < n0; j += NT) {
-        const int col = (int)col32[j];
-        for (int32_t k = a.col_ptr[col]; k < a.col_ptr[col + 1]; ++k)
-          __hip_atomic_store(&fpos[a.csc_row[k]], WIN_NONE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
+    reset_rows();
     __syncthreads();
   }
 }
@@ -778,23 +810,31 @@ tmcs_status dispatch_kpt_lds(int kpt, const OSDArgs& a, int grid, size_t lds, hi
 
 bool osd_lds_basis_ok(int mw, int npad) { return mw <= 8 && npad <= 4096; }
 
-tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s) {
-  auto k = k_osd<WIN_MW, WIN_MW, WIN_KEYS / OSD_THREADS, false, OSD_THREADS, true>;
+// Windowed OSD-0 with 64 MW local rows.  The smaller window (WIN_SMALL_MW)
+// runs first and hands the shots it cannot settle to a.retry; the full one
+// (WIN_MW) decodes those (a.jobs = the retry list), timed as k_osd_retry.
+template <int MW, bool MULTI>
+tmcs_status launch_osd_win_t(const OSDArgs& a, const OSDMulti& mu, int grid, size_t lds, hipStream_t s) {
+  auto k = k_osd<MW, MW, WIN_KEYS / OSD_THREADS, false, OSD_THREADS, true, false, MULTI>;
   if (lds > 64 * 1024 && hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return fail(TMCS_EUNSUPPORTED, "OSD workspace does not fit in LDS");
-  TMCS_LAUNCH("k_osd", k, dim3(grid), dim3(OSD_THREADS), lds, s, a, OSDMulti{nullptr, 0, nullptr});
+  TMCS_LAUNCH(a.jobs ? "k_osd_retry" : "k_osd", k, dim3(grid), dim3(OSD_THREADS), lds, s, a, mu);
   return hip_check(hipGetLastError(), "k_osd launch");
 }
 
-tmcs_status launch_osd_win_multi(const OSDArgs& first, const OSDMulti& mu, int grid, size_t lds, hipStream_t s) {
+tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s, bool small) {
+  const OSDMulti none{nullptr, 0, nullptr};
+  return small ? launch_osd_win_t<WIN_SMALL_MW, false>(a, none, grid, lds, s)
+               : launch_osd_win_t<WIN_MW, false>(a, none, grid, lds, s);
+}
+
+tmcs_status launch_osd_win_multi(const OSDArgs& first, const OSDMulti& mu, int grid, size_t lds, hipStream_t s,
+                                 bool small) {
   if (mu.n < 1 || mu.n > MAX_MULTI_OSD) return fail(TMCS_EINVAL, "multi-item OSD: 1..16 items");
   if (first.npad != WIN_KEYS) return fail(TMCS_EINVAL, "multi-item OSD: windowed items only");
-  auto k = k_osd<WIN_MW, WIN_MW, WIN_KEYS / OSD_THREADS, false, OSD_THREADS, true, false, true>;
-  if (lds > 64 * 1024 && hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-    return fail(TMCS_EUNSUPPORTED, "OSD workspace does not fit in LDS");
   // the first item's arguments set the LDS layout, which every windowed item shares
-  TMCS_LAUNCH("k_osd", k, dim3(grid), dim3(OSD_THREADS), lds, s, first, mu);
-  return hip_check(hipGetLastError(), "k_osd launch");
+  return small ? launch_osd_win_t<WIN_SMALL_MW, true>(first, mu, grid, lds, s)
+               : launch_osd_win_t<WIN_MW, true>(first, mu, grid, lds, s);
 }
 
 tmcs_status dispatch_osd(int mw, int kpt, bool bl, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {

@@ -41,7 +41,7 @@ def _oracle_det(spec, shots, seed=3):
     return det, obs
 
 
-def _run_lib(tmcs, spec, shots, T, seed=3, alpha=1.0):
+def _run_lib(tmcs, spec, shots, T, seed=3, alpha=1.0, **kw):
     import torch
     c = tmcs.Circuit(spec)
     dem = tmcs.DEM(c)
@@ -56,9 +56,9 @@ def _run_lib(tmcs, spec, shots, T, seed=3, alpha=1.0):
     flags = torch.zeros(shots, dtype=torch.uint8, device="cuda")
     stats = tmcs.new_stats()
     dem.decode(det, shots, pred, max_iter=T, alpha=alpha, ehat=ehat, llr=llr, iters=iters,
-               flags=flags, stats=stats)
+               flags=flags, stats=stats, **kw)
     pred2 = torch.zeros_like(pred)
-    dem.decode(det, shots, pred2, max_iter=T, alpha=alpha)          # compacted path
+    dem.decode(det, shots, pred2, max_iter=T, alpha=alpha, **kw)          # compacted path
     torch.cuda.synchronize()
     out = dict(det=det.cpu().numpy().view(np.uint64), obs=obs.cpu().numpy().view(np.uint64),
                pred=pred.cpu().numpy().view(np.uint64), pred2=pred2.cpu().numpy().view(np.uint64),
@@ -74,6 +74,27 @@ def _run_lib(tmcs, spec, shots, T, seed=3, alpha=1.0):
 def test_decoder_parity(gpu_lib, name, spec, shots, T):
     print(f"[decoder] {name} shots={shots} T={T}", flush=True)
     r = _run_lib(gpu_lib, spec, shots, T)
+    od, synd = _check_oracle(r, spec, shots, T)
+    check_fp64(r, od, synd, T, name)
+
+
+LANES_CASES = [c for c in CASES if c[0] in ("sc3-memory", "sc5-nlcnot", "bb18-nlcnot", "bb144-memory",
+                                            "sc3-nlcnot-decoherence", "bb18-pstring16")]
+
+
+@pytest.mark.parametrize("name,spec,shots,T", LANES_CASES, ids=[c[0] for c in LANES_CASES])
+def test_lanes_kernel_parity(gpu_lib, name, spec, shots, T):
+    """BP with 64 shots per workgroup (state in device memory, lane-interleaved)
+    against the FP32 oracle: the same bits as the team kernels.  sc3-memory has
+    shots with s = 0 in the uncompacted (per-shot output) path, bb18-pstring16 two
+    observable words."""
+    print(f"[lanes] {name} shots={shots} T={T}", flush=True)
+    r = _run_lib(gpu_lib, spec, shots, T, bp_global_state=2)
+    _check_oracle(r, spec, shots, T)
+
+
+def _check_oracle(r, spec, shots, T):
+    """Every per-shot output of a decoder run equals the FP32 oracle's."""
     oc = build_circuit(spec)
     od = build_dem(oc)
     synd = unpack_bits(r["det"], shots).T
@@ -98,7 +119,10 @@ def test_decoder_parity(gpu_lib, name, spec, shots, T):
     st = r["stats"]
     assert st["shots"] == shots and st["osd"] == int(osd.sum())
     assert st["converged"] == int(conv.sum())
-    check_fp64(r, od, synd, T, name)
+    assert st["bp_iters"] == int(r["iters"].sum())
+    hist = np.bincount(np.minimum(r["iters"], 64), minlength=65)
+    assert list(st["bp_iter_hist"]) == list(hist)
+    return od, synd
 
 
 def fp64_along(f32, priors):
@@ -235,7 +259,8 @@ def test_decoder_launch_shape_invariance(gpu_lib, name, spec, shots):
     ref = None
     for kw in (dict(), dict(bp_threads=64, bp_per_cu=2, osd_per_cu=1),
                dict(bp_threads=256, bp_per_cu=16, osd_per_cu=8), dict(bp_threads=1024, osd_per_cu=3),
-               dict(bp_global_state=1), dict(bp_global_state=1, bp_threads=128, bp_per_cu=3)):
+               dict(bp_global_state=1), dict(bp_global_state=1, bp_threads=128, bp_per_cu=3),
+               dict(bp_global_state=2), dict(bp_global_state=2, bp_sched=1, bp_per_cu=2)):
         for full in (True, False):
             pred = torch.zeros_like(obs)
             ehat = torch.zeros((shots, dem.cols), dtype=torch.uint8, device="cuda") if full else None
@@ -365,3 +390,55 @@ def test_several_decoder_passes_equal_one(gpu_lib):
         for key, v in ref.items():
             assert torch.equal(r[key], v), (chunk, key)
         assert s == st and s2 == st, chunk
+
+
+@pytest.mark.parametrize("T,weighted", [(30, False), (1, False), (2, True), (20, True)],
+                         ids=["T30", "T1", "T2-weighted", "T20-weighted"])
+def test_lanes_kernel_refills_lanes(gpu_lib, T, weighted):
+    """More shots than lanes in flight (256 workgroups x 64 lanes): lanes whose
+    shot ends take the next one while the others go on, so lanes of one
+    workgroup run different iterations (and, with per-iteration weights,
+    different weight rows).  Every per-shot output and the prediction equal the
+    team kernel's with its state in LDS, in the per-shot output path and in
+    the compacted one; T = 1 and 2 exercise the last-iteration paths."""
+    import torch
+    spec = sc(5, NLCNOT, 5, 5, 3e-3, 2e-2)
+    shots = 40000 + 37
+    print(f"[lanes-refill] sc5-nlcnot shots={shots} T={T} weighted={weighted}", flush=True)
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    det, obs = c.alloc_outputs(shots)
+    c.sample(21, 0, 0, shots, det, obs)
+    wt = None
+    if weighted:
+        g = torch.Generator().manual_seed(5)
+        wt = (0.5 + 0.6 * torch.rand((T, dem.edges), generator=g)).cuda()
+
+    def run(full, **kw):
+        pred = torch.zeros_like(obs)
+        st = gpu_lib.new_stats()
+        out = dict()
+        if full:
+            out["llr"] = torch.zeros((shots, dem.cols), dtype=torch.float32, device="cuda")
+            out["ehat"] = torch.zeros((shots, dem.cols), dtype=torch.uint8, device="cuda")
+            out["iters"] = torch.zeros(shots, dtype=torch.int32, device="cuda")
+            out["flags"] = torch.zeros(shots, dtype=torch.uint8, device="cuda")
+        dem.decode(det, shots, pred, max_iter=T, weights=wt, stats=st, **out, **kw)
+        torch.cuda.synchronize()
+        res = {k: v.cpu().numpy() for k, v in out.items()}
+        res["pred"] = pred.cpu().numpy()
+        res["stats"] = gpu_lib.read_stats(st)
+        return res
+
+    for full in (True, False):
+        ref = run(full)
+        for kw in (dict(bp_global_state=2), dict(bp_global_state=2, bp_sched=1, bp_per_cu=2)):
+            got = run(full, **kw)
+            for k in ref:
+                if k == "stats":
+                    assert got[k] == ref[k], (kw, full)
+                else:
+                    assert (got[k] == ref[k]).all(), (k, kw, full)
+    st = ref["stats"]
+    print(f"[lanes-refill] stats {st}", flush=True)
+    assert st["nontrivial"] > 16384 and st["osd"] > 0

@@ -97,3 +97,32 @@ def test_autotune_keeps_results(gpu_lib):
     assert time.perf_counter() - t0 < 0.05
     assert (cfg2.bp_threads, cfg2.bp_per_cu, cfg2.osd_per_cu, cfg2.bp_sched) == \
         (cfg.bp_threads, cfg.bp_per_cu, cfg.osd_per_cu, cfg.bp_sched)
+
+
+def test_plan_with_lanes_kernel_matches_eager(gpu_lib):
+    """Items whose BP runs in the lanes kernel (64 shots per workgroup) share one
+    multi-item launch and one state slab sized for the largest DEM; the plan's
+    counts equal eager calls with the team kernel (state in LDS), with and
+    without per-edge weights."""
+    import torch
+    specs = [sc(5, NLCNOT, 3, 3, 3e-3, 2e-2), bb("bb18", MEMORY, 3, 0, 4e-3), sc(3, NLCNOT, 3, 3, 5e-3, 2e-2)]
+    B, T = 8192, 20
+    circuits = [gpu_lib.Circuit(s) for s in specs]
+    dems = [gpu_lib.DEM(c) for c in circuits]
+    g = torch.Generator().manual_seed(23)
+    wts = (0.6 + 0.4 * torch.rand((T, dems[0].edges), generator=g)).cuda()
+    kws = [dict(weights=wts), dict(), dict()]
+    items = [(c, d, gpu_lib.make_cfg(max_iter=T, bp_global_state=2, **kw), 6, i)
+             for i, (c, d, kw) in enumerate(zip(circuits, dems, kws))]
+    plan = gpu_lib.Plan(items, B, use_graph=True)
+    plan.run(2)
+    torch.cuda.synchronize()
+    ref = [_eager(gpu_lib, c, d, 6, i, 0, 3 * B, T, **kw)
+           for i, (c, d, kw) in enumerate(zip(circuits, dems, kws))]
+    plan.run(1)
+    for i in range(len(items)):
+        r = plan.result(i)
+        print(f"[plan-lanes] item {i} {r} eager {ref[i]}", flush=True)
+        assert r["shots"] == 3 * B and r["errors"] == ref[i][0]
+        for k in ("osd", "converged", "bp_iters", "nontrivial", "bp_iter_hist"):
+            assert r[k] == ref[i][1][k], k
