@@ -229,7 +229,10 @@ typedef struct {
                                memory, one team (workgroup) per shot.  2: device memory, 64
                                shots per workgroup interleaved by lane (each wave runs one
                                record list of the Tanner graph for all 64 shots; a lane whose
-                               shot ends takes the next one).  Other values: TMCS_EINVAL */
+                               shot ends takes the next one).  3: device memory, one team per
+                               shot, one pass per iteration (L_v rebuilt per edge from the
+                               previous states of v's checks; check states double-buffered).
+                               All four give identical results.  Other values: TMCS_EINVAL */
   int32_t osd_order;        /* 0: OSD-0.  1..64: OSD-CS of this order (combination sweep,
                                Roffe et al. 2020; the paper's BP-OSD uses order 7): after the
                                full information set S, every weight-1 flip of the other

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libtmcs.so")
 
 SOURCES = [
     "host/capi.cpp", "host/codes.cpp", "host/circuit.cpp", "host/dem.cpp", "host/program.cpp", "host/timing.cpp", "host/distance.cpp",
-    "kernels/sample.hip", "kernels/decode.hip", "kernels/osd.hip", "kernels/bp_lanes.hip", "kernels/wbp.hip", "kernels/plan.hip", "kernels/distance.hip",
+    "kernels/sample.hip", "kernels/decode.hip", "kernels/osd.hip", "kernels/bp_lanes.hip", "kernels/bp_fused.hip", "kernels/wbp.hip", "kernels/plan.hip", "kernels/distance.hip",
 ]
 
 FLAGS = [

@@ -174,8 +174,8 @@ tmcs_status tmcs_decode(const tmcs_dem* d, const tmcs_decoder_cfg* cfg, const ui
   if (cfg->decode_chunk < 0 || cfg->decode_chunk % 64 != 0)
     return fail(TMCS_EINVAL, "decode_chunk must be 0 or a positive multiple of 64");
   if (cfg->bp_sched < 0 || cfg->bp_sched > 2) return fail(TMCS_EINVAL, "bp_sched must be 0, 1 or 2");
-  if (cfg->bp_global_state < 0 || cfg->bp_global_state > 2)
-    return fail(TMCS_EINVAL, "bp_global_state must be 0, 1 or 2");
+  if (cfg->bp_global_state < 0 || cfg->bp_global_state > 3)
+    return fail(TMCS_EINVAL, "bp_global_state must be 0, 1, 2 or 3");
   TMCS_TRY({
     return decode_run(d->d, *cfg, det_dev, n_shots, pred_obs_dev, stats_dev, (hipStream_t)stream);
   })

@@ -59,8 +59,12 @@ struct DecodeDevice {
   int32_t max_row_deg = 0;
   uint64_t* lone = nullptr;        // [mw] checks without edges (null: none)
   uint64_t pm_lam[MAX_OW] = {};    // observables of the hard decision of lambda
+  uint64_t pm_iso[MAX_OW] = {};    // the same over the columns without edges
   // per-lane BP schedules, one per team size used so far
-  struct Sched { int P = 0; int mode = 1; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr; };
+  struct Sched {
+    int P = 0; int mode = 1; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr;
+    int Kf = 0; int4* f = nullptr;   // single-pass records (built on first use)
+  };
   std::vector<Sched> scheds;
   // scratch
   int32_t* counters = nullptr;     // [0] queue len, [1] bp next, [2] osd len, [3] osd next
@@ -469,7 +473,7 @@ void free_device(DecodeDevice* d) {
   hipFree(d->lam); hipFree(d->obs_mask); hipFree(d->counters); hipFree(d->queue); hipFree(d->osd_queue);
   hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd); hipFree(d->gstate); hipFree(d->init); hipFree(d->sign0);
   hipFree(d->rowmap); hipFree(d->retry); hipFree(d->lone);
-  for (auto& q : d->scheds) { hipFree(q.c); hipFree(q.v); }
+  for (auto& q : d->scheds) { hipFree(q.c); hipFree(q.v); hipFree(q.f); }
   *d = DecodeDevice();
 }
 
@@ -525,7 +529,10 @@ tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
     if (D.row_ptr[c + 1] == D.row_ptr[c]) { lone[c >> 6] |= 1ull << (c & 63); any_lone = true; }
   for (int j = 0; j < D.cols; ++j)
     if (lam[j] < 0.0f)
-      for (int w = 0; w < D.obs_words && w < MAX_OW; ++w) d->pm_lam[w] ^= D.obs_mask[(size_t)j * D.obs_words + w];
+      for (int w = 0; w < D.obs_words && w < MAX_OW; ++w) {
+        d->pm_lam[w] ^= D.obs_mask[(size_t)j * D.obs_words + w];
+        if (D.col_ptr[j + 1] == D.col_ptr[j]) d->pm_iso[w] ^= D.obs_mask[(size_t)j * D.obs_words + w];
+      }
   if (any_lone && (st = upload(&d->lone, lone)) != TMCS_OK) {
     free_device(d);
     delete d;
@@ -651,6 +658,52 @@ tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevi
   return TMCS_OK;
 }
 
+// Records of the single-pass kernel for team size P: the check-pass lane lists
+// of get_sched (same assignment), two int4 per edge ([K + 2][P][2]).
+tmcs_status get_fsched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevice::Sched* out) {
+  tmcs_status st = get_sched(D, d, P, mode, out);
+  if (st != TMCS_OK) return st;
+  DecodeDevice::Sched* q = nullptr;
+  for (auto& x : d->scheds)
+    if (x.P == P && x.mode == mode) q = &x;
+  if (!q) return fail(TMCS_EDEVICE, "BP schedule cache");
+  if (q->f) { *out = *q; return TMCS_OK; }
+  std::vector<int4> cs((size_t)(q->Kc + 2) * P);
+  if (hipMemcpy(cs.data(), q->c, cs.size() * sizeof(int4), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(TMCS_EDEVICE, "hipMemcpy failed (BP schedule)");
+  // per CSR edge: its column, and where that column's entries start in CSC order
+  std::vector<int32_t> pos_in_col((size_t)std::max<int64_t>(D.edges, 1));
+  for (int v = 0; v < D.cols; ++v)
+    for (int32_t j = D.col_ptr[v]; j < D.col_ptr[v + 1]; ++j) pos_in_col[D.csc_edge[j]] = j;
+  std::vector<int4> fs((size_t)(q->Kc + 2) * P * 2);
+  for (size_t i = 0; i < cs.size(); ++i) {
+    const int4 r = cs[i];
+    int4 A = r, B = make_int4(-1, 0, 0, 0);
+    if (r.y < D.edges && r.z < D.rows) {               // (padding records keep B = degree 1, no flags)
+      const int v = r.x & R_IDX, e = r.y, c = r.z;
+      const int32_t j0 = D.col_ptr[v], deg = D.col_ptr[v + 1] - j0;
+      float lv = (float)std::log((1.0 - D.priors[v]) / D.priors[v]);
+      std::memcpy(&A.w, &lv, 4);
+      const int firstcol = D.row_idx[j0] == c ? 2 : 0;
+      if (deg == 2) {
+        const int32_t jo = pos_in_col[e] == j0 ? j0 + 1 : j0;
+        const int c2 = D.row_idx[jo];
+        B = make_int4(c2, D.csc_edge[jo], (c2 < c ? 1 : 0) | firstcol, 0);
+      } else if (deg == 1) {
+        B = make_int4(-1, 0, firstcol, 0);
+      } else {
+        B = make_int4(-2, j0, firstcol, deg);
+      }
+    }
+    fs[2 * i] = A;
+    fs[2 * i + 1] = B;
+  }
+  if ((st = upload(&q->f, fs)) != TMCS_OK) return st;
+  q->Kf = q->Kc;
+  *out = *q;
+  return TMCS_OK;
+}
+
 // The device state cached on the DEM handle (rebuilt when the device changes).
 tmcs_status ensure_device(const Dem& dc, DecodeDevice** out) {
   Dem& D = const_cast<Dem&>(dc);
@@ -688,6 +741,7 @@ struct DecodePass {
   int mw = 0;
   bool gstate = false;
   bool lanes = false;          // state in device memory, 64 shots per workgroup (bp_lanes.hip)
+  bool fused = false;          // state in device memory, one pass per iteration (bp_fused.hip)
   int P = 0, bp_grid_max = 0;
   size_t bp_lds = 0, team_bytes = 0;
   DecodeDevice::Sched sch;
@@ -696,6 +750,18 @@ struct DecodePass {
   int npad = 0, pfx_keys = 0, pfx_rank = 0, osd_grid = 0, pfx_grid = 0, win1_grid = 0, win1_rows = 0;
   size_t osd_lds = 0, pfx_lds = 0, win1_lds = 0;
 };
+
+// Expected number of detection events per shot: sum over detectors of the
+// probability that an odd number of its mechanisms fire.
+double expected_events(const Dem& D) {
+  double ev = 0.0;
+  for (int c = 0; c < D.rows; ++c) {
+    double prod = 1.0;
+    for (int32_t e = D.row_ptr[c]; e < D.row_ptr[c + 1]; ++e) prod *= 1.0 - 2.0 * D.priors[D.col_idx[e]];
+    ev += 0.5 * (1.0 - prod);
+  }
+  return ev;
+}
 
 // Workgroups of a lanes launch over ns shots: one per 64 shots, at most the
 // resident grid, and at most LANES_SLAB_MAX bytes of state in device memory.
@@ -726,8 +792,8 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   if (cfg.osd_window < 0 || cfg.osd_window > WIN_MAX_ROWS)
     return fail(TMCS_EINVAL, "osd_window must be in [0, 2048]");
   if (cfg.osd_order < 0 || cfg.osd_order > 64) return fail(TMCS_EINVAL, "osd_order must be in [0, 64]");
-  if (cfg.bp_global_state < 0 || cfg.bp_global_state > 2)
-    return fail(TMCS_EINVAL, "bp_global_state must be 0, 1 or 2");
+  if (cfg.bp_global_state < 0 || cfg.bp_global_state > 3)
+    return fail(TMCS_EINVAL, "bp_global_state must be 0, 1, 2 or 3");
   // dense OSD-0 while H fits its registers and sort, windowed beyond (or on request)
   const bool osd_win = cfg.use_osd && (cfg.osd_window > 0 || npad > OSD_MAX_KEYS || mw > 32);
   if (osd_win && cfg.osd_order > 0)
@@ -749,7 +815,10 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
     ps.team_bytes = lanes_slab_bytes(D.rows, D.cols, d->E4);
     ps.bp_grid_max = cus * std::max(1, std::min(cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 1, 2));
   }
-  const size_t team_bytes = (bp_lds + 255) & ~(size_t)255;
+  // (or one pass per iteration, on request)
+  const bool fused = gstate && !lanes && cfg.bp_global_state == 3 && D.rows > 0;
+  ps.fused = fused;
+  const size_t team_bytes = fused ? fused_team_bytes(D.rows, D.cols, d->E4) : (bp_lds + 255) & ~(size_t)255;
   // teams per CU: as many as fit in LDS; with the state in device memory, one
   // team of 16 waves (fewer slabs in flight: at d = 15..29 that was 1.2-1.7x
   // faster than 4 teams of 8 waves), unless the caller asks for another shape
@@ -768,7 +837,7 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   }
   P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
   const int sched_mode = cfg.bp_sched > 0 ? cfg.bp_sched : 1;
-  if (!lanes && (st = get_sched(D, d, P, sched_mode, &ps.sch)) != TMCS_OK) return st;
+  if (!lanes && (st = (fused ? get_fsched : get_sched)(D, d, P, sched_mode, &ps.sch)) != TMCS_OK) return st;
   if (!gstate && bp_lds > 64 * 1024 &&
       (hipFuncSetAttribute((const void*)k_bp<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
        hipFuncSetAttribute((const void*)k_bp<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
@@ -831,9 +900,15 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   // window's basis is a prefix of the larger's and every settled shot gets the
   // same correction.
   // (first window: a quarter of the full one's rows, at most WIN_SMALL_ROWS)
+  // By default the first window is used only where the expected number of
+  // detection events per shot (from the priors) is at most three quarters of
+  // its rows: on the surface-code CNOT at p = 1e-3 that is d <= 21 (327 events
+  // at d = 21: 8 instead of 24 ms per 4096 shots); at d = 29 (about 860) nearly
+  // every shot outgrew it and went to the full window anyway.  An explicit
+  // osd_window always takes both passes.
   const int user_rows = cfg.osd_window > 0 ? cfg.osd_window : WIN_MAX_ROWS;
   const int win1_rows = std::min(WIN_SMALL_ROWS, user_rows / 4);
-  const bool win2 = osd_win && win1_rows >= 2;
+  const bool win2 = osd_win && win1_rows >= 2 && (cfg.osd_window > 0 || expected_events(D) <= 0.75 * win1_rows);
   const int W1 = 2 * WIN_SMALL_MW;
   const size_t win1_lds = (size_t)WIN_KEYS * 8 + (size_t)WIN_SMALL_ROWS * 16 + (size_t)W1 * 8 + 64;
   const int win1_fit = std::max<int>(1, (int)((160 * 1024) / (win1_lds + 512)));
@@ -894,6 +969,8 @@ BPArgs bp_args(const DecodePass& ps, const uint64_t* det_unused, uint64_t* pred,
   a.gstate = d->gstate; a.team_bytes = ps.team_bytes;
   a.lone = d->lone;
   for (int w = 0; w < MAX_OW; ++w) a.pm_lam[w] = d->pm_lam[w];
+  a.fsched = ps.sch.f; a.Kf = ps.sch.Kf; a.csc_row = d->csc_row; a.csc_edge = d->csc_edge;
+  for (int w = 0; w < MAX_OW; ++w) a.pm_iso[w] = d->pm_iso[w];
   return a;
 }
 
@@ -960,6 +1037,7 @@ tmcs_status decode_bp_launch(const DecodePass& ps, const BPArgs& a, int64_t ns, 
   if (ps.lanes)
     return launch_bp_lanes(a, none, ps.cfg.weights_dev != nullptr, lanes_grid(ps.bp_grid_max, ps.team_bytes, ns),
                            stream);
+  if (ps.fused) return launch_bp_fused(a, none, ps.cfg.weights_dev != nullptr, bp_grid, ps.P, stream);
   if (ps.gstate) {
     if (ps.cfg.weights_dev) TMCS_LAUNCH("k_bp_dev", (k_bp<true, true>), dim3(bp_grid), dim3(ps.P), 0, stream, a, none);
     else TMCS_LAUNCH("k_bp_dev", (k_bp<false, true>), dim3(bp_grid), dim3(ps.P), 0, stream, a, none);
@@ -1034,7 +1112,7 @@ struct MultiDecode {
     tmcs_decode_stats* stats = nullptr;
   };
   struct BPGroup {
-    bool gstate = false, lanes = false, weighted = false;
+    bool gstate = false, lanes = false, fused = false, weighted = false;
     unsigned char* slab = nullptr;   // lanes: the state of every workgroup, shared by the group's items
     int P = 0, grid = 0;
     size_t lds = 0;
@@ -1088,12 +1166,13 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
     const DecodePass& ps = m->items[i].ps;
     MultiDecode::BPGroup* g = nullptr;
     for (auto& q : m->bp)
-      if (q.gstate == ps.gstate && q.lanes == ps.lanes && q.P == ps.P) g = &q;
+      if (q.gstate == ps.gstate && q.lanes == ps.lanes && q.fused == ps.fused && q.P == ps.P) g = &q;
     if (!g) {
       m->bp.push_back(MultiDecode::BPGroup());
       g = &m->bp.back();
       g->gstate = ps.gstate;
       g->lanes = ps.lanes;
+      g->fused = ps.fused;
       g->P = ps.P;
       g->grid = ps.bp_grid_max;
     }
@@ -1207,6 +1286,10 @@ tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream) {
     const BPArgs& a0 = g.first;
     if (g.lanes) {
       if ((st = launch_bp_lanes(a0, mu, g.weighted, grid, stream)) != TMCS_OK) return st;
+      continue;
+    }
+    if (g.fused) {
+      if ((st = launch_bp_fused(a0, mu, g.weighted, grid, g.P, stream)) != TMCS_OK) return st;
       continue;
     }
     if (g.gstate) {

@@ -99,6 +99,12 @@ struct BPArgs {
   size_t team_bytes;
   const uint64_t* lone;      // nullable [mw]: checks without edges (such a check with s_c = 1 is never satisfied)
   uint64_t pm_lam[MAX_OW];   // observables flipped by the hard decision of lambda (a shot with s = 0)
+  // single-pass kernel (bp_fused.hip)
+  const int4* fsched;        // [Kf + 2][P][2] per-lane records, two int4 per edge
+  int32_t Kf;
+  const int32_t* csc_row;    // [E] check of each CSC entry (columns of degree >= 3)
+  const int32_t* csc_edge;   // [E] CSR edge of each CSC entry
+  uint64_t pm_iso[MAX_OW];   // observables of the columns without edges whose lambda < 0
 };
 
 // Several decode items' BP queues served by one launch.
@@ -119,6 +125,15 @@ inline size_t lanes_slab_bytes(int m, int n, int E4) {
 }
 // mu.n > 0: a multi launch over mu's items (a is ignored); grid workgroups of LANES_WAVES waves.
 tmcs_status launch_bp_lanes(const BPArgs& a, const BPMulti& mu, bool weighted, int grid, hipStream_t s);
+
+// BP with one pass per iteration and its state in device memory (bp_fused.hip): a
+// team of `threads` lanes per shot, as the two-pass team kernel.
+// Device-memory bytes of one team's state: two buffers of check records, L, sign bytes.
+inline size_t fused_team_bytes(int m, int n, int E4) {
+  const size_t b = 2 * (size_t)(m + 1) * 16 + (size_t)n * 4 + (size_t)E4 + 4;
+  return (b + 255) & ~(size_t)255;
+}
+tmcs_status launch_bp_fused(const BPArgs& a, const BPMulti& mu, bool weighted, int grid, int threads, hipStream_t s);
 
 // ------------------------------------------------------------------ OSD-0
 struct OSDArgs {

@@ -82,14 +82,16 @@ LANES_CASES = [c for c in CASES if c[0] in ("sc3-memory", "sc5-nlcnot", "bb18-nl
                                             "sc3-nlcnot-decoherence", "bb18-pstring16")]
 
 
+@pytest.mark.parametrize("mode", [2, 3], ids=["lanes", "one-pass"])
 @pytest.mark.parametrize("name,spec,shots,T", LANES_CASES, ids=[c[0] for c in LANES_CASES])
-def test_lanes_kernel_parity(gpu_lib, name, spec, shots, T):
-    """BP with 64 shots per workgroup (state in device memory, lane-interleaved)
-    against the FP32 oracle: the same bits as the team kernels.  sc3-memory has
-    shots with s = 0 in the uncompacted (per-shot output) path, bb18-pstring16 two
-    observable words."""
-    print(f"[lanes] {name} shots={shots} T={T}", flush=True)
-    r = _run_lib(gpu_lib, spec, shots, T, bp_global_state=2)
+def test_device_state_kernels_parity(gpu_lib, name, spec, shots, T, mode):
+    """The device-memory BP variants against the FP32 oracle: 64 shots per
+    workgroup with lane-interleaved state (mode 2), and one team per shot with
+    one pass per iteration (mode 3, L_v rebuilt per edge).  sc3-memory has shots
+    with s = 0 in the uncompacted (per-shot output) path, bb18-pstring16 two
+    observable words, bb144-memory columns of degree 3 and more."""
+    print(f"[device-state {mode}] {name} shots={shots} T={T}", flush=True)
+    r = _run_lib(gpu_lib, spec, shots, T, bp_global_state=mode)
     _check_oracle(r, spec, shots, T)
 
 
@@ -260,7 +262,8 @@ def test_decoder_launch_shape_invariance(gpu_lib, name, spec, shots):
     for kw in (dict(), dict(bp_threads=64, bp_per_cu=2, osd_per_cu=1),
                dict(bp_threads=256, bp_per_cu=16, osd_per_cu=8), dict(bp_threads=1024, osd_per_cu=3),
                dict(bp_global_state=1), dict(bp_global_state=1, bp_threads=128, bp_per_cu=3),
-               dict(bp_global_state=2), dict(bp_global_state=2, bp_sched=1, bp_per_cu=2)):
+               dict(bp_global_state=2), dict(bp_global_state=2, bp_sched=1, bp_per_cu=2),
+               dict(bp_global_state=3), dict(bp_global_state=3, bp_threads=256, bp_per_cu=4)):
         for full in (True, False):
             pred = torch.zeros_like(obs)
             ehat = torch.zeros((shots, dem.cols), dtype=torch.uint8, device="cuda") if full else None
@@ -432,7 +435,8 @@ def test_lanes_kernel_refills_lanes(gpu_lib, T, weighted):
 
     for full in (True, False):
         ref = run(full)
-        for kw in (dict(bp_global_state=2), dict(bp_global_state=2, bp_sched=1, bp_per_cu=2)):
+        for kw in (dict(bp_global_state=2), dict(bp_global_state=2, bp_sched=1, bp_per_cu=2),
+                   dict(bp_global_state=3)):
             got = run(full, **kw)
             for k in ref:
                 if k == "stats":

@@ -104,7 +104,7 @@ def test_large_bp_and_windowed_osd(gpu_lib, name, shots):
     # the state placements and lane schedules give the same bits
     for kw in (dict(bp_global_state=0), dict(bp_global_state=1, bp_sched=2),
                dict(bp_global_state=1, bp_threads=512, bp_per_cu=2, bp_sched=1),
-               dict(bp_global_state=2), dict(bp_global_state=2, bp_sched=1)):
+               dict(bp_global_state=2), dict(bp_global_state=2, bp_sched=1), dict(bp_global_state=3)):
         other = run(False, **kw)
         assert (other["llr"] == bp["llr"]).all() and (other["iters"] == bp["iters"]).all(), kw
     r = decode_bp(H, priors, d_or.T, T, dtype=np.float32)

@@ -99,11 +99,12 @@ def test_autotune_keeps_results(gpu_lib):
         (cfg.bp_threads, cfg.bp_per_cu, cfg.osd_per_cu, cfg.bp_sched)
 
 
-def test_plan_with_lanes_kernel_matches_eager(gpu_lib):
-    """Items whose BP runs in the lanes kernel (64 shots per workgroup) share one
-    multi-item launch and one state slab sized for the largest DEM; the plan's
-    counts equal eager calls with the team kernel (state in LDS), with and
-    without per-edge weights."""
+@pytest.mark.parametrize("mode", [2, 3], ids=["lanes", "one-pass"])
+def test_plan_with_device_state_kernels_matches_eager(gpu_lib, mode):
+    """Items whose BP state lives in device memory (mode 2: 64 shots per
+    workgroup sharing one slab sized for the largest DEM; mode 3: one pass per
+    iteration) share one multi-item launch; the plan's counts equal eager calls
+    with the team kernel (state in LDS), with and without per-edge weights."""
     import torch
     specs = [sc(5, NLCNOT, 3, 3, 3e-3, 2e-2), bb("bb18", MEMORY, 3, 0, 4e-3), sc(3, NLCNOT, 3, 3, 5e-3, 2e-2)]
     B, T = 8192, 20
@@ -112,7 +113,7 @@ def test_plan_with_lanes_kernel_matches_eager(gpu_lib):
     g = torch.Generator().manual_seed(23)
     wts = (0.6 + 0.4 * torch.rand((T, dems[0].edges), generator=g)).cuda()
     kws = [dict(weights=wts), dict(), dict()]
-    items = [(c, d, gpu_lib.make_cfg(max_iter=T, bp_global_state=2, **kw), 6, i)
+    items = [(c, d, gpu_lib.make_cfg(max_iter=T, bp_global_state=mode, **kw), 6, i)
              for i, (c, d, kw) in enumerate(zip(circuits, dems, kws))]
     plan = gpu_lib.Plan(items, B, use_graph=True)
     plan.run(2)
@@ -122,7 +123,7 @@ def test_plan_with_lanes_kernel_matches_eager(gpu_lib):
     plan.run(1)
     for i in range(len(items)):
         r = plan.result(i)
-        print(f"[plan-lanes] item {i} {r} eager {ref[i]}", flush=True)
+        print(f"[plan-device-state {mode}] item {i} {r} eager {ref[i]}", flush=True)
         assert r["shots"] == 3 * B and r["errors"] == ref[i][0]
         for k in ("osd", "converged", "bp_iters", "nontrivial", "bp_iter_hist"):
             assert r[k] == ref[i][1][k], k
