@@ -52,6 +52,12 @@ EVENT_APPLY_OPS = 4
 # they were taken on: the SHA-256 of those files, in order, must match.
 # Commands and raw figures: profiles/hbm_traffic_*.md
 TRAFFIC = {
+    "sc_nlcnot_mixed": {
+        # one multi-item launch per step (every instance whose BP state is in device memory)
+        "k_bp_dev": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
+                     "sha256": "ff9f06465fb3f07b7ee6cb70cf1894e556f6c21ab2aa78cd6d294af63c4ad83a",
+                     "fetch_kib": 1401346850.2, "write_kib": 642598028.9},
+    },
     "sc5_nlcnot": {
         "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
                  "sha256": "03be1640d29e262e7fa79b55d7c89ae35d2a88b8fc854330c6b0d2413b9f1bfa",
