@@ -55,6 +55,7 @@ struct DecodeDevice {
   uint64_t* obs_mask = nullptr;
   int4* init = nullptr;            // [m] BP check state of iteration 1
   uint32_t* sign0 = nullptr;       // [E4 / 4] sign bytes of iteration 1
+  int4* init_pk = nullptr;         // [m] packed check state of iteration 1 (every check <= PK_MAX_DEG edges)
   int32_t E4 = 0;
   int32_t max_row_deg = 0;
   uint64_t* lone = nullptr;        // [mw] checks without edges (null: none)
@@ -206,6 +207,12 @@ __global__ void __launch_bounds__(256) k_compact_wide(const uint64_t* __restrict
 // rebuilt from it: m_{c->v} = (-1)^{s_c + parity + sgn q_e} alpha_t(e) *
 // (e == argmin ? n2 : n1).
 //
+// PK (every check of at most PK_MAX_DEG edges): no sign bytes.  A check
+// record's last word holds s_c (bit 1) and the sign of the message to its j-th
+// edge (bit 2 + j); the check pass collects the new signs in a register and
+// writes them with the record, and both passes read a message's sign from the
+// record they already load.  Results are the same.
+//
 // Iteration 1 needs no check pass: with q_{v->c} = lambda_v its state depends
 // on the DEM alone (precomputed, plus the syndrome bit).  Iteration t is then a
 // variable pass (L^t) followed by a check pass that tests H [L^t < 0] = s and,
@@ -222,13 +229,13 @@ __global__ void __launch_bounds__(256) k_compact_wide(const uint64_t* __restrict
 // team switches at most once per item; its statistics go to the item they
 // belong to.  Weights are then per item (weights may be null: scalar alpha).
 
-template <bool WEIGHTED, bool GSTATE, bool MULTI = false>
+template <bool WEIGHTED, bool GSTATE, bool MULTI, bool PK>
 __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
   extern __shared__ __align__(16) unsigned char sm[];
   unsigned char* base = nullptr;
   float4* state = nullptr;                            // [m + 1] (slot m: padding records)
   float* L = nullptr;                                 // [n]
-  uint8_t* sgn = nullptr;                             // [E4 + 4] (byte E4: padding records)
+  uint8_t* sgn = nullptr;                             // [E4 + 4] (byte E4: padding records); !PK only
   auto bind = [&]() {
     base = GSTATE ? a.gstate + (size_t)blockIdx.x * a.team_bytes : sm;
     state = (float4*)base;
@@ -308,15 +315,17 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
       const uint64_t* sy = a.synd + ls * a.mw;
       int fl = 0;
       for (int c = tid; c < a.m; c += P) {
-        int4 s0 = a.init[c];
+        int4 s0 = PK ? a.init_pk[c] : a.init[c];
         const int sb = (int)((sy[c >> 6] >> (c & 63)) & 1ull);
         fl |= sb | ((s0.z < 0 && sb) ? 2 : 0);   // bit 1: a check without edges can never be satisfied
-        s0.w |= sb << 1;
+        if (PK) s0.w ^= sb ? (int)0xFFFFFFFEu : 0;   // s_c = 1 flips every message sign
+        else s0.w |= sb << 1;
         state[c] = make_float4(__int_as_float(s0.x), __int_as_float(s0.y), __int_as_float(s0.z),
                                __int_as_float(s0.w));
       }
       for (int v = tid; v < a.n; v += P) L[v] = a.lam[v];
-      for (int i = tid; i < (a.E4 >> 2); i += P) ((uint32_t*)sgn)[i] = a.sign0[i];
+      if (!PK)
+        for (int i = tid; i < (a.E4 >> 2); i += P) ((uint32_t*)sgn)[i] = a.sign0[i];
       if (fl) atomicOr(&s_flag, fl);
     }
     __syncthreads();
@@ -333,12 +342,14 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           auto vstep = [&](const int4 r) {
             const int v = r.x & R_IDX, e = r.y, c = r.z;
             const float4 s = state[c];
-            const int se = sgn[e];
             const float at = use_w ? wt[e < a.E32 ? e : 0] : a.alpha;
             const float mag = __fmul_rn(at, e == __float_as_int(s.z) ? s.y : s.x);
             const int fl = __float_as_int(s.w);
             const float base = (r.x & R_FIRST) ? __int_as_float(r.w) : acc;   // lambda_v on a column's first edge
-            acc = __fadd_rn(base, (((fl >> 1) ^ fl ^ se) & 1) ? -mag : mag);
+            int neg;
+            if constexpr (PK) neg = (fl >> ((r.x >> R_SH) & 31)) & 1;
+            else neg = ((fl >> 1) ^ fl ^ sgn[e]) & 1;
+            acc = __fadd_rn(base, neg ? -mag : mag);
             if (r.x & R_LAST) L[v] = acc;
           };
           // records are read two steps ahead; the schedule holds two rows of
@@ -360,6 +371,7 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           const float* wo = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;   // weights of the messages m^t
           float n1o = 0.0f, n2o = 0.0f, n1 = BP_BIG, n2 = BP_BIG;
           int nago = -1, nag = -1, sc = 0, spo = 0, npar = 0, hard = 0;
+          int flo = 0, nbits = 0;                        // PK: the old record's word, the new message signs
           auto cstep = [&](const int4 r) {
             const int v = r.x & R_IDX, e = r.y, c = r.z;
             const bool first = (r.x & R_FIRST) != 0;
@@ -372,9 +384,9 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
               nago = __float_as_int(s.z);
               sc = (fl >> 1) & 1;
               spo = fl & 1;
+              flo = fl;
             }
             const float Lv = L[v];
-            const int se = sgn[e];
             n1 = first ? BP_BIG : n1;
             n2 = first ? BP_BIG : n2;
             nag = first ? -1 : nag;
@@ -383,7 +395,14 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
             if (update) {
               const float ao = use_w ? wo[e < a.E32 ? e : 0] : a.alpha;
               const float mag = __fmul_rn(ao, e == nago ? n2o : n1o);
-              const float q = __fsub_rn(Lv, (sc ^ spo ^ se) ? -mag : mag);   // q = L_v - m_old
+              int sh = 0, neg;
+              if constexpr (PK) {
+                sh = (r.x >> R_SH) & 31;
+                neg = (flo >> sh) & 1;
+              } else {
+                neg = sc ^ spo ^ sgn[e];
+              }
+              const float q = __fsub_rn(Lv, neg ? -mag : mag);   // q = L_v - m_old
               const float aq = fabsf(q);
               const int ng = q < 0.0f ? 1 : 0;
               const bool lt1 = aq < n1, lt2 = aq < n2;
@@ -391,12 +410,17 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
               n1 = lt1 ? aq : n1;
               nag = lt1 ? e : nag;
               npar ^= ng;
-              sgn[e] = (uint8_t)ng;
+              if constexpr (PK) nbits = (first ? 0 : nbits) | (ng << sh);
+              else sgn[e] = (uint8_t)ng;
             }
             if (r.x & R_LAST) {
               unsat |= hard != sc;
-              if (update)
-                state[c] = make_float4(n1, n2, __int_as_float(nag), __int_as_float((sc << 1) | npar));
+              if (update) {
+                // PK: message sign of edge j = s_c + parity + sgn q_j (mod 2)
+                const int w = PK ? ((sc << 1) | ((nbits ^ ((sc ^ npar) ? (int)0xFFFFFFFCu : 0)) & (int)0xFFFFFFFCu))
+                                 : ((sc << 1) | npar);
+                state[c] = make_float4(n1, n2, __int_as_float(nag), __int_as_float(w));
+              }
             }
           };
           const int4* rp = a.csched + tid;
@@ -472,6 +496,7 @@ void free_device(DecodeDevice* d) {
   hipFree(d->row_ptr); hipFree(d->col_idx); hipFree(d->col_ptr); hipFree(d->csc_row); hipFree(d->csc_edge);
   hipFree(d->lam); hipFree(d->obs_mask); hipFree(d->counters); hipFree(d->queue); hipFree(d->osd_queue);
   hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd); hipFree(d->gstate); hipFree(d->init); hipFree(d->sign0);
+  hipFree(d->init_pk);
   hipFree(d->rowmap); hipFree(d->retry); hipFree(d->lone);
   for (auto& q : d->scheds) { hipFree(q.c); hipFree(q.v); hipFree(q.f); }
   *d = DecodeDevice();
@@ -498,7 +523,7 @@ tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
   }
   // iteration 1 of BP has q_{v->c} = lambda_v: its check state and edge signs
   // follow from the DEM alone (same FP32 comparisons as the check pass)
-  std::vector<int4> init(std::max(D.rows, 0));
+  std::vector<int4> init(std::max(D.rows, 0)), init_pk(std::max(D.rows, 0));
   d->E4 = (int32_t)((D.edges + 3) & ~3ll);
   std::vector<uint8_t> sg((size_t)d->E4, 0);
   for (int c = 0; c < D.rows; ++c) {
@@ -520,6 +545,12 @@ tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
     r.w = npar;
     init[c] = r;
     d->max_row_deg = std::max(d->max_row_deg, D.row_ptr[c + 1] - D.row_ptr[c]);
+    // packed: the sign of the message to the j-th edge in bit 2 + j (s_c = 0)
+    uint32_t pw = 0;
+    for (int32_t e = D.row_ptr[c]; e < D.row_ptr[c + 1] && e - D.row_ptr[c] < PK_MAX_DEG; ++e)
+      pw |= (uint32_t)(npar ^ sg[e]) << (2 + e - D.row_ptr[c]);
+    r.w = (int32_t)pw;
+    init_pk[c] = r;
   }
   // checks without edges (a shot with such a detection event never satisfies
   // H e = s) and the observables flipped by the hard decision of lambda alone
@@ -540,7 +571,8 @@ tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
   }
   std::vector<uint32_t> sg32((size_t)d->E4 / 4);
   if (!sg32.empty()) std::memcpy(sg32.data(), sg.data(), sg.size());
-  if ((st = upload(&d->init, init)) != TMCS_OK || (st = upload(&d->sign0, sg32)) != TMCS_OK) {
+  if ((st = upload(&d->init, init)) != TMCS_OK || (st = upload(&d->sign0, sg32)) != TMCS_OK ||
+      (d->max_row_deg <= PK_MAX_DEG && D.cols <= R_IDX && (st = upload(&d->init_pk, init_pk)) != TMCS_OK)) {
     free_device(d);
     delete d;
     return st;
@@ -606,6 +638,9 @@ int strided_assign(const std::vector<int>& size, int P, std::vector<std::vector<
 // stored contiguously ([P][K + LANES_UNROLL]): their length is a multiple of
 // LANES_UNROLL, followed by LANES_UNROLL records of padding.  Team lists are
 // interleaved ([K + 2][P]): even length, two rows of padding.
+// Record bits of an edge's position j within its check (packed check state).
+int32_t pos_bits(int32_t j) { return j < PK_MAX_DEG ? (2 + j) << R_SH : 0; }
+
 tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevice::Sched* out) {
   for (const auto& q : d->scheds)
     if (q.P == P && q.mode == mode) { *out = q; return TMCS_OK; }
@@ -629,7 +664,7 @@ tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevi
     int k = 0;
     for (int c : lanes[l])
       for (int32_t e = D.row_ptr[c]; e < D.row_ptr[c + 1]; ++e, ++k) {
-        int32_t x = D.col_idx[e];
+        int32_t x = D.col_idx[e] | pos_bits(e - D.row_ptr[c]);
         if (e == D.row_ptr[c]) x |= R_FIRST;
         if (e == D.row_ptr[c + 1] - 1) x |= R_LAST;
         cs[P < 64 ? (size_t)l * (q.Kc + kb) + k : (size_t)k * P + l] = make_int4(x, e, c, 0);
@@ -641,7 +676,7 @@ tmcs_status get_sched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevi
     int k = 0;
     for (int v : lanes[l])
       for (int32_t j = D.col_ptr[v]; j < D.col_ptr[v + 1]; ++j, ++k) {
-        int32_t x = v;
+        int32_t x = v | pos_bits(D.csc_edge[j] - D.row_ptr[D.row_idx[j]]);
         if (j == D.col_ptr[v]) x |= R_FIRST;
         if (j == D.col_ptr[v + 1] - 1) x |= R_LAST;
         float lv = (float)std::log((1.0 - D.priors[v]) / D.priors[v]);
@@ -727,6 +762,41 @@ int device_cus() {
 }
 
 
+// Dynamic LDS beyond 64 KB for every LDS-state variant of k_bp.
+bool bp_lds_allow(size_t lds) {
+  const void* f[] = {(const void*)k_bp<false, false, false, false>, (const void*)k_bp<true, false, false, false>,
+                     (const void*)k_bp<false, false, true, false>,  (const void*)k_bp<true, false, true, false>,
+                     (const void*)k_bp<false, false, false, true>,  (const void*)k_bp<true, false, false, true>,
+                     (const void*)k_bp<false, false, true, true>,   (const void*)k_bp<true, false, true, true>};
+  for (const void* p : f)
+    if (hipFuncSetAttribute(p, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return false;
+  return true;
+}
+
+// Launch of the team kernel variant (state in LDS: "k_bp", in device memory: "k_bp_dev").
+template <bool MULTI>
+void launch_k_bp(bool weighted, bool gstate, bool pk, int grid, int P, size_t lds, hipStream_t stream,
+                 const BPArgs& a, const BPMulti& mu) {
+  const dim3 g((unsigned)grid), b((unsigned)P);
+  if (gstate) {
+    if (pk) {
+      if (weighted) TMCS_LAUNCH("k_bp_dev", (k_bp<true, true, MULTI, true>), g, b, 0, stream, a, mu);
+      else TMCS_LAUNCH("k_bp_dev", (k_bp<false, true, MULTI, true>), g, b, 0, stream, a, mu);
+    } else {
+      if (weighted) TMCS_LAUNCH("k_bp_dev", (k_bp<true, true, MULTI, false>), g, b, 0, stream, a, mu);
+      else TMCS_LAUNCH("k_bp_dev", (k_bp<false, true, MULTI, false>), g, b, 0, stream, a, mu);
+    }
+  } else {
+    if (pk) {
+      if (weighted) TMCS_LAUNCH("k_bp", (k_bp<true, false, MULTI, true>), g, b, lds, stream, a, mu);
+      else TMCS_LAUNCH("k_bp", (k_bp<false, false, MULTI, true>), g, b, lds, stream, a, mu);
+    } else {
+      if (weighted) TMCS_LAUNCH("k_bp", (k_bp<true, false, MULTI, false>), g, b, lds, stream, a, mu);
+      else TMCS_LAUNCH("k_bp", (k_bp<false, false, MULTI, false>), g, b, lds, stream, a, mu);
+    }
+  }
+}
+
 constexpr int64_t DECODE_CHUNK_MIN = 4096;
 
 // Everything one decoder pass needs: launch shapes, scratch and the kernel
@@ -742,6 +812,7 @@ struct DecodePass {
   bool gstate = false;
   bool lanes = false;          // state in device memory, 64 shots per workgroup (bp_lanes.hip)
   bool fused = false;          // state in device memory, one pass per iteration (bp_fused.hip)
+  bool pk = false;             // team kernel with the packed check state (no sign bytes)
   int P = 0, bp_grid_max = 0;
   size_t bp_lds = 0, team_bytes = 0;
   DecodeDevice::Sched sch;
@@ -794,13 +865,16 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   if (cfg.osd_order < 0 || cfg.osd_order > 64) return fail(TMCS_EINVAL, "osd_order must be in [0, 64]");
   if (cfg.bp_global_state < 0 || cfg.bp_global_state > 3)
     return fail(TMCS_EINVAL, "bp_global_state must be 0, 1, 2 or 3");
+  if (D.cols > R_IDX || D.rows > R_IDX) return fail(TMCS_EUNSUPPORTED, "BP: more than 2^25 - 1 columns or detectors");
   // dense OSD-0 while H fits its registers and sort, windowed beyond (or on request)
   const bool osd_win = cfg.use_osd && (cfg.osd_window > 0 || npad > OSD_MAX_KEYS || mw > 32);
   if (osd_win && cfg.osd_order > 0)
     return fail(TMCS_EUNSUPPORTED, "OSD-CS needs the dense elimination (<= 2048 detectors, <= 16384 columns)");
   const int cus = device_cus();
   // BP launch shape: one team (workgroup) per shot in flight, state in LDS
-  const size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (size_t)d->E4 + 4;
+  // (the packed check state needs no sign bytes; the other kernels keep them)
+  const bool pk_ok = d->init_pk != nullptr && cfg.bp_global_state <= 1;
+  const size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (pk_ok ? 0 : (size_t)d->E4 + 4);
   const bool gstate = cfg.bp_global_state != 0 || bp_lds > 160 * 1024;
   // state in device memory: one team per shot, or on request 64 shots per
   // workgroup in the lanes of its waves (on the surface-code NL-CNOT at d = 15..29
@@ -838,13 +912,10 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
   const int sched_mode = cfg.bp_sched > 0 ? cfg.bp_sched : 1;
   if (!lanes && (st = (fused ? get_fsched : get_sched)(D, d, P, sched_mode, &ps.sch)) != TMCS_OK) return st;
-  if (!gstate && bp_lds > 64 * 1024 &&
-      (hipFuncSetAttribute((const void*)k_bp<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
-       hipFuncSetAttribute((const void*)k_bp<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess ||
-       hipFuncSetAttribute((const void*)k_bp<true, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bp_lds) != hipSuccess))
-    return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
+  if (!gstate && bp_lds > 64 * 1024 && !bp_lds_allow(bp_lds)) return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
   const int per_cu = std::max(1, std::min({team_fit, 32 / (P / 64), cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 32}));
   ps.gstate = gstate;
+  ps.pk = pk_ok && !lanes && !fused;
   ps.bp_lds = bp_lds;
   if (!lanes) {
     ps.P = P;
@@ -958,6 +1029,7 @@ BPArgs bp_args(const DecodePass& ps, const uint64_t* det_unused, uint64_t* pred,
   const tmcs_decoder_cfg& cfg = ps.cfg;
   BPArgs a;
   a.csched = ps.sch.c; a.vsched = ps.sch.v; a.Kc = ps.sch.Kc; a.Kv = ps.sch.Kv; a.init = d->init; a.sign0 = d->sign0;
+  a.init_pk = d->init_pk;
   a.lam = d->lam; a.obs_mask = d->obs_mask; a.ow = D.obs_words;
   a.m = D.rows; a.n = D.cols; a.E = D.edges; a.E32 = (int32_t)D.edges; a.E4 = d->E4; a.T = cfg.max_iter; a.alpha = cfg.alpha;
   a.w = cfg.weights_dev;
@@ -1038,13 +1110,8 @@ tmcs_status decode_bp_launch(const DecodePass& ps, const BPArgs& a, int64_t ns, 
     return launch_bp_lanes(a, none, ps.cfg.weights_dev != nullptr, lanes_grid(ps.bp_grid_max, ps.team_bytes, ns),
                            stream);
   if (ps.fused) return launch_bp_fused(a, none, ps.cfg.weights_dev != nullptr, bp_grid, ps.P, stream);
-  if (ps.gstate) {
-    if (ps.cfg.weights_dev) TMCS_LAUNCH("k_bp_dev", (k_bp<true, true>), dim3(bp_grid), dim3(ps.P), 0, stream, a, none);
-    else TMCS_LAUNCH("k_bp_dev", (k_bp<false, true>), dim3(bp_grid), dim3(ps.P), 0, stream, a, none);
-  } else {
-    if (ps.cfg.weights_dev) TMCS_LAUNCH("k_bp", (k_bp<true, false>), dim3(bp_grid), dim3(ps.P), ps.bp_lds, stream, a, none);
-    else TMCS_LAUNCH("k_bp", (k_bp<false, false>), dim3(bp_grid), dim3(ps.P), ps.bp_lds, stream, a, none);
-  }
+  launch_k_bp<false>(ps.cfg.weights_dev != nullptr, ps.gstate, ps.pk, bp_grid, ps.P, ps.gstate ? 0 : ps.bp_lds, stream,
+                     a, none);
   return hip_check(hipGetLastError(), "k_bp launch");
 }
 
@@ -1112,7 +1179,7 @@ struct MultiDecode {
     tmcs_decode_stats* stats = nullptr;
   };
   struct BPGroup {
-    bool gstate = false, lanes = false, fused = false, weighted = false;
+    bool gstate = false, lanes = false, fused = false, pk = false, weighted = false;
     unsigned char* slab = nullptr;   // lanes: the state of every workgroup, shared by the group's items
     int P = 0, grid = 0;
     size_t lds = 0;
@@ -1166,13 +1233,14 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
     const DecodePass& ps = m->items[i].ps;
     MultiDecode::BPGroup* g = nullptr;
     for (auto& q : m->bp)
-      if (q.gstate == ps.gstate && q.lanes == ps.lanes && q.fused == ps.fused && q.P == ps.P) g = &q;
+      if (q.gstate == ps.gstate && q.lanes == ps.lanes && q.fused == ps.fused && q.pk == ps.pk && q.P == ps.P) g = &q;
     if (!g) {
       m->bp.push_back(MultiDecode::BPGroup());
       g = &m->bp.back();
       g->gstate = ps.gstate;
       g->lanes = ps.lanes;
       g->fused = ps.fused;
+      g->pk = ps.pk;
       g->P = ps.P;
       g->grid = ps.bp_grid_max;
     }
@@ -1187,9 +1255,7 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
       // teams resident per CU with the largest state of the group
       const int fit = std::max(1, std::min((int)((160 * 1024) / (g.lds + 1024)), 32 / (g.P / 64)));
       g.grid = std::min(g.grid, cus * fit);
-      if (g.lds > 64 * 1024 &&
-          (hipFuncSetAttribute((const void*)k_bp<false, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds) != hipSuccess ||
-           hipFuncSetAttribute((const void*)k_bp<true, false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds) != hipSuccess)) {
+      if (g.lds > 64 * 1024 && !bp_lds_allow(g.lds)) {
         decode_multi_free(m);
         return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
       }
@@ -1292,13 +1358,7 @@ tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream) {
       if ((st = launch_bp_fused(a0, mu, g.weighted, grid, g.P, stream)) != TMCS_OK) return st;
       continue;
     }
-    if (g.gstate) {
-      if (g.weighted) TMCS_LAUNCH("k_bp_dev", (k_bp<true, true, true>), dim3(grid), dim3(g.P), 0, stream, a0, mu);
-      else TMCS_LAUNCH("k_bp_dev", (k_bp<false, true, true>), dim3(grid), dim3(g.P), 0, stream, a0, mu);
-    } else {
-      if (g.weighted) TMCS_LAUNCH("k_bp", (k_bp<true, false, true>), dim3(grid), dim3(g.P), g.lds, stream, a0, mu);
-      else TMCS_LAUNCH("k_bp", (k_bp<false, false, true>), dim3(grid), dim3(g.P), g.lds, stream, a0, mu);
-    }
+    launch_k_bp<true>(g.weighted, g.gstate, g.pk, grid, g.P, g.gstate ? 0 : g.lds, stream, a0, mu);
     if ((st = hip_check(hipGetLastError(), "k_bp launch")) != TMCS_OK) return st;
   }
   if (!m->osd_win_items.empty()) {

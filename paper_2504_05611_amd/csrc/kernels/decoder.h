@@ -56,17 +56,26 @@ __device__ __forceinline__ uint64_t block_xor_u64(uint64_t v, uint64_t* scratch)
 //               consecutive in one lane, in CSR order)
 //   var pass:   x = v | flags, y = CSR edge e, z = check c, w = lambda_v bits
 //               (entries of a column are consecutive in one lane, in CSC order)
+//   both:       bits R_SH.. of x = 2 + the edge's position within its check
+//               (0 where the check has more than PK_MAX_DEG edges)
 // A team kernel gives every lane its own record list; the lanes kernel gives
 // every wave one.
 constexpr int32_t R_FIRST = 1 << 30;    // first edge of its check / column
 constexpr int32_t R_LAST = (int32_t)(1u << 31);
-constexpr int32_t R_IDX = (1 << 30) - 1;
+constexpr int32_t R_SH = 25;
+constexpr int32_t R_IDX = (1 << R_SH) - 1;
+// Packed check state (team kernel, checks of at most PK_MAX_DEG edges): the
+// last word of a check record holds s_c in bit 1 and, in bit 2 + j, the sign
+// of the message to the check's j-th edge (s_c + sign parity + sgn q_e mod 2),
+// so no per-edge sign byte is stored.
+constexpr int PK_MAX_DEG = 30;
 
 struct BPArgs {
   const int4* csched;        // [Kc][P] check-pass records
   const int4* vsched;        // [Kv][P] variable-pass records
   int32_t Kc, Kv;
   const int4* init;          // [m] check state of iteration 1 (n1, n2 bits, argmin edge, sign parity)
+  const int4* init_pk;       // [m] the same in the packed layout (message signs, s_c = 0); null if not built
   const uint32_t* sign0;     // [E4 / 4] sign bytes of q at iteration 1
   const float* lam;
   const uint64_t* obs_mask;  // [ow][n]
