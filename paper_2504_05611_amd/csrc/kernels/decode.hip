@@ -55,7 +55,7 @@ struct DecodeDevice {
   uint64_t* obs_mask = nullptr;
   int4* init = nullptr;            // [m] BP check state of iteration 1
   uint32_t* sign0 = nullptr;       // [E4 / 4] sign bytes of iteration 1
-  int4* init_pk = nullptr;         // [m] packed check state of iteration 1 (every check <= PK_MAX_DEG edges)
+  std::vector<int4> init_pk;       // host [m] packed check state of iteration 1 (empty: a check has > PK_MAX_DEG edges)
   int32_t E4 = 0;
   int32_t max_row_deg = 0;
   uint64_t* lone = nullptr;        // [mw] checks without edges (null: none)
@@ -65,6 +65,11 @@ struct DecodeDevice {
   struct Sched {
     int P = 0; int mode = 1; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr;
     int Kf = 0; int4* f = nullptr;   // single-pass records (built on first use)
+    // packed-state team kernel (built on first use)
+    int2 *pc = nullptr, *pv = nullptr;
+    int32_t *pce = nullptr, *pve = nullptr, *vmap = nullptr, *corig = nullptr;
+    int4* pinit = nullptr;
+    int32_t Mpk = 0, Npk = 0;
   };
   std::vector<Sched> scheds;
   // scratch
@@ -211,7 +216,11 @@ __global__ void __launch_bounds__(256) k_compact_wide(const uint64_t* __restrict
 // record's last word holds s_c (bit 1) and the sign of the message to its j-th
 // edge (bit 2 + j); the check pass collects the new signs in a register and
 // writes them with the record, and both passes read a message's sign from the
-// record they already load.  Results are the same.
+// record they already load.  The argmin edge is kept as 2 + its position.
+// Checks and columns are renumbered (c', v': the state and L slots in the
+// order the lanes reach them) and the schedules hold 8-byte records, half the
+// schedule bytes a team streams per iteration; the CSR edge of a record (for
+// per-edge weights) comes from arrays of its own.  Results are the same.
 //
 // Iteration 1 needs no check pass: with q_{v->c} = lambda_v its state depends
 // on the DEM alone (precomputed, plus the syndrome bit).  Iteration t is then a
@@ -233,13 +242,13 @@ template <bool WEIGHTED, bool GSTATE, bool MULTI, bool PK>
 __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
   extern __shared__ __align__(16) unsigned char sm[];
   unsigned char* base = nullptr;
-  float4* state = nullptr;                            // [m + 1] (slot m: padding records)
-  float* L = nullptr;                                 // [n]
+  float4* state = nullptr;                            // [m + 1] (slot m: padding records); PK: [Mpk + 1]
+  float* L = nullptr;                                 // [n]; PK: [Npk + 1]
   uint8_t* sgn = nullptr;                             // [E4 + 4] (byte E4: padding records); !PK only
   auto bind = [&]() {
     base = GSTATE ? a.gstate + (size_t)blockIdx.x * a.team_bytes : sm;
     state = (float4*)base;
-    L = (float*)(state + a.m + 1);
+    L = (float*)(state + (PK ? a.Mpk : a.m) + 1);
     sgn = (uint8_t*)(L + a.n);
   };
   __shared__ int s_job, s_flag, s_pos, s_inst;
@@ -314,18 +323,33 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
     {
       const uint64_t* sy = a.synd + ls * a.mw;
       int fl = 0;
-      for (int c = tid; c < a.m; c += P) {
-        int4 s0 = PK ? a.init_pk[c] : a.init[c];
-        const int sb = (int)((sy[c >> 6] >> (c & 63)) & 1ull);
-        fl |= sb | ((s0.z < 0 && sb) ? 2 : 0);   // bit 1: a check without edges can never be satisfied
-        if (PK) s0.w ^= sb ? (int)0xFFFFFFFEu : 0;   // s_c = 1 flips every message sign
-        else s0.w |= sb << 1;
-        state[c] = make_float4(__int_as_float(s0.x), __int_as_float(s0.y), __int_as_float(s0.z),
-                               __int_as_float(s0.w));
-      }
-      for (int v = tid; v < a.n; v += P) L[v] = a.lam[v];
-      if (!PK)
+      if constexpr (PK) {
+        // (L needs no start value: the variable pass writes every slot the check pass reads)
+        for (int c = tid; c < a.Mpk; c += P) {
+          int4 s0 = a.pinit[c];
+          const int co = a.corig[c];
+          const int sb = (int)((sy[co >> 6] >> (co & 63)) & 1ull);
+          fl |= sb;
+          s0.w ^= sb ? (int)0xFFFFFFFEu : 0;   // s_c = 1 flips every message sign
+          state[c] = make_float4(__int_as_float(s0.x), __int_as_float(s0.y), __int_as_float(s0.z),
+                                 __int_as_float(s0.w));
+        }
+        // a detection event on a check without edges: never satisfied
+        if (a.lone)
+          for (int w = tid; w < a.mw; w += P)
+            if (sy[w] & a.lone[w]) fl |= 3;
+      } else {
+        for (int c = tid; c < a.m; c += P) {
+          int4 s0 = a.init[c];
+          const int sb = (int)((sy[c >> 6] >> (c & 63)) & 1ull);
+          fl |= sb | ((s0.z < 0 && sb) ? 2 : 0);   // bit 1: a check without edges can never be satisfied
+          s0.w |= sb << 1;
+          state[c] = make_float4(__int_as_float(s0.x), __int_as_float(s0.y), __int_as_float(s0.z),
+                                 __int_as_float(s0.w));
+        }
+        for (int v = tid; v < a.n; v += P) L[v] = a.lam[v];
         for (int i = tid; i < (a.E4 >> 2); i += P) ((uint32_t*)sgn)[i] = a.sign0[i];
+      }
       if (fl) atomicOr(&s_flag, fl);
     }
     __syncthreads();
@@ -336,7 +360,38 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
       conv = false;
       for (int t = 1;; ++t) {
         // variable pass: L^t from the state of iteration t
-        {
+        if constexpr (PK) {
+          const float* wt = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;
+          float acc = 0.0f;
+          int vo = tid;                                   // v' of the lane's current column
+          auto vstep = [&](const int2 r, const int e) {
+            const int c = r.x & R_IDX, sh = (r.x >> R_SH) & 31;
+            const float4 s = state[c];
+            const float at = use_w ? wt[e] : a.alpha;
+            const float mag = __fmul_rn(at, sh == __float_as_int(s.z) ? s.y : s.x);
+            const float base = (r.x & R_FIRST) ? __int_as_float(r.y) : acc;   // lambda_v on a column's first edge
+            acc = __fadd_rn(base, ((__float_as_int(s.w) >> sh) & 1) ? -mag : mag);
+            if (r.x & R_LAST) {
+              L[vo] = acc;
+              vo += P;
+            }
+          };
+          // records are read two steps ahead; the schedule holds two rows of
+          // padding past its (even) length, so every read is in bounds
+          const int2* rp = a.pvs + tid;
+          const int32_t* ep = a.pve + tid;
+          int2 ra = rp[0], rb = rp[P];
+          int ea = 0, eb = 0;
+          if (use_w) { ea = ep[0]; eb = ep[P]; }
+          for (int k = 0; k < a.Kv; k += 2) {
+            vstep(ra, ea);
+            ra = rp[(size_t)(k + 2) * P];
+            if (use_w) ea = ep[(size_t)(k + 2) * P];
+            vstep(rb, eb);
+            rb = rp[(size_t)(k + 3) * P];
+            if (use_w) eb = ep[(size_t)(k + 3) * P];
+          }
+        } else {
           const float* wt = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;
           float acc = 0.0f;
           auto vstep = [&](const int4 r) {
@@ -346,10 +401,7 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
             const float mag = __fmul_rn(at, e == __float_as_int(s.z) ? s.y : s.x);
             const int fl = __float_as_int(s.w);
             const float base = (r.x & R_FIRST) ? __int_as_float(r.w) : acc;   // lambda_v on a column's first edge
-            int neg;
-            if constexpr (PK) neg = (fl >> ((r.x >> R_SH) & 31)) & 1;
-            else neg = ((fl >> 1) ^ fl ^ sgn[e]) & 1;
-            acc = __fadd_rn(base, neg ? -mag : mag);
+            acc = __fadd_rn(base, (((fl >> 1) ^ fl ^ sgn[e]) & 1) ? -mag : mag);
             if (r.x & R_LAST) L[v] = acc;
           };
           // records are read two steps ahead; the schedule holds two rows of
@@ -372,9 +424,11 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           float n1o = 0.0f, n2o = 0.0f, n1 = BP_BIG, n2 = BP_BIG;
           int nago = -1, nag = -1, sc = 0, spo = 0, npar = 0, hard = 0;
           int flo = 0, nbits = 0;                        // PK: the old record's word, the new message signs
-          auto cstep = [&](const int4 r) {
-            const int v = r.x & R_IDX, e = r.y, c = r.z;
-            const bool first = (r.x & R_FIRST) != 0;
+          // x: the record's flag word; e: the CSR edge (PK: for the weights only)
+          auto cstep = [&](const int x, const int v, const int c, const int e) {
+            const bool first = (x & R_FIRST) != 0;
+            const int sh = (x >> R_SH) & 31;
+            const int key = PK ? sh : e;                 // how the check state names its argmin edge
             // only lanes that start a check read its state (the others carry it)
             if (first) {
               const float4 s = state[c];
@@ -394,26 +448,22 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
             hard = (first ? 0 : hard) ^ (Lv < 0.0f ? 1 : 0);
             if (update) {
               const float ao = use_w ? wo[e < a.E32 ? e : 0] : a.alpha;
-              const float mag = __fmul_rn(ao, e == nago ? n2o : n1o);
-              int sh = 0, neg;
-              if constexpr (PK) {
-                sh = (r.x >> R_SH) & 31;
-                neg = (flo >> sh) & 1;
-              } else {
-                neg = sc ^ spo ^ sgn[e];
-              }
+              const float mag = __fmul_rn(ao, key == nago ? n2o : n1o);
+              int neg;
+              if constexpr (PK) neg = (flo >> sh) & 1;
+              else neg = sc ^ spo ^ sgn[e];
               const float q = __fsub_rn(Lv, neg ? -mag : mag);   // q = L_v - m_old
               const float aq = fabsf(q);
               const int ng = q < 0.0f ? 1 : 0;
               const bool lt1 = aq < n1, lt2 = aq < n2;
               n2 = lt1 ? n1 : (lt2 ? aq : n2);
               n1 = lt1 ? aq : n1;
-              nag = lt1 ? e : nag;
+              nag = lt1 ? key : nag;
               npar ^= ng;
               if constexpr (PK) nbits = (first ? 0 : nbits) | (ng << sh);
               else sgn[e] = (uint8_t)ng;
             }
-            if (r.x & R_LAST) {
+            if (x & R_LAST) {
               unsat |= hard != sc;
               if (update) {
                 // PK: message sign of edge j = s_c + parity + sgn q_j (mod 2)
@@ -423,13 +473,29 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
               }
             }
           };
-          const int4* rp = a.csched + tid;
-          int4 ra = rp[0], rb = rp[P];
-          for (int k = 0; k < a.Kc; k += 2) {
-            cstep(ra);
-            ra = rp[(size_t)(k + 2) * P];
-            cstep(rb);
-            rb = rp[(size_t)(k + 3) * P];
+          if constexpr (PK) {
+            const int2* rp = a.pcs + tid;
+            const int32_t* ep = a.pce + tid;
+            int2 ra = rp[0], rb = rp[P];
+            int ea = 0, eb = 0;
+            if (use_w) { ea = ep[0]; eb = ep[P]; }
+            for (int k = 0; k < a.Kc; k += 2) {
+              cstep(ra.x, ra.x & R_IDX, ra.y, ea);
+              ra = rp[(size_t)(k + 2) * P];
+              if (use_w) ea = ep[(size_t)(k + 2) * P];
+              cstep(rb.x, rb.x & R_IDX, rb.y, eb);
+              rb = rp[(size_t)(k + 3) * P];
+              if (use_w) eb = ep[(size_t)(k + 3) * P];
+            }
+          } else {
+            const int4* rp = a.csched + tid;
+            int4 ra = rp[0], rb = rp[P];
+            for (int k = 0; k < a.Kc; k += 2) {
+              cstep(ra.x, ra.x & R_IDX, ra.z, ra.y);
+              ra = rp[(size_t)(k + 2) * P];
+              cstep(rb.x, rb.x & R_IDX, rb.z, rb.y);
+              rb = rp[(size_t)(k + 3) * P];
+            }
           }
         }
         if (unsat) s_unsat[t & 1] = 1;                     // benign race: every writer stores 1
@@ -445,7 +511,13 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
     const int pos = s_pos;
     uint64_t pm[MAX_OW] = {0ull, 0ull, 0ull, 0ull};
     for (int v = tid; v < a.n; v += P) {
-      const float Lv = L[v];
+      float Lv;
+      if constexpr (PK) {
+        const int vm = a.vmap[v];
+        Lv = (vm >= 0 && (f0 & 1)) ? L[vm] : a.lam[v];   // (no BP run: the priors)
+      } else {
+        Lv = L[v];
+      }
       if (pos < 0 && Lv < 0.0f)
         for (int w = 0; w < a.ow; ++w) pm[w] ^= a.obs_mask[(int64_t)w * a.n + v];
       if (pos >= 0) a.osd_llr[(int64_t)pos * a.n + v] = Lv;
@@ -496,9 +568,11 @@ void free_device(DecodeDevice* d) {
   hipFree(d->row_ptr); hipFree(d->col_idx); hipFree(d->col_ptr); hipFree(d->csc_row); hipFree(d->csc_edge);
   hipFree(d->lam); hipFree(d->obs_mask); hipFree(d->counters); hipFree(d->queue); hipFree(d->osd_queue);
   hipFree(d->osd_llr); hipFree(d->basis); hipFree(d->synd); hipFree(d->gstate); hipFree(d->init); hipFree(d->sign0);
-  hipFree(d->init_pk);
   hipFree(d->rowmap); hipFree(d->retry); hipFree(d->lone);
-  for (auto& q : d->scheds) { hipFree(q.c); hipFree(q.v); hipFree(q.f); }
+  for (auto& q : d->scheds) {
+    hipFree(q.c); hipFree(q.v); hipFree(q.f);
+    hipFree(q.pc); hipFree(q.pv); hipFree(q.pce); hipFree(q.pve); hipFree(q.vmap); hipFree(q.corig); hipFree(q.pinit);
+  }
   *d = DecodeDevice();
 }
 
@@ -545,13 +619,16 @@ tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
     r.w = npar;
     init[c] = r;
     d->max_row_deg = std::max(d->max_row_deg, D.row_ptr[c + 1] - D.row_ptr[c]);
-    // packed: the sign of the message to the j-th edge in bit 2 + j (s_c = 0)
+    // packed: the sign of the message to the j-th edge in bit 2 + j (s_c = 0),
+    // the argmin edge as 2 + its position
     uint32_t pw = 0;
     for (int32_t e = D.row_ptr[c]; e < D.row_ptr[c + 1] && e - D.row_ptr[c] < PK_MAX_DEG; ++e)
       pw |= (uint32_t)(npar ^ sg[e]) << (2 + e - D.row_ptr[c]);
+    r.z = nag < 0 ? -1 : 2 + (nag - D.row_ptr[c]);
     r.w = (int32_t)pw;
     init_pk[c] = r;
   }
+  if (d->max_row_deg <= PK_MAX_DEG && D.cols < R_IDX && D.rows < R_IDX) d->init_pk = init_pk;
   // checks without edges (a shot with such a detection event never satisfies
   // H e = s) and the observables flipped by the hard decision of lambda alone
   std::vector<uint64_t> lone((size_t)std::max((D.rows + 63) / 64, 1), 0ull);
@@ -571,8 +648,7 @@ tmcs_status build_state(const Dem& D, int dev, DecodeDevice** out) {
   }
   std::vector<uint32_t> sg32((size_t)d->E4 / 4);
   if (!sg32.empty()) std::memcpy(sg32.data(), sg.data(), sg.size());
-  if ((st = upload(&d->init, init)) != TMCS_OK || (st = upload(&d->sign0, sg32)) != TMCS_OK ||
-      (d->max_row_deg <= PK_MAX_DEG && D.cols <= R_IDX && (st = upload(&d->init_pk, init_pk)) != TMCS_OK)) {
+  if ((st = upload(&d->init, init)) != TMCS_OK || (st = upload(&d->sign0, sg32)) != TMCS_OK) {
     free_device(d);
     delete d;
     return st;
@@ -739,6 +815,79 @@ tmcs_status get_fsched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
   return TMCS_OK;
 }
 
+// Records of the packed-state team kernel for team size P (the lane lists of
+// get_sched, same assignment): checks renumbered in the order the lanes first
+// reach them, the i-th column of lane l at v' = i P + l.
+tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevice::Sched* out) {
+  tmcs_status st = get_sched(D, d, P, mode, out);
+  if (st != TMCS_OK) return st;
+  DecodeDevice::Sched* q = nullptr;
+  for (auto& x : d->scheds)
+    if (x.P == P && x.mode == mode) q = &x;
+  if (!q) return fail(TMCS_EDEVICE, "BP schedule cache");
+  if (q->pc) { *out = *q; return TMCS_OK; }
+  if (d->init_pk.empty()) return fail(TMCS_EUNSUPPORTED, "packed BP state: a check has more than 30 edges");
+  auto assign = mode == 2 ? strided_assign : lpt_assign;
+  std::vector<int> rdeg(std::max(D.rows, 0)), cdeg(std::max(D.cols, 0));
+  for (int c = 0; c < D.rows; ++c) rdeg[c] = D.row_ptr[c + 1] - D.row_ptr[c];
+  for (int v = 0; v < D.cols; ++v) cdeg[v] = D.col_ptr[v + 1] - D.col_ptr[v];
+  std::vector<std::vector<int>> rl, cl;
+  assign(rdeg, P, &rl);
+  assign(cdeg, P, &cl);
+  size_t ri = 0, ci = 0;
+  for (int l = 0; l < P; ++l) { ri = std::max(ri, rl[l].size()); ci = std::max(ci, cl[l].size()); }
+  std::vector<int32_t> cslot(std::max(D.rows, 0), -1), corig, vmap(std::max(D.cols, 0), -1);
+  for (size_t i = 0; i < ri; ++i)
+    for (int l = 0; l < P; ++l)
+      if (i < rl[l].size()) { cslot[rl[l][i]] = (int32_t)corig.size(); corig.push_back(rl[l][i]); }
+  for (int l = 0; l < P; ++l)
+    for (size_t i = 0; i < cl[l].size(); ++i) vmap[cl[l][i]] = (int32_t)(i * P + l);
+  const int32_t Mpk = (int32_t)corig.size(), Npk = (int32_t)(ci * P);
+  if (Npk > R_IDX) return fail(TMCS_EUNSUPPORTED, "BP: too many column slots");
+  // padding steps read the spare slots (check Mpk, column Npk) and never store
+  std::vector<int2> pc((size_t)(q->Kc + 2) * P, make_int2(Npk, Mpk)), pv((size_t)(q->Kv + 2) * P, make_int2(Mpk, 0));
+  std::vector<int32_t> pce(pc.size(), 0), pve(pv.size(), 0);
+  for (int l = 0; l < P; ++l) {
+    size_t k = 0;
+    for (int c : rl[l])
+      for (int32_t e = D.row_ptr[c]; e < D.row_ptr[c + 1]; ++e, ++k) {
+        int32_t x = vmap[D.col_idx[e]] | pos_bits(e - D.row_ptr[c]);
+        if (e == D.row_ptr[c]) x |= R_FIRST;
+        if (e == D.row_ptr[c + 1] - 1) x |= R_LAST;
+        pc[k * P + l] = make_int2(x, cslot[c]);
+        pce[k * P + l] = e;
+      }
+    k = 0;
+    for (int v : cl[l]) {
+      const float lv = (float)std::log((1.0 - D.priors[v]) / D.priors[v]);
+      int32_t lbits;
+      std::memcpy(&lbits, &lv, 4);
+      for (int32_t j = D.col_ptr[v]; j < D.col_ptr[v + 1]; ++j, ++k) {
+        const int c = D.row_idx[j], e = D.csc_edge[j];
+        int32_t x = cslot[c] | pos_bits(e - D.row_ptr[c]);
+        if (j == D.col_ptr[v]) x |= R_FIRST;
+        if (j == D.col_ptr[v + 1] - 1) x |= R_LAST;
+        pv[k * P + l] = make_int2(x, lbits);
+        pve[k * P + l] = e;
+      }
+    }
+  }
+  std::vector<int4> pinit(std::max<int32_t>(Mpk, 1));
+  for (int32_t c = 0; c < Mpk; ++c) pinit[c] = d->init_pk[corig[c]];
+  if (corig.empty()) corig.push_back(0);
+  if (vmap.empty()) vmap.push_back(-1);
+  // (pc last: a schedule with pc set is complete)
+  if ((st = upload(&q->pv, pv)) != TMCS_OK || (st = upload(&q->pce, pce)) != TMCS_OK ||
+      (st = upload(&q->pve, pve)) != TMCS_OK || (st = upload(&q->vmap, vmap)) != TMCS_OK ||
+      (st = upload(&q->corig, corig)) != TMCS_OK || (st = upload(&q->pinit, pinit)) != TMCS_OK ||
+      (st = upload(&q->pc, pc)) != TMCS_OK)
+    return st;
+  q->Mpk = Mpk;
+  q->Npk = Npk;
+  *out = *q;
+  return TMCS_OK;
+}
+
 // The device state cached on the DEM handle (rebuilt when the device changes).
 tmcs_status ensure_device(const Dem& dc, DecodeDevice** out) {
   Dem& D = const_cast<Dem&>(dc);
@@ -872,10 +1021,11 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
     return fail(TMCS_EUNSUPPORTED, "OSD-CS needs the dense elimination (<= 2048 detectors, <= 16384 columns)");
   const int cus = device_cus();
   // BP launch shape: one team (workgroup) per shot in flight, state in LDS
-  // (the packed check state needs no sign bytes; the other kernels keep them)
-  const bool pk_ok = d->init_pk != nullptr && cfg.bp_global_state <= 1;
-  const size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (pk_ok ? 0 : (size_t)d->E4 + 4);
-  const bool gstate = cfg.bp_global_state != 0 || bp_lds > 160 * 1024;
+  // (the packed check state needs no sign bytes, and its column slots are
+  // about n: the exact size follows from the schedule; the other kernels keep the sign bytes)
+  const bool pk_ok = !d->init_pk.empty() && cfg.bp_global_state <= 1;
+  size_t bp_lds = (size_t)(D.rows + 1) * 16 + (size_t)D.cols * 4 + (pk_ok ? 0 : (size_t)d->E4 + 4);
+  bool gstate = cfg.bp_global_state != 0 || bp_lds > 160 * 1024;
   // state in device memory: one team per shot, or on request 64 shots per
   // workgroup in the lanes of its waves (on the surface-code NL-CNOT at d = 15..29
   // that layout measured 2-5x slower than the team kernel)
@@ -892,11 +1042,11 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   // (or one pass per iteration, on request)
   const bool fused = gstate && !lanes && cfg.bp_global_state == 3 && D.rows > 0;
   ps.fused = fused;
-  const size_t team_bytes = fused ? fused_team_bytes(D.rows, D.cols, d->E4) : (bp_lds + 255) & ~(size_t)255;
+  size_t team_bytes = fused ? fused_team_bytes(D.rows, D.cols, d->E4) : (bp_lds + 255) & ~(size_t)255;
   // teams per CU: as many as fit in LDS; with the state in device memory, one
   // team of 16 waves (fewer slabs in flight: at d = 15..29 that was 1.2-1.7x
   // faster than 4 teams of 8 waves), unless the caller asks for another shape
-  const int team_fit = gstate ? (cfg.bp_per_cu > 0 ? 32 : 1) : std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));
+  int team_fit = gstate ? (cfg.bp_per_cu > 0 ? 32 : 1) : std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));
   int P = 64;
   if (lanes) {
   } else if (cfg.bp_threads > 0) {
@@ -911,11 +1061,19 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   }
   P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
   const int sched_mode = cfg.bp_sched > 0 ? cfg.bp_sched : 1;
-  if (!lanes && (st = (fused ? get_fsched : get_sched)(D, d, P, sched_mode, &ps.sch)) != TMCS_OK) return st;
+  const bool pk = pk_ok && !lanes && !fused;
+  if (!lanes && (st = (fused ? get_fsched : pk ? get_psched : get_sched)(D, d, P, sched_mode, &ps.sch)) != TMCS_OK)
+    return st;
+  if (pk) {
+    bp_lds = (size_t)(ps.sch.Mpk + 1) * 16 + (size_t)(ps.sch.Npk + 1) * 4;
+    team_bytes = (bp_lds + 255) & ~(size_t)255;
+    if (!gstate && bp_lds > 160 * 1024) gstate = true;   // (the column slots' padding tipped it over)
+    team_fit = gstate ? (cfg.bp_per_cu > 0 ? 32 : 1) : std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));
+  }
   if (!gstate && bp_lds > 64 * 1024 && !bp_lds_allow(bp_lds)) return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
   const int per_cu = std::max(1, std::min({team_fit, 32 / (P / 64), cfg.bp_per_cu > 0 ? cfg.bp_per_cu : 32}));
   ps.gstate = gstate;
-  ps.pk = pk_ok && !lanes && !fused;
+  ps.pk = pk;
   ps.bp_lds = bp_lds;
   if (!lanes) {
     ps.P = P;
@@ -1029,7 +1187,8 @@ BPArgs bp_args(const DecodePass& ps, const uint64_t* det_unused, uint64_t* pred,
   const tmcs_decoder_cfg& cfg = ps.cfg;
   BPArgs a;
   a.csched = ps.sch.c; a.vsched = ps.sch.v; a.Kc = ps.sch.Kc; a.Kv = ps.sch.Kv; a.init = d->init; a.sign0 = d->sign0;
-  a.init_pk = d->init_pk;
+  a.pcs = ps.sch.pc; a.pvs = ps.sch.pv; a.pce = ps.sch.pce; a.pve = ps.sch.pve; a.vmap = ps.sch.vmap;
+  a.corig = ps.sch.corig; a.pinit = ps.sch.pinit; a.Mpk = ps.sch.Mpk; a.Npk = ps.sch.Npk;
   a.lam = d->lam; a.obs_mask = d->obs_mask; a.ow = D.obs_words;
   a.m = D.rows; a.n = D.cols; a.E = D.edges; a.E32 = (int32_t)D.edges; a.E4 = d->E4; a.T = cfg.max_iter; a.alpha = cfg.alpha;
   a.w = cfg.weights_dev;

@@ -58,6 +58,12 @@ __device__ __forceinline__ uint64_t block_xor_u64(uint64_t v, uint64_t* scratch)
 //               (entries of a column are consecutive in one lane, in CSC order)
 //   both:       bits R_SH.. of x = 2 + the edge's position within its check
 //               (0 where the check has more than PK_MAX_DEG edges)
+// The packed-state team kernel (PK) reads compact records instead (int2):
+//   check pass: x = v' | flags, y = c'
+//   var pass:   x = c' | flags, y = lambda_v bits
+// where c' numbers the checks in the order the lanes first reach them (step i
+// of lane l before step i of lane l + 1, before step i + 1) and v' = i P + l
+// for the i-th column of lane l, so state and L are written in lane order.
 // A team kernel gives every lane its own record list; the lanes kernel gives
 // every wave one.
 constexpr int32_t R_FIRST = 1 << 30;    // first edge of its check / column
@@ -75,7 +81,6 @@ struct BPArgs {
   const int4* vsched;        // [Kv][P] variable-pass records
   int32_t Kc, Kv;
   const int4* init;          // [m] check state of iteration 1 (n1, n2 bits, argmin edge, sign parity)
-  const int4* init_pk;       // [m] the same in the packed layout (message signs, s_c = 0); null if not built
   const uint32_t* sign0;     // [E4 / 4] sign bytes of q at iteration 1
   const float* lam;
   const uint64_t* obs_mask;  // [ow][n]
@@ -114,6 +119,15 @@ struct BPArgs {
   const int32_t* csc_row;    // [E] check of each CSC entry (columns of degree >= 3)
   const int32_t* csc_edge;   // [E] CSR edge of each CSC entry
   uint64_t pm_iso[MAX_OW];   // observables of the columns without edges whose lambda < 0
+  // packed-state team kernel: compact records over renumbered checks (c') and columns (v')
+  const int2* pcs;           // [Kc + 2][P] check-pass records
+  const int2* pvs;           // [Kv + 2][P] variable-pass records
+  const int32_t* pce;        // [Kc + 2][P] CSR edge of each check-pass record (per-edge weights)
+  const int32_t* pve;        // [Kv + 2][P] the same for the variable pass
+  const int32_t* vmap;       // [n] v -> v' (-1: a column without edges)
+  const int32_t* corig;      // [Mpk] c' -> c
+  const int4* pinit;         // [Mpk] packed check state of iteration 1 (s_c = 0; argmin as 2 + position)
+  int32_t Mpk, Npk;          // check slots (the checks with edges), column slots
 };
 
 // Several decode items' BP queues served by one launch.
