@@ -251,6 +251,28 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
     L = (float*)(state + (PK ? a.Mpk : a.m) + 1);
     sgn = (uint8_t*)(L + a.n);
   };
+  // state and L accesses (device memory: kept global in a multi launch, whose slab pointer is read from memory)
+  auto ld_state = [&](int c) -> float4 {
+    if constexpr (GSTATE) return gload(state + c);
+    else return state[c];
+  };
+  auto st_state = [&](int c, const float4 x) {
+    if constexpr (GSTATE) gstore(state + c, x);
+    else state[c] = x;
+  };
+  auto ld_L = [&](int v) -> float {
+    if constexpr (GSTATE) return gload(L + v);
+    else return L[v];
+  };
+  auto st_L = [&](int v, const float x) {
+    if constexpr (GSTATE) gstore(L + v, x);
+    else L[v] = x;
+  };
+  // schedule records and weights (a multi launch reads their pointers from memory)
+  auto rec = [&](const auto* p) {
+    if constexpr (MULTI) return gload(p);
+    else return *p;
+  };
   __shared__ int s_job, s_flag, s_pos, s_inst;
   __shared__ int s_unsat[2];
   __shared__ int s_pref[MAX_MULTI + 1];
@@ -326,18 +348,18 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
       if constexpr (PK) {
         // (L needs no start value: the variable pass writes every slot the check pass reads)
         for (int c = tid; c < a.Mpk; c += P) {
-          int4 s0 = a.pinit[c];
-          const int co = a.corig[c];
-          const int sb = (int)((sy[co >> 6] >> (co & 63)) & 1ull);
+          int4 s0 = gload(a.pinit + c);
+          const int co = gload(a.corig + c);
+          const int sb = (int)((gload(sy + (co >> 6)) >> (co & 63)) & 1ull);
           fl |= sb;
           s0.w ^= sb ? (int)0xFFFFFFFEu : 0;   // s_c = 1 flips every message sign
-          state[c] = make_float4(__int_as_float(s0.x), __int_as_float(s0.y), __int_as_float(s0.z),
-                                 __int_as_float(s0.w));
+          st_state(c, make_float4(__int_as_float(s0.x), __int_as_float(s0.y), __int_as_float(s0.z),
+                                  __int_as_float(s0.w)));
         }
         // a detection event on a check without edges: never satisfied
         if (a.lone)
           for (int w = tid; w < a.mw; w += P)
-            if (sy[w] & a.lone[w]) fl |= 3;
+            if (gload(sy + w) & gload(a.lone + w)) fl |= 3;
       } else {
         for (int c = tid; c < a.m; c += P) {
           int4 s0 = a.init[c];
@@ -364,15 +386,14 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           const float* wt = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;
           float acc = 0.0f;
           int vo = tid;                                   // v' of the lane's current column
-          auto vstep = [&](const int2 r, const int e) {
-            const int c = r.x & R_IDX, sh = (r.x >> R_SH) & 31;
-            const float4 s = state[c];
-            const float at = use_w ? wt[e] : a.alpha;
+          auto vstep = [&](const int2 r, const int e, const float4 s) {
+            const int sh = (r.x >> R_SH) & 31;
+            const float at = use_w ? rec(wt + e) : a.alpha;
             const float mag = __fmul_rn(at, sh == __float_as_int(s.z) ? s.y : s.x);
             const float base = (r.x & R_FIRST) ? __int_as_float(r.y) : acc;   // lambda_v on a column's first edge
             acc = __fadd_rn(base, ((__float_as_int(s.w) >> sh) & 1) ? -mag : mag);
             if (r.x & R_LAST) {
-              L[vo] = acc;
+              st_L(vo, acc);
               vo += P;
             }
           };
@@ -380,39 +401,49 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           // padding past its (even) length, so every read is in bounds
           const int2* rp = a.pvs + tid;
           const int32_t* ep = a.pve + tid;
-          int2 ra = rp[0], rb = rp[P];
+          int2 ra = rec(rp), rb = rec(rp + P);
           int ea = 0, eb = 0;
-          if (use_w) { ea = ep[0]; eb = ep[P]; }
+          if (use_w) { ea = rec(ep); eb = rec(ep + P); }
           for (int k = 0; k < a.Kv; k += 2) {
-            vstep(ra, ea);
-            ra = rp[(size_t)(k + 2) * P];
-            if (use_w) ea = ep[(size_t)(k + 2) * P];
-            vstep(rb, eb);
-            rb = rp[(size_t)(k + 3) * P];
-            if (use_w) eb = ep[(size_t)(k + 3) * P];
+            if constexpr (GSTATE) {
+              // both steps' state loads go out before either step's store (the
+              // compiler cannot tell that L and the check states do not overlap)
+              const float4 sa = ld_state(ra.x & R_IDX), sb = ld_state(rb.x & R_IDX);
+              vstep(ra, ea, sa);
+              ra = rec(rp + (size_t)(k + 2) * P);
+              if (use_w) ea = rec(ep + (size_t)(k + 2) * P);
+              vstep(rb, eb, sb);
+            } else {
+              vstep(ra, ea, state[ra.x & R_IDX]);
+              ra = rec(rp + (size_t)(k + 2) * P);
+              if (use_w) ea = rec(ep + (size_t)(k + 2) * P);
+              vstep(rb, eb, state[rb.x & R_IDX]);
+            }
+            rb = rec(rp + (size_t)(k + 3) * P);
+            if (use_w) eb = rec(ep + (size_t)(k + 3) * P);
           }
         } else {
           const float* wt = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;
           float acc = 0.0f;
           auto vstep = [&](const int4 r) {
             const int v = r.x & R_IDX, e = r.y, c = r.z;
-            const float4 s = state[c];
-            const float at = use_w ? wt[e < a.E32 ? e : 0] : a.alpha;
+            const float4 s = ld_state(c);
+            const float at = use_w ? rec(wt + (e < a.E32 ? e : 0)) : a.alpha;
             const float mag = __fmul_rn(at, e == __float_as_int(s.z) ? s.y : s.x);
             const int fl = __float_as_int(s.w);
             const float base = (r.x & R_FIRST) ? __int_as_float(r.w) : acc;   // lambda_v on a column's first edge
             acc = __fadd_rn(base, (((fl >> 1) ^ fl ^ sgn[e]) & 1) ? -mag : mag);
-            if (r.x & R_LAST) L[v] = acc;
+            if (r.x & R_LAST) st_L(v, acc);
           };
           // records are read two steps ahead; the schedule holds two rows of
           // padding past its (even) length, so every read is in bounds
           const int4* rp = a.vsched + tid;
-          int4 ra = rp[0], rb = rp[P];
+          int4 ra = rec(rp), rb = rec(rp + P);
           for (int k = 0; k < a.Kv; k += 2) {
             vstep(ra);
-            ra = rp[(size_t)(k + 2) * P];
+            ra = rec(rp + (size_t)(k + 2) * P);
             vstep(rb);
-            rb = rp[(size_t)(k + 3) * P];
+            rb = rec(rp + (size_t)(k + 3) * P);
           }
         }
         __syncthreads();
@@ -424,14 +455,16 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           float n1o = 0.0f, n2o = 0.0f, n1 = BP_BIG, n2 = BP_BIG;
           int nago = -1, nag = -1, sc = 0, spo = 0, npar = 0, hard = 0;
           int flo = 0, nbits = 0;                        // PK: the old record's word, the new message signs
-          // x: the record's flag word; e: the CSR edge (PK: for the weights only)
-          auto cstep = [&](const int x, const int v, const int c, const int e) {
+          // x: the record's flag word; e: the CSR edge (PK: for the weights only);
+          // get_s() gives the check's state (called on a check's first edge only),
+          // get_L() gives L_v
+          auto cstep = [&](const int x, const int c, const int e, auto&& get_s, auto&& get_L) {
             const bool first = (x & R_FIRST) != 0;
             const int sh = (x >> R_SH) & 31;
             const int key = PK ? sh : e;                 // how the check state names its argmin edge
             // only lanes that start a check read its state (the others carry it)
             if (first) {
-              const float4 s = state[c];
+              const float4 s = get_s();
               const int fl = __float_as_int(s.w);
               n1o = s.x;
               n2o = s.y;
@@ -440,14 +473,14 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
               spo = fl & 1;
               flo = fl;
             }
-            const float Lv = L[v];
+            const float Lv = get_L();
             n1 = first ? BP_BIG : n1;
             n2 = first ? BP_BIG : n2;
             nag = first ? -1 : nag;
             npar = first ? 0 : npar;
             hard = (first ? 0 : hard) ^ (Lv < 0.0f ? 1 : 0);
             if (update) {
-              const float ao = use_w ? wo[e < a.E32 ? e : 0] : a.alpha;
+              const float ao = use_w ? rec(wo + (e < a.E32 ? e : 0)) : a.alpha;
               const float mag = __fmul_rn(ao, key == nago ? n2o : n1o);
               int neg;
               if constexpr (PK) neg = (flo >> sh) & 1;
@@ -469,32 +502,45 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
                 // PK: message sign of edge j = s_c + parity + sgn q_j (mod 2)
                 const int w = PK ? ((sc << 1) | ((nbits ^ ((sc ^ npar) ? (int)0xFFFFFFFCu : 0)) & (int)0xFFFFFFFCu))
                                  : ((sc << 1) | npar);
-                state[c] = make_float4(n1, n2, __int_as_float(nag), __int_as_float(w));
+                st_state(c, make_float4(n1, n2, __int_as_float(nag), __int_as_float(w)));
               }
             }
           };
           if constexpr (PK) {
             const int2* rp = a.pcs + tid;
             const int32_t* ep = a.pce + tid;
-            int2 ra = rp[0], rb = rp[P];
+            int2 ra = rec(rp), rb = rec(rp + P);
             int ea = 0, eb = 0;
-            if (use_w) { ea = ep[0]; eb = ep[P]; }
+            if (use_w) { ea = rec(ep); eb = rec(ep + P); }
+            float4 sa = make_float4(0.0f, 0.0f, 0.0f, 0.0f), sb = sa;
             for (int k = 0; k < a.Kc; k += 2) {
-              cstep(ra.x, ra.x & R_IDX, ra.y, ea);
-              ra = rp[(size_t)(k + 2) * P];
-              if (use_w) ea = ep[(size_t)(k + 2) * P];
-              cstep(rb.x, rb.x & R_IDX, rb.y, eb);
-              rb = rp[(size_t)(k + 3) * P];
-              if (use_w) eb = ep[(size_t)(k + 3) * P];
+              if constexpr (GSTATE) {
+                // both steps' loads go out before either step's store (a lane's
+                // checks are distinct, so a store never feeds a later read of the pass)
+                const float La = ld_L(ra.x & R_IDX), Lb = ld_L(rb.x & R_IDX);
+                if (ra.x & R_FIRST) sa = ld_state(ra.y);
+                if (rb.x & R_FIRST) sb = ld_state(rb.y);
+                cstep(ra.x, ra.y, ea, [&] { return sa; }, [&] { return La; });
+                ra = rec(rp + (size_t)(k + 2) * P);
+                if (use_w) ea = rec(ep + (size_t)(k + 2) * P);
+                cstep(rb.x, rb.y, eb, [&] { return sb; }, [&] { return Lb; });
+              } else {
+                cstep(ra.x, ra.y, ea, [&] { return state[ra.y]; }, [&] { return L[ra.x & R_IDX]; });
+                ra = rec(rp + (size_t)(k + 2) * P);
+                if (use_w) ea = rec(ep + (size_t)(k + 2) * P);
+                cstep(rb.x, rb.y, eb, [&] { return state[rb.y]; }, [&] { return L[rb.x & R_IDX]; });
+              }
+              rb = rec(rp + (size_t)(k + 3) * P);
+              if (use_w) eb = rec(ep + (size_t)(k + 3) * P);
             }
           } else {
             const int4* rp = a.csched + tid;
-            int4 ra = rp[0], rb = rp[P];
+            int4 ra = rec(rp), rb = rec(rp + P);
             for (int k = 0; k < a.Kc; k += 2) {
-              cstep(ra.x, ra.x & R_IDX, ra.z, ra.y);
-              ra = rp[(size_t)(k + 2) * P];
-              cstep(rb.x, rb.x & R_IDX, rb.z, rb.y);
-              rb = rp[(size_t)(k + 3) * P];
+              cstep(ra.x, ra.z, ra.y, [&] { return ld_state(ra.z); }, [&] { return ld_L(ra.x & R_IDX); });
+              ra = rec(rp + (size_t)(k + 2) * P);
+              cstep(rb.x, rb.z, rb.y, [&] { return ld_state(rb.z); }, [&] { return ld_L(rb.x & R_IDX); });
+              rb = rec(rp + (size_t)(k + 3) * P);
             }
           }
         }
@@ -513,8 +559,8 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
     for (int v = tid; v < a.n; v += P) {
       float Lv;
       if constexpr (PK) {
-        const int vm = a.vmap[v];
-        Lv = (vm >= 0 && (f0 & 1)) ? L[vm] : a.lam[v];   // (no BP run: the priors)
+        const int vm = gload(a.vmap + v);
+        Lv = (vm >= 0 && (f0 & 1)) ? ld_L(vm) : gload(a.lam + v);   // (no BP run: the priors)
       } else {
         Lv = L[v];
       }

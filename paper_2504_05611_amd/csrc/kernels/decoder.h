@@ -40,6 +40,37 @@ __device__ __forceinline__ void write_pred(uint64_t* pred, int64_t stride, int n
                (unsigned long long)(1ull << (shot & 63)));
 }
 
+// Loads and stores through the global address space.  A pointer the kernel
+// reads from memory (the per-item arguments of a multi launch) is generic to
+// the compiler, which then emits flat accesses and waits for every
+// outstanding memory operation before using any of them; these helpers keep
+// such accesses global, so loads issued ahead stay in flight.
+#define TMCS_GLOBAL_AS __attribute__((address_space(1)))
+typedef int tmcs_v2i __attribute__((ext_vector_type(2)));
+typedef int tmcs_v4i __attribute__((ext_vector_type(4)));
+typedef float tmcs_v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ int2 gload(const int2* p) {
+  const tmcs_v2i v = *(const TMCS_GLOBAL_AS tmcs_v2i*)p;
+  return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ int4 gload(const int4* p) {
+  const tmcs_v4i v = *(const TMCS_GLOBAL_AS tmcs_v4i*)p;
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float4 gload(const float4* p) {
+  const tmcs_v4f v = *(const TMCS_GLOBAL_AS tmcs_v4f*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int32_t gload(const int32_t* p) { return *(const TMCS_GLOBAL_AS int32_t*)p; }
+__device__ __forceinline__ float gload(const float* p) { return *(const TMCS_GLOBAL_AS float*)p; }
+__device__ __forceinline__ uint64_t gload(const uint64_t* p) { return *(const TMCS_GLOBAL_AS uint64_t*)p; }
+__device__ __forceinline__ void gstore(float4* p, const float4 x) {
+  tmcs_v4f v;
+  v.x = x.x; v.y = x.y; v.z = x.z; v.w = x.w;
+  *(TMCS_GLOBAL_AS tmcs_v4f*)p = v;
+}
+__device__ __forceinline__ void gstore(float* p, const float x) { *(TMCS_GLOBAL_AS float*)p = x; }
+
 __device__ __forceinline__ uint64_t block_xor_u64(uint64_t v, uint64_t* scratch) {
   if (threadIdx.x == 0) *scratch = 0ull;
   __syncthreads();
