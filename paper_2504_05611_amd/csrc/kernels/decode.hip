@@ -70,6 +70,7 @@ struct DecodeDevice {
     int32_t *pce = nullptr, *pve = nullptr, *vmap = nullptr, *corig = nullptr;
     int4* pinit = nullptr;
     int32_t Mpk = 0, Npk = 0;
+    int32_t Kc4 = 0, Kv4 = 0;        // list lengths rounded up to 4 (arrays: [K4 + 4][P])
   };
   std::vector<Sched> scheds;
   // scratch
@@ -401,26 +402,40 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           // padding past its (even) length, so every read is in bounds
           const int2* rp = a.pvs + tid;
           const int32_t* ep = a.pve + tid;
-          int2 ra = rec(rp), rb = rec(rp + P);
-          int ea = 0, eb = 0;
-          if (use_w) { ea = rec(ep); eb = rec(ep + P); }
-          for (int k = 0; k < a.Kv; k += 2) {
-            if constexpr (GSTATE) {
-              // both steps' state loads go out before either step's store (the
-              // compiler cannot tell that L and the check states do not overlap)
-              const float4 sa = ld_state(ra.x & R_IDX), sb = ld_state(rb.x & R_IDX);
-              vstep(ra, ea, sa);
-              ra = rec(rp + (size_t)(k + 2) * P);
-              if (use_w) ea = rec(ep + (size_t)(k + 2) * P);
-              vstep(rb, eb, sb);
-            } else {
+          if constexpr (GSTATE) {
+            // device memory: four steps' state loads go out before any of their
+            // stores (the compiler cannot tell that L and the check states do
+            // not overlap); records are read four steps ahead
+            int2 r[4];
+            int ev[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              r[u] = rec(rp + (size_t)u * P);
+              if (use_w) ev[u] = rec(ep + (size_t)u * P);
+            }
+            for (int k = 0; k < a.Kv4; k += 4) {
+              float4 sv[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) sv[u] = ld_state(r[u].x & R_IDX);
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                vstep(r[u], ev[u], sv[u]);
+                r[u] = rec(rp + (size_t)(k + 4 + u) * P);
+                if (use_w) ev[u] = rec(ep + (size_t)(k + 4 + u) * P);
+              }
+            }
+          } else {
+            int2 ra = rec(rp), rb = rec(rp + P);
+            int ea = 0, eb = 0;
+            if (use_w) { ea = rec(ep); eb = rec(ep + P); }
+            for (int k = 0; k < a.Kv; k += 2) {
               vstep(ra, ea, state[ra.x & R_IDX]);
               ra = rec(rp + (size_t)(k + 2) * P);
               if (use_w) ea = rec(ep + (size_t)(k + 2) * P);
               vstep(rb, eb, state[rb.x & R_IDX]);
+              rb = rec(rp + (size_t)(k + 3) * P);
+              if (use_w) eb = rec(ep + (size_t)(k + 3) * P);
             }
-            rb = rec(rp + (size_t)(k + 3) * P);
-            if (use_w) eb = rec(ep + (size_t)(k + 3) * P);
           }
         } else {
           const float* wt = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;
@@ -509,29 +524,44 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           if constexpr (PK) {
             const int2* rp = a.pcs + tid;
             const int32_t* ep = a.pce + tid;
-            int2 ra = rec(rp), rb = rec(rp + P);
-            int ea = 0, eb = 0;
-            if (use_w) { ea = rec(ep); eb = rec(ep + P); }
-            float4 sa = make_float4(0.0f, 0.0f, 0.0f, 0.0f), sb = sa;
-            for (int k = 0; k < a.Kc; k += 2) {
-              if constexpr (GSTATE) {
-                // both steps' loads go out before either step's store (a lane's
-                // checks are distinct, so a store never feeds a later read of the pass)
-                const float La = ld_L(ra.x & R_IDX), Lb = ld_L(rb.x & R_IDX);
-                if (ra.x & R_FIRST) sa = ld_state(ra.y);
-                if (rb.x & R_FIRST) sb = ld_state(rb.y);
-                cstep(ra.x, ra.y, ea, [&] { return sa; }, [&] { return La; });
-                ra = rec(rp + (size_t)(k + 2) * P);
-                if (use_w) ea = rec(ep + (size_t)(k + 2) * P);
-                cstep(rb.x, rb.y, eb, [&] { return sb; }, [&] { return Lb; });
-              } else {
+            if constexpr (GSTATE) {
+              // four steps' loads go out before any of their stores (a lane's
+              // checks are distinct, so a store never feeds a later read of the pass)
+              int2 r[4];
+              int ev[4] = {0, 0, 0, 0};
+              float4 sv[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                r[u] = rec(rp + (size_t)u * P);
+                if (use_w) ev[u] = rec(ep + (size_t)u * P);
+                sv[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+              }
+              for (int k = 0; k < a.Kc4; k += 4) {
+                float Lu[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  Lu[u] = ld_L(r[u].x & R_IDX);
+                  if (r[u].x & R_FIRST) sv[u] = ld_state(r[u].y);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  cstep(r[u].x, r[u].y, ev[u], [&] { return sv[u]; }, [&] { return Lu[u]; });
+                  r[u] = rec(rp + (size_t)(k + 4 + u) * P);
+                  if (use_w) ev[u] = rec(ep + (size_t)(k + 4 + u) * P);
+                }
+              }
+            } else {
+              int2 ra = rec(rp), rb = rec(rp + P);
+              int ea = 0, eb = 0;
+              if (use_w) { ea = rec(ep); eb = rec(ep + P); }
+              for (int k = 0; k < a.Kc; k += 2) {
                 cstep(ra.x, ra.y, ea, [&] { return state[ra.y]; }, [&] { return L[ra.x & R_IDX]; });
                 ra = rec(rp + (size_t)(k + 2) * P);
                 if (use_w) ea = rec(ep + (size_t)(k + 2) * P);
                 cstep(rb.x, rb.y, eb, [&] { return state[rb.y]; }, [&] { return L[rb.x & R_IDX]; });
+                rb = rec(rp + (size_t)(k + 3) * P);
+                if (use_w) eb = rec(ep + (size_t)(k + 3) * P);
               }
-              rb = rec(rp + (size_t)(k + 3) * P);
-              if (use_w) eb = rec(ep + (size_t)(k + 3) * P);
             }
           } else {
             const int4* rp = a.csched + tid;
@@ -891,7 +921,9 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
   const int32_t Mpk = (int32_t)corig.size(), Npk = (int32_t)(ci * P);
   if (Npk > R_IDX) return fail(TMCS_EUNSUPPORTED, "BP: too many column slots");
   // padding steps read the spare slots (check Mpk, column Npk) and never store
-  std::vector<int2> pc((size_t)(q->Kc + 2) * P, make_int2(Npk, Mpk)), pv((size_t)(q->Kv + 2) * P, make_int2(Mpk, 0));
+  // (lists padded to a multiple of 4 plus 4 rows: the device-memory kernel reads four steps ahead)
+  const int32_t Kc4 = (q->Kc + 3) & ~3, Kv4 = (q->Kv + 3) & ~3;
+  std::vector<int2> pc((size_t)(Kc4 + 4) * P, make_int2(Npk, Mpk)), pv((size_t)(Kv4 + 4) * P, make_int2(Mpk, 0));
   std::vector<int32_t> pce(pc.size(), 0), pve(pv.size(), 0);
   for (int l = 0; l < P; ++l) {
     size_t k = 0;
@@ -930,6 +962,8 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
     return st;
   q->Mpk = Mpk;
   q->Npk = Npk;
+  q->Kc4 = Kc4;
+  q->Kv4 = Kv4;
   *out = *q;
   return TMCS_OK;
 }
@@ -1235,6 +1269,7 @@ BPArgs bp_args(const DecodePass& ps, const uint64_t* det_unused, uint64_t* pred,
   a.csched = ps.sch.c; a.vsched = ps.sch.v; a.Kc = ps.sch.Kc; a.Kv = ps.sch.Kv; a.init = d->init; a.sign0 = d->sign0;
   a.pcs = ps.sch.pc; a.pvs = ps.sch.pv; a.pce = ps.sch.pce; a.pve = ps.sch.pve; a.vmap = ps.sch.vmap;
   a.corig = ps.sch.corig; a.pinit = ps.sch.pinit; a.Mpk = ps.sch.Mpk; a.Npk = ps.sch.Npk;
+  a.Kc4 = ps.sch.Kc4; a.Kv4 = ps.sch.Kv4;
   a.lam = d->lam; a.obs_mask = d->obs_mask; a.ow = D.obs_words;
   a.m = D.rows; a.n = D.cols; a.E = D.edges; a.E32 = (int32_t)D.edges; a.E4 = d->E4; a.T = cfg.max_iter; a.alpha = cfg.alpha;
   a.w = cfg.weights_dev;

@@ -151,14 +151,15 @@ struct BPArgs {
   const int32_t* csc_edge;   // [E] CSR edge of each CSC entry
   uint64_t pm_iso[MAX_OW];   // observables of the columns without edges whose lambda < 0
   // packed-state team kernel: compact records over renumbered checks (c') and columns (v')
-  const int2* pcs;           // [Kc + 2][P] check-pass records
-  const int2* pvs;           // [Kv + 2][P] variable-pass records
-  const int32_t* pce;        // [Kc + 2][P] CSR edge of each check-pass record (per-edge weights)
-  const int32_t* pve;        // [Kv + 2][P] the same for the variable pass
+  const int2* pcs;           // [Kc4 + 4][P] check-pass records
+  const int2* pvs;           // [Kv4 + 4][P] variable-pass records
+  const int32_t* pce;        // [Kc4 + 4][P] CSR edge of each check-pass record (per-edge weights)
+  const int32_t* pve;        // [Kv4 + 4][P] the same for the variable pass
   const int32_t* vmap;       // [n] v -> v' (-1: a column without edges)
   const int32_t* corig;      // [Mpk] c' -> c
   const int4* pinit;         // [Mpk] packed check state of iteration 1 (s_c = 0; argmin as 2 + position)
   int32_t Mpk, Npk;          // check slots (the checks with edges), column slots
+  int32_t Kc4, Kv4;          // Kc, Kv rounded up to 4 (the arrays hold 4 rows of padding past them)
 };
 
 // Several decode items' BP queues served by one launch.
