@@ -70,7 +70,7 @@ struct DecodeDevice {
     int32_t *pce = nullptr, *pve = nullptr, *vmap = nullptr, *corig = nullptr;
     int4* pinit = nullptr;
     int32_t Mpk = 0, Npk = 0;
-    int32_t Kc4 = 0, Kv4 = 0;        // list lengths rounded up to 4 (arrays: [K4 + 4][P])
+    int32_t Kc4 = 0, Kv4 = 0;        // list lengths rounded up to BP_AHEAD (arrays: [K4 + BP_AHEAD][P])
   };
   std::vector<Sched> scheds;
   // scratch
@@ -327,16 +327,17 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
     }
     __syncthreads();
     if constexpr (MULTI) {
-      const int inst = s_inst;
+      // (read through readfirstlane: the compiler then knows the value is uniform)
+      const int inst = __builtin_amdgcn_readfirstlane(s_inst);
       if (inst != cur) {                              // uniform: the team moves to the next item
         if (cur >= 0) flush();
         if (inst >= mu.n) break;
         cur = inst;
-        a = mu.tab[inst];
+        a = load_uniform(mu.tab + inst);
         bind();
       }
     }
-    const int job = s_job;
+    const int job = MULTI ? __builtin_amdgcn_readfirstlane(s_job) : s_job;
     if (!MULTI && job >= total) break;
     // per-item weights in a multi launch (null: scalar alpha)
     const bool use_w = WEIGHTED && (!MULTI || a.w != nullptr);
@@ -376,7 +377,7 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
       if (fl) atomicOr(&s_flag, fl);
     }
     __syncthreads();
-    const int f0 = s_flag;
+    const int f0 = MULTI ? __builtin_amdgcn_readfirstlane(s_flag) : s_flag;
     int itr = 0;
     bool conv = true;
     if (f0 & 1) {
@@ -403,25 +404,26 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           const int2* rp = a.pvs + tid;
           const int32_t* ep = a.pve + tid;
           if constexpr (GSTATE) {
-            // device memory: four steps' state loads go out before any of their
-            // stores (the compiler cannot tell that L and the check states do
-            // not overlap); records are read four steps ahead
-            int2 r[4];
-            int ev[4] = {0, 0, 0, 0};
+            // device memory: BP_AHEAD steps' state loads go out before any of
+            // their stores (the compiler cannot tell that L and the check states
+            // do not overlap); records are read BP_AHEAD steps ahead
+            constexpr int U = BP_AHEAD;
+            int2 r[U];
+            int ev[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < U; ++u) {
               r[u] = rec(rp + (size_t)u * P);
-              if (use_w) ev[u] = rec(ep + (size_t)u * P);
+              ev[u] = use_w ? rec(ep + (size_t)u * P) : 0;
             }
-            for (int k = 0; k < a.Kv4; k += 4) {
-              float4 sv[4];
+            for (int k = 0; k < a.Kv4; k += U) {
+              float4 sv[U];
 #pragma unroll
-              for (int u = 0; u < 4; ++u) sv[u] = ld_state(r[u].x & R_IDX);
+              for (int u = 0; u < U; ++u) sv[u] = ld_state(r[u].x & R_IDX);
 #pragma unroll
-              for (int u = 0; u < 4; ++u) {
+              for (int u = 0; u < U; ++u) {
                 vstep(r[u], ev[u], sv[u]);
-                r[u] = rec(rp + (size_t)(k + 4 + u) * P);
-                if (use_w) ev[u] = rec(ep + (size_t)(k + 4 + u) * P);
+                r[u] = rec(rp + (size_t)(k + U + u) * P);
+                if (use_w) ev[u] = rec(ep + (size_t)(k + U + u) * P);
               }
             }
           } else {
@@ -525,29 +527,30 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
             const int2* rp = a.pcs + tid;
             const int32_t* ep = a.pce + tid;
             if constexpr (GSTATE) {
-              // four steps' loads go out before any of their stores (a lane's
+              // BP_AHEAD steps' loads go out before any of their stores (a lane's
               // checks are distinct, so a store never feeds a later read of the pass)
-              int2 r[4];
-              int ev[4] = {0, 0, 0, 0};
-              float4 sv[4];
+              constexpr int U = BP_AHEAD;
+              int2 r[U];
+              int ev[U];
+              float4 sv[U];
 #pragma unroll
-              for (int u = 0; u < 4; ++u) {
+              for (int u = 0; u < U; ++u) {
                 r[u] = rec(rp + (size_t)u * P);
-                if (use_w) ev[u] = rec(ep + (size_t)u * P);
+                ev[u] = use_w ? rec(ep + (size_t)u * P) : 0;
                 sv[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
               }
-              for (int k = 0; k < a.Kc4; k += 4) {
-                float Lu[4];
+              for (int k = 0; k < a.Kc4; k += U) {
+                float Lu[U];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < U; ++u) {
                   Lu[u] = ld_L(r[u].x & R_IDX);
                   if (r[u].x & R_FIRST) sv[u] = ld_state(r[u].y);
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < U; ++u) {
                   cstep(r[u].x, r[u].y, ev[u], [&] { return sv[u]; }, [&] { return Lu[u]; });
-                  r[u] = rec(rp + (size_t)(k + 4 + u) * P);
-                  if (use_w) ev[u] = rec(ep + (size_t)(k + 4 + u) * P);
+                  r[u] = rec(rp + (size_t)(k + U + u) * P);
+                  if (use_w) ev[u] = rec(ep + (size_t)(k + U + u) * P);
                 }
               }
             } else {
@@ -584,7 +587,7 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
     // finalise: prediction from the hard decision, or hand the posteriors to OSD
     if (tid == 0) s_pos = (!conv && a.use_osd) ? atomicAdd(&a.counters[2], 1) : -1;
     __syncthreads();
-    const int pos = s_pos;
+    const int pos = MULTI ? __builtin_amdgcn_readfirstlane(s_pos) : s_pos;
     uint64_t pm[MAX_OW] = {0ull, 0ull, 0ull, 0ull};
     for (int v = tid; v < a.n; v += P) {
       float Lv;
@@ -921,9 +924,11 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
   const int32_t Mpk = (int32_t)corig.size(), Npk = (int32_t)(ci * P);
   if (Npk > R_IDX) return fail(TMCS_EUNSUPPORTED, "BP: too many column slots");
   // padding steps read the spare slots (check Mpk, column Npk) and never store
-  // (lists padded to a multiple of 4 plus 4 rows: the device-memory kernel reads four steps ahead)
-  const int32_t Kc4 = (q->Kc + 3) & ~3, Kv4 = (q->Kv + 3) & ~3;
-  std::vector<int2> pc((size_t)(Kc4 + 4) * P, make_int2(Npk, Mpk)), pv((size_t)(Kv4 + 4) * P, make_int2(Mpk, 0));
+  // (lists padded to a multiple of BP_AHEAD plus BP_AHEAD rows: the device-memory
+  // kernel reads BP_AHEAD steps ahead)
+  const int32_t Kc4 = (q->Kc + BP_AHEAD - 1) / BP_AHEAD * BP_AHEAD, Kv4 = (q->Kv + BP_AHEAD - 1) / BP_AHEAD * BP_AHEAD;
+  std::vector<int2> pc((size_t)(Kc4 + BP_AHEAD) * P, make_int2(Npk, Mpk)),
+      pv((size_t)(Kv4 + BP_AHEAD) * P, make_int2(Mpk, 0));
   std::vector<int32_t> pce(pc.size(), 0), pve(pv.size(), 0);
   for (int l = 0; l < P; ++l) {
     size_t k = 0;

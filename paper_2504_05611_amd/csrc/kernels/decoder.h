@@ -71,6 +71,21 @@ __device__ __forceinline__ void gstore(float4* p, const float4 x) {
 }
 __device__ __forceinline__ void gstore(float* p, const float x) { *(TMCS_GLOBAL_AS float*)p = x; }
 
+// A copy of a workgroup-uniform struct read from device memory, every word
+// passed through readfirstlane, so that the compiler keeps the fields in
+// scalar registers (a plain copy lands in vector registers, one per word:
+// the memory might be written by the kernel, so no scalar load is used).
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T* p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized struct");
+  T out;
+  const uint32_t* src = (const uint32_t*)p;
+  uint32_t* dst = (uint32_t*)&out;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return out;
+}
+
 __device__ __forceinline__ uint64_t block_xor_u64(uint64_t v, uint64_t* scratch) {
   if (threadIdx.x == 0) *scratch = 0ull;
   __syncthreads();
@@ -151,16 +166,19 @@ struct BPArgs {
   const int32_t* csc_edge;   // [E] CSR edge of each CSC entry
   uint64_t pm_iso[MAX_OW];   // observables of the columns without edges whose lambda < 0
   // packed-state team kernel: compact records over renumbered checks (c') and columns (v')
-  const int2* pcs;           // [Kc4 + 4][P] check-pass records
-  const int2* pvs;           // [Kv4 + 4][P] variable-pass records
-  const int32_t* pce;        // [Kc4 + 4][P] CSR edge of each check-pass record (per-edge weights)
-  const int32_t* pve;        // [Kv4 + 4][P] the same for the variable pass
+  const int2* pcs;           // [Kc4 + BP_AHEAD][P] check-pass records
+  const int2* pvs;           // [Kv4 + BP_AHEAD][P] variable-pass records
+  const int32_t* pce;        // [Kc4 + BP_AHEAD][P] CSR edge of each check-pass record (per-edge weights)
+  const int32_t* pve;        // [Kv4 + BP_AHEAD][P] the same for the variable pass
   const int32_t* vmap;       // [n] v -> v' (-1: a column without edges)
   const int32_t* corig;      // [Mpk] c' -> c
   const int4* pinit;         // [Mpk] packed check state of iteration 1 (s_c = 0; argmin as 2 + position)
   int32_t Mpk, Npk;          // check slots (the checks with edges), column slots
-  int32_t Kc4, Kv4;          // Kc, Kv rounded up to 4 (the arrays hold 4 rows of padding past them)
+  int32_t Kc4, Kv4;          // Kc, Kv rounded up to BP_AHEAD (the arrays hold BP_AHEAD rows of padding past them)
 };
+
+// Steps whose loads the device-memory team kernel keeps in flight per lane.
+constexpr int BP_AHEAD = 4;
 
 // Several decode items' BP queues served by one launch.
 struct BPMulti {
