@@ -1053,6 +1053,7 @@ struct DecodePass {
   bool osd_win = false, osd_pfx = false, osd_bl = false;
   bool win2 = false;           // windowed: a smaller first window, then the full one on what it leaves open
   int npad = 0, pfx_keys = 0, pfx_rank = 0, osd_grid = 0, pfx_grid = 0, win1_grid = 0, win1_rows = 0;
+  int win1_mw = 0;             // words of local rows of the first window (WIN_SMALL_MW or WIN_MID_MW)
   size_t osd_lds = 0, pfx_lds = 0, win1_lds = 0;
 };
 
@@ -1207,30 +1208,34 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   const int osd_grid = std::max(1, cus * osd_per_cu);
   const int pfx_fit = std::max<int>(1, (int)((160 * 1024) / (pfx_lds + 512)));
   const int pfx_grid = std::max(1, cus * std::min(pfx_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 16));
-  // windowed OSD-0 in two passes: a window of WIN_SMALL_ROWS local rows first
-  // (a quarter of the registers and LDS, so more workgroups per compute unit),
-  // then the full window on the shots whose early stop it does not reach.
-  // Local rows are numbered in order of first touch in both, so the smaller
-  // window's basis is a prefix of the larger's and every settled shot gets the
-  // same correction.
-  // (first window: a quarter of the full one's rows, at most WIN_SMALL_ROWS)
-  // By default the first window is used only where the expected number of
+  // windowed OSD-0 in two passes: a smaller window first (fewer registers and
+  // less LDS, so more workgroups per compute unit, and half or a quarter of
+  // the work per pivot), then the full window on the shots whose early stop
+  // it does not reach.  Local rows are numbered in order of first touch in
+  // both, so the smaller window's basis is a prefix of the larger's and every
+  // settled shot gets the same correction.
+  // The first window has WIN_SMALL_ROWS rows where the expected number of
   // detection events per shot (from the priors) is at most three quarters of
-  // its rows: on the surface-code CNOT at p = 1e-3 that is d <= 21 (327 events
-  // at d = 21: 8 instead of 24 ms per 4096 shots); at d = 29 (about 860) nearly
-  // every shot outgrew it and went to the full window anyway.  An explicit
-  // osd_window always takes both passes.
+  // that, WIN_MID_ROWS where it is at most 0.9 of that, and there is none
+  // beyond.  On the surface-code CNOT at p = 1e-3: d = 21 (327 events) takes
+  // 512 rows (8 instead of 24 ms per 4096 shots; 1024 rows: 12 ms), d = 29
+  // (about 860) 1024 rows (44 instead of 71 ms, 2 % of the shots retried; with
+  // 512 rows nearly every shot outgrew the first window).  An explicit
+  // osd_window always takes both passes, the first with a quarter of its rows
+  // (at most WIN_SMALL_ROWS).
   const int user_rows = cfg.osd_window > 0 ? cfg.osd_window : WIN_MAX_ROWS;
-  const int win1_rows = std::min(WIN_SMALL_ROWS, user_rows / 4);
-  const bool win2 = osd_win && win1_rows >= 2 && (cfg.osd_window > 0 || expected_events(D) <= 0.75 * win1_rows);
-  const int W1 = 2 * WIN_SMALL_MW;
-  const size_t win1_lds = (size_t)WIN_KEYS * 8 + (size_t)WIN_SMALL_ROWS * 16 + (size_t)W1 * 8 + 64;
+  const double ev = osd_win && cfg.osd_window == 0 ? expected_events(D) : 0.0;
+  const int mw1 = cfg.osd_window > 0 || ev <= 0.75 * WIN_SMALL_ROWS ? WIN_SMALL_MW : WIN_MID_MW;
+  const int win1_rows = cfg.osd_window > 0 ? std::min(WIN_SMALL_ROWS, user_rows / 4) : 64 * mw1;
+  const bool win2 = osd_win && win1_rows >= 2 && (cfg.osd_window > 0 || ev <= (mw1 == WIN_SMALL_MW ? 0.75 : 0.9) * win1_rows);
+  const int W1 = 2 * mw1;
+  const size_t win1_lds = (size_t)WIN_KEYS * 8 + (size_t)(64 * mw1) * 16 + (size_t)W1 * 8 + 64;
   const int win1_fit = std::max<int>(1, (int)((160 * 1024) / (win1_lds + 512)));
   const int win1_grid = std::max(1, cus * std::min(win1_fit, cfg.osd_per_cu > 0 ? cfg.osd_per_cu : 8));
   ps.osd_win = osd_win; ps.osd_pfx = osd_pfx; ps.osd_bl = osd_bl; ps.win2 = win2;
   ps.npad = npad; ps.pfx_keys = pfx_keys; ps.pfx_rank = pfx_rank;
   ps.osd_grid = osd_grid; ps.pfx_grid = pfx_grid; ps.osd_lds = osd_lds; ps.pfx_lds = pfx_lds;
-  ps.win1_grid = win1_grid; ps.win1_lds = win1_lds; ps.win1_rows = win1_rows;
+  ps.win1_grid = win1_grid; ps.win1_lds = win1_lds; ps.win1_rows = win1_rows; ps.win1_mw = mw1;
   if ((st = grow(&d->queue, &d->cap_queue, (size_t)chunk)) != TMCS_OK) return st;
   if ((st = grow(&d->synd, &d->cap_synd, (size_t)chunk * (size_t)std::max(mw, 1))) != TMCS_OK) return st;
   if (gstate && !lanes && (st = grow(&d->gstate, &d->cap_gstate, (size_t)cus * per_cu * team_bytes)) != TMCS_OK)
@@ -1245,7 +1250,7 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
         (!osd_bl && (st = grow(&d->basis, &d->cap_basis,
                                std::max({(size_t)osd_grid * (size_t)std::max(osd_rank, 1) * W,
                                          osd_pfx ? (size_t)pfx_grid * (size_t)std::max(pfx_rank, 1) * W_pfx : 0,
-                                         win2 ? (size_t)win1_grid * WIN_SMALL_ROWS * W1 : 0}))) != TMCS_OK))
+                                         win2 ? (size_t)win1_grid * (64 * mw1) * W1 : 0}))) != TMCS_OK))
       return st;
     if ((osd_pfx || win2) && (st = grow(&d->retry, &d->cap_retry, (size_t)chunk)) != TMCS_OK) return st;
     if (osd_win) {
@@ -1365,15 +1370,15 @@ tmcs_status decode_osd_launch(const DecodePass& ps, uint64_t* pred, tmcs_decode_
   if (!ps.cfg.use_osd) return TMCS_OK;
   const OSDArgs o = osd_args(ps, pred, stats, s0);
   if (ps.osd_win) {
-    if (!ps.win2) return launch_osd_win(o, ps.osd_grid, ps.osd_lds, stream, false);
+    if (!ps.win2) return launch_osd_win(o, ps.osd_grid, ps.osd_lds, stream, WIN_MW);
     OSDArgs o1 = o;
     o1.retry = ps.d->retry;
     o1.win_rows = ps.win1_rows;
-    tmcs_status st = launch_osd_win(o1, ps.win1_grid, ps.win1_lds, stream, true);
+    tmcs_status st = launch_osd_win(o1, ps.win1_grid, ps.win1_lds, stream, ps.win1_mw);
     if (st != TMCS_OK) return st;
     OSDArgs o2 = o;
     o2.jobs = ps.d->retry; o2.cnt_total = 4; o2.cnt_next = 5;
-    return launch_osd_win(o2, ps.osd_grid, ps.osd_lds, stream, false);
+    return launch_osd_win(o2, ps.osd_grid, ps.osd_lds, stream, WIN_MW);
   }
   if (ps.osd_pfx) {
     OSDArgs op = o;
@@ -1440,7 +1445,7 @@ struct MultiDecode {
   OSDArgs* osd_tab = nullptr;
   OSDArgs* osd_tab2 = nullptr;   // win2: the full window's pass over the retry lists
   OSDArgs osd_first2{};
-  int osd_grid1 = 0;
+  int osd_grid1 = 0, osd_mw1 = 0;
   size_t osd_lds1 = 0;
   OSDArgs osd_first{};       // host copy of the first windowed item's arguments
   int osd_grid = 0;
@@ -1538,7 +1543,7 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
     if (!ps.cfg.use_osd) continue;
     const bool join = ps.osd_win && (m->osd_win_items.empty() || (ps.osd_grid == m->osd_grid && ps.osd_lds == m->osd_lds &&
                                                                ps.win2 == m->osd_win2 && ps.win1_grid == m->osd_grid1 &&
-                                                               ps.win1_lds == m->osd_lds1));
+                                                               ps.win1_lds == m->osd_lds1 && ps.win1_mw == m->osd_mw1));
     if (join) {
       m->osd_win_items.push_back(i);
       m->osd_grid = ps.osd_grid;
@@ -1546,6 +1551,7 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
       m->osd_win2 = ps.win2;
       m->osd_grid1 = ps.win1_grid;
       m->osd_lds1 = ps.win1_lds;
+      m->osd_mw1 = ps.win1_mw;
     } else {
       m->osd_other_items.push_back(i);
     }
@@ -1609,10 +1615,11 @@ tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream) {
   if (!m->osd_win_items.empty()) {
     const OSDMulti mu{m->osd_tab, (int32_t)m->osd_win_items.size(), m->next + 1};
     if (m->osd_win2) {
-      if ((st = launch_osd_win_multi(m->osd_first, mu, m->osd_grid1, m->osd_lds1, stream, true)) != TMCS_OK) return st;
+      if ((st = launch_osd_win_multi(m->osd_first, mu, m->osd_grid1, m->osd_lds1, stream, m->osd_mw1)) != TMCS_OK)
+        return st;
       const OSDMulti mu2{m->osd_tab2, (int32_t)m->osd_win_items.size(), m->next + 2};
-      if ((st = launch_osd_win_multi(m->osd_first2, mu2, m->osd_grid, m->osd_lds, stream, false)) != TMCS_OK) return st;
-    } else if ((st = launch_osd_win_multi(m->osd_first, mu, m->osd_grid, m->osd_lds, stream, false)) != TMCS_OK) {
+      if ((st = launch_osd_win_multi(m->osd_first2, mu2, m->osd_grid, m->osd_lds, stream, WIN_MW)) != TMCS_OK) return st;
+    } else if ((st = launch_osd_win_multi(m->osd_first, mu, m->osd_grid, m->osd_lds, stream, WIN_MW)) != TMCS_OK) {
       return st;
     }
   }

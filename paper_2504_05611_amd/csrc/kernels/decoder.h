@@ -19,9 +19,11 @@ constexpr int OSD_MAX_KEYS = 16384;
 constexpr int WIN_KEYS = 2048;
 constexpr int WIN_MW = 32;
 constexpr int WIN_MAX_ROWS = 64 * WIN_MW;
-// the smaller first window (its shots that need more rows go to the full one)
+// the smaller first windows (their shots that need more rows go to the full one)
 constexpr int WIN_SMALL_MW = 8;
 constexpr int WIN_SMALL_ROWS = 64 * WIN_SMALL_MW;
+constexpr int WIN_MID_MW = 16;
+constexpr int WIN_MID_ROWS = 64 * WIN_MID_MW;
 // dense OSD-0 first tries this many smallest keys (one-wave and 256-thread variants)
 constexpr int PFX_KEYS_WAVE = 128;
 constexpr int PFX_KEYS_WG = 1024;
@@ -247,11 +249,12 @@ struct OSDMulti {
 
 // OSD launchers (osd.hip).  grid workgroups, lds bytes of dynamic LDS.
 // first: the first item's arguments (host copy; they fix the shared LDS layout).
-// small: the first window of WIN_SMALL_ROWS rows (a.retry receives what it leaves open).
+// mw: words of local rows, WIN_MW for the full window, WIN_SMALL_MW or WIN_MID_MW
+// for a first window (a.retry receives what it leaves open).
 tmcs_status launch_osd_win_multi(const OSDArgs& first, const OSDMulti& mu, int grid, size_t lds, hipStream_t s,
-                                 bool small);
+                                 int mw);
 // Windowed OSD-0 (DEMs beyond the dense limits).
-tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s, bool small);
+tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s, int mw);
 // Dense OSD-0 on the npad - 1 smallest keys first (jobs the prefix does not settle go to a.retry).
 tmcs_status dispatch_osd_pfx(int mw, bool bl, const OSDArgs& a, int grid, size_t lds, hipStream_t s);
 // Dense OSD-0 (or OSD-CS) with a full sort of kpt keys per thread; bl: basis in LDS, one wave per shot.

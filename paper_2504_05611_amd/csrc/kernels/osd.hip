@@ -810,8 +810,8 @@ tmcs_status dispatch_kpt_lds(int kpt, const OSDArgs& a, int grid, size_t lds, hi
 
 bool osd_lds_basis_ok(int mw, int npad) { return mw <= 8 && npad <= 4096; }
 
-// Windowed OSD-0 with 64 MW local rows.  The smaller window (WIN_SMALL_MW)
-// runs first and hands the shots it cannot settle to a.retry; the full one
+// Windowed OSD-0 with 64 MW local rows.  A smaller window (WIN_SMALL_MW or
+// WIN_MID_MW) runs first and hands the shots it cannot settle to a.retry; the full one
 // (WIN_MW) decodes those (a.jobs = the retry list), timed as k_osd_retry.
 template <int MW, bool MULTI>
 tmcs_status launch_osd_win_t(const OSDArgs& a, const OSDMulti& mu, int grid, size_t lds, hipStream_t s) {
@@ -822,19 +822,23 @@ tmcs_status launch_osd_win_t(const OSDArgs& a, const OSDMulti& mu, int grid, siz
   return hip_check(hipGetLastError(), "k_osd launch");
 }
 
-tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s, bool small) {
+tmcs_status launch_osd_win(const OSDArgs& a, int grid, size_t lds, hipStream_t s, int mw) {
   const OSDMulti none{nullptr, 0, nullptr};
-  return small ? launch_osd_win_t<WIN_SMALL_MW, false>(a, none, grid, lds, s)
-               : launch_osd_win_t<WIN_MW, false>(a, none, grid, lds, s);
+  if (mw == WIN_SMALL_MW) return launch_osd_win_t<WIN_SMALL_MW, false>(a, none, grid, lds, s);
+  if (mw == WIN_MID_MW) return launch_osd_win_t<WIN_MID_MW, false>(a, none, grid, lds, s);
+  if (mw == WIN_MW) return launch_osd_win_t<WIN_MW, false>(a, none, grid, lds, s);
+  return fail(TMCS_EINVAL, "windowed OSD: unsupported window size");
 }
 
 tmcs_status launch_osd_win_multi(const OSDArgs& first, const OSDMulti& mu, int grid, size_t lds, hipStream_t s,
-                                 bool small) {
+                                 int mw) {
   if (mu.n < 1 || mu.n > MAX_MULTI_OSD) return fail(TMCS_EINVAL, "multi-item OSD: 1..16 items");
   if (first.npad != WIN_KEYS) return fail(TMCS_EINVAL, "multi-item OSD: windowed items only");
   // the first item's arguments set the LDS layout, which every windowed item shares
-  return small ? launch_osd_win_t<WIN_SMALL_MW, true>(first, mu, grid, lds, s)
-               : launch_osd_win_t<WIN_MW, true>(first, mu, grid, lds, s);
+  if (mw == WIN_SMALL_MW) return launch_osd_win_t<WIN_SMALL_MW, true>(first, mu, grid, lds, s);
+  if (mw == WIN_MID_MW) return launch_osd_win_t<WIN_MID_MW, true>(first, mu, grid, lds, s);
+  if (mw == WIN_MW) return launch_osd_win_t<WIN_MW, true>(first, mu, grid, lds, s);
+  return fail(TMCS_EINVAL, "windowed OSD: unsupported window size");
 }
 
 tmcs_status dispatch_osd(int mw, int kpt, bool bl, const OSDArgs& a, int grid, size_t lds, hipStream_t s) {

@@ -166,3 +166,30 @@ def test_sc11_nlcnot_osd_beyond_dense_limits(gpu_lib):
         assert (pred[i] == ((e.astype(np.int64) @ Lm.T.astype(np.int64)) % 2 == 1)).all()
     assert ((r["ehat"].astype(np.int64) @ H.T.astype(np.int64)) % 2 == d_or.T).all()
     assert (r["pred2"] == r["pred"]).all()
+
+
+def test_mid_first_window_agrees_with_the_small_one(gpu_lib):
+    """d = 29 non-local CNOT of the mixed batch at p = 1e-3 (49,560 detectors,
+    about 860 expected detection events): by default a 1024-row first window
+    runs before the full 2048-row one; an explicit 2048-row window runs a
+    512-row first window instead.  Each window is exact whenever it spans the
+    syndrome and numbers its rows in order of first touch, so the smaller
+    windows' bases are prefixes of the full one's: every shot's correction,
+    flags and predicted observables agree, while far fewer shots reach the
+    full window after the larger first one."""
+    w = WORKLOADS["sc_nlcnot_mixed"]
+    idx, spec = next((i, s) for i, s in enumerate(w.specs) if s.d == 29 and s.p == 1e-3)
+    shots = 256
+    print(f"[osd-window] sc29 first windows shots={shots}", flush=True)
+    c = gpu_lib.Circuit(spec)
+    dem = gpu_lib.DEM(c)
+    det, obs = c.alloc_outputs(shots)
+    c.sample(w.seed, idx, 0, shots, det, obs)
+    a = _decode(gpu_lib, dem, det, shots, w.bp_iters)
+    b = _decode(gpu_lib, dem, det, shots, w.bp_iters, osd_window=2048)
+    assert int((a["flags"] & 2).astype(bool).sum()) > shots // 2
+    assert (a["flags"] == b["flags"]).all()
+    assert (a["ehat"] == b["ehat"]).all()
+    assert (a["pred"] == b["pred"]).all()
+    assert (a["pred2"] == a["pred"]).all() and (b["pred2"] == b["pred"]).all()
+    assert a["stats"]["osd_prefix_retry"] < b["stats"]["osd_prefix_retry"]
