@@ -71,6 +71,12 @@ struct DecodeDevice {
     int4* pinit = nullptr;
     int32_t Mpk = 0, Npk = 0;
     int32_t Kc4 = 0, Kv4 = 0;        // list lengths rounded up to BP_AHEAD (arrays: [K4 + BP_AHEAD][P])
+    // the same lists for the state in device memory: 4-byte records, check
+    // slots numbered i P + l like the column slots, lambda per column slot
+    int32_t *pc4 = nullptr, *pv4 = nullptr, *corig4 = nullptr;
+    int4* pinit4 = nullptr;
+    float* lamp = nullptr;
+    int32_t Mpk4 = 0;
   };
   std::vector<Sched> scheds;
   // scratch
@@ -352,6 +358,7 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
         for (int c = tid; c < a.Mpk; c += P) {
           int4 s0 = gload(a.pinit + c);
           const int co = gload(a.corig + c);
+          if (co < 0) continue;                         // an empty slot (never read)
           const int sb = (int)((gload(sy + (co >> 6)) >> (co & 63)) & 1ull);
           fl |= sb;
           s0.w ^= sb ? (int)0xFFFFFFFEu : 0;   // s_c = 1 flips every message sign
@@ -388,27 +395,29 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
           const float* wt = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;
           float acc = 0.0f;
           int vo = tid;                                   // v' of the lane's current column
-          auto vstep = [&](const int2 r, const int e, const float4 s) {
-            const int sh = (r.x >> R_SH) & 31;
+          // x: the record's flag word; lam = lambda_v (read on a column's first edge)
+          auto vstep = [&](const int x, const float lam, const int e, const float4 s) {
+            const int sh = (x >> R_SH) & 31;
             const float at = use_w ? rec(wt + e) : a.alpha;
             const float mag = __fmul_rn(at, sh == __float_as_int(s.z) ? s.y : s.x);
-            const float base = (r.x & R_FIRST) ? __int_as_float(r.y) : acc;   // lambda_v on a column's first edge
+            const float base = (x & R_FIRST) ? lam : acc;   // lambda_v on a column's first edge
             acc = __fadd_rn(base, ((__float_as_int(s.w) >> sh) & 1) ? -mag : mag);
-            if (r.x & R_LAST) {
+            if (x & R_LAST) {
               st_L(vo, acc);
               vo += P;
             }
           };
           // records are read two steps ahead; the schedule holds two rows of
           // padding past its (even) length, so every read is in bounds
-          const int2* rp = a.pvs + tid;
           const int32_t* ep = a.pve + tid;
           if constexpr (GSTATE) {
-            // device memory: BP_AHEAD steps' state loads go out before any of
-            // their stores (the compiler cannot tell that L and the check states
-            // do not overlap); records are read BP_AHEAD steps ahead
+            // device memory: 4-byte records (lambda_v from its column slot);
+            // BP_AHEAD steps' loads go out before any of their stores (the
+            // compiler cannot tell that L and the check states do not
+            // overlap); records are read BP_AHEAD steps ahead
+            const int32_t* rp = a.pvs4 + tid;
             constexpr int U = BP_AHEAD;
-            int2 r[U];
+            int r[U];
             int ev[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -417,24 +426,31 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
             }
             for (int k = 0; k < a.Kv4; k += U) {
               float4 sv[U];
-#pragma unroll
-              for (int u = 0; u < U; ++u) sv[u] = ld_state(r[u].x & R_IDX);
+              float lv[U];
+              int vu = vo;                                  // the column slot of step u
 #pragma unroll
               for (int u = 0; u < U; ++u) {
-                vstep(r[u], ev[u], sv[u]);
+                sv[u] = ld_state(r[u] & R_IDX);
+                lv[u] = (r[u] & R_FIRST) ? gload(a.lamp + vu) : 0.0f;
+                vu += (r[u] & R_LAST) ? P : 0;
+              }
+#pragma unroll
+              for (int u = 0; u < U; ++u) {
+                vstep(r[u], lv[u], ev[u], sv[u]);
                 r[u] = rec(rp + (size_t)(k + U + u) * P);
                 if (use_w) ev[u] = rec(ep + (size_t)(k + U + u) * P);
               }
             }
           } else {
+            const int2* rp = a.pvs + tid;
             int2 ra = rec(rp), rb = rec(rp + P);
             int ea = 0, eb = 0;
             if (use_w) { ea = rec(ep); eb = rec(ep + P); }
             for (int k = 0; k < a.Kv; k += 2) {
-              vstep(ra, ea, state[ra.x & R_IDX]);
+              vstep(ra.x, __int_as_float(ra.y), ea, state[ra.x & R_IDX]);
               ra = rec(rp + (size_t)(k + 2) * P);
               if (use_w) ea = rec(ep + (size_t)(k + 2) * P);
-              vstep(rb, eb, state[rb.x & R_IDX]);
+              vstep(rb.x, __int_as_float(rb.y), eb, state[rb.x & R_IDX]);
               rb = rec(rp + (size_t)(k + 3) * P);
               if (use_w) eb = rec(ep + (size_t)(k + 3) * P);
             }
@@ -524,13 +540,14 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
             }
           };
           if constexpr (PK) {
-            const int2* rp = a.pcs + tid;
             const int32_t* ep = a.pce + tid;
             if constexpr (GSTATE) {
+              // 4-byte records: the lane's i-th check is at slot i P + tid.
               // BP_AHEAD steps' loads go out before any of their stores (a lane's
               // checks are distinct, so a store never feeds a later read of the pass)
+              const int32_t* rp = a.pcs4 + tid;
               constexpr int U = BP_AHEAD;
-              int2 r[U];
+              int r[U];
               int ev[U];
               float4 sv[U];
 #pragma unroll
@@ -539,21 +556,26 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
                 ev[u] = use_w ? rec(ep + (size_t)u * P) : 0;
                 sv[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
               }
+              int co = tid;                                 // the slot of the lane's current check
               for (int k = 0; k < a.Kc4; k += U) {
                 float Lu[U];
+                int cu[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                  Lu[u] = ld_L(r[u].x & R_IDX);
-                  if (r[u].x & R_FIRST) sv[u] = ld_state(r[u].y);
+                  Lu[u] = ld_L(r[u] & R_IDX);
+                  cu[u] = co;
+                  if (r[u] & R_FIRST) sv[u] = ld_state(co);
+                  co += (r[u] & R_LAST) ? P : 0;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                  cstep(r[u].x, r[u].y, ev[u], [&] { return sv[u]; }, [&] { return Lu[u]; });
+                  cstep(r[u], cu[u], ev[u], [&] { return sv[u]; }, [&] { return Lu[u]; });
                   r[u] = rec(rp + (size_t)(k + U + u) * P);
                   if (use_w) ev[u] = rec(ep + (size_t)(k + U + u) * P);
                 }
               }
             } else {
+              const int2* rp = a.pcs + tid;
               int2 ra = rec(rp), rb = rec(rp + P);
               int ea = 0, eb = 0;
               if (use_w) { ea = rec(ep); eb = rec(ep + P); }
@@ -651,6 +673,7 @@ void free_device(DecodeDevice* d) {
   for (auto& q : d->scheds) {
     hipFree(q.c); hipFree(q.v); hipFree(q.f);
     hipFree(q.pc); hipFree(q.pv); hipFree(q.pce); hipFree(q.pve); hipFree(q.vmap); hipFree(q.corig); hipFree(q.pinit);
+    hipFree(q.pc4); hipFree(q.pv4); hipFree(q.corig4); hipFree(q.pinit4); hipFree(q.lamp);
   }
   *d = DecodeDevice();
 }
@@ -921,8 +944,16 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
       if (i < rl[l].size()) { cslot[rl[l][i]] = (int32_t)corig.size(); corig.push_back(rl[l][i]); }
   for (int l = 0; l < P; ++l)
     for (size_t i = 0; i < cl[l].size(); ++i) vmap[cl[l][i]] = (int32_t)(i * P + l);
-  const int32_t Mpk = (int32_t)corig.size(), Npk = (int32_t)(ci * P);
-  if (Npk > R_IDX) return fail(TMCS_EUNSUPPORTED, "BP: too many column slots");
+  const int32_t Mpk = (int32_t)corig.size(), Npk = (int32_t)(ci * P), Mpk4 = (int32_t)(ri * P);
+  if (Npk > R_IDX || Mpk4 > R_IDX) return fail(TMCS_EUNSUPPORTED, "BP: too many column or check slots");
+  // device-memory flavour: the i-th check of lane l at slot i P + l (-1: an empty slot)
+  std::vector<int32_t> cslot4(std::max(D.rows, 0), -1), corig4(std::max<int32_t>(Mpk4, 1), -1);
+  for (int l = 0; l < P; ++l)
+    for (size_t i = 0; i < rl[l].size(); ++i) {
+      cslot4[rl[l][i]] = (int32_t)(i * P + l);
+      corig4[i * P + l] = rl[l][i];
+    }
+  std::vector<float> lamp(std::max<int32_t>(Npk, 1), 0.0f);
   // padding steps read the spare slots (check Mpk, column Npk) and never store
   // (lists padded to a multiple of BP_AHEAD plus BP_AHEAD rows: the device-memory
   // kernel reads BP_AHEAD steps ahead)
@@ -930,6 +961,7 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
   std::vector<int2> pc((size_t)(Kc4 + BP_AHEAD) * P, make_int2(Npk, Mpk)),
       pv((size_t)(Kv4 + BP_AHEAD) * P, make_int2(Mpk, 0));
   std::vector<int32_t> pce(pc.size(), 0), pve(pv.size(), 0);
+  std::vector<int32_t> pc4(pc.size(), Npk), pv4(pv.size(), Mpk4);
   for (int l = 0; l < P; ++l) {
     size_t k = 0;
     for (int c : rl[l])
@@ -938,6 +970,7 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
         if (e == D.row_ptr[c]) x |= R_FIRST;
         if (e == D.row_ptr[c + 1] - 1) x |= R_LAST;
         pc[k * P + l] = make_int2(x, cslot[c]);
+        pc4[k * P + l] = x;
         pce[k * P + l] = e;
       }
     k = 0;
@@ -945,26 +978,33 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
       const float lv = (float)std::log((1.0 - D.priors[v]) / D.priors[v]);
       int32_t lbits;
       std::memcpy(&lbits, &lv, 4);
+      lamp[vmap[v]] = lv;
       for (int32_t j = D.col_ptr[v]; j < D.col_ptr[v + 1]; ++j, ++k) {
         const int c = D.row_idx[j], e = D.csc_edge[j];
-        int32_t x = cslot[c] | pos_bits(e - D.row_ptr[c]);
-        if (j == D.col_ptr[v]) x |= R_FIRST;
-        if (j == D.col_ptr[v + 1] - 1) x |= R_LAST;
-        pv[k * P + l] = make_int2(x, lbits);
+        int32_t f = pos_bits(e - D.row_ptr[c]);
+        if (j == D.col_ptr[v]) f |= R_FIRST;
+        if (j == D.col_ptr[v + 1] - 1) f |= R_LAST;
+        pv[k * P + l] = make_int2(cslot[c] | f, lbits);
+        pv4[k * P + l] = cslot4[c] | f;
         pve[k * P + l] = e;
       }
     }
   }
-  std::vector<int4> pinit(std::max<int32_t>(Mpk, 1));
+  std::vector<int4> pinit(std::max<int32_t>(Mpk, 1)), pinit4(std::max<int32_t>(Mpk4, 1), make_int4(0, 0, 0, 0));
   for (int32_t c = 0; c < Mpk; ++c) pinit[c] = d->init_pk[corig[c]];
+  for (int32_t c = 0; c < Mpk4; ++c)
+    if (corig4[c] >= 0) pinit4[c] = d->init_pk[corig4[c]];
   if (corig.empty()) corig.push_back(0);
   if (vmap.empty()) vmap.push_back(-1);
   // (pc last: a schedule with pc set is complete)
   if ((st = upload(&q->pv, pv)) != TMCS_OK || (st = upload(&q->pce, pce)) != TMCS_OK ||
       (st = upload(&q->pve, pve)) != TMCS_OK || (st = upload(&q->vmap, vmap)) != TMCS_OK ||
       (st = upload(&q->corig, corig)) != TMCS_OK || (st = upload(&q->pinit, pinit)) != TMCS_OK ||
-      (st = upload(&q->pc, pc)) != TMCS_OK)
+      (st = upload(&q->pc4, pc4)) != TMCS_OK || (st = upload(&q->pv4, pv4)) != TMCS_OK ||
+      (st = upload(&q->corig4, corig4)) != TMCS_OK || (st = upload(&q->pinit4, pinit4)) != TMCS_OK ||
+      (st = upload(&q->lamp, lamp)) != TMCS_OK || (st = upload(&q->pc, pc)) != TMCS_OK)
     return st;
+  q->Mpk4 = Mpk4;
   q->Mpk = Mpk;
   q->Npk = Npk;
   q->Kc4 = Kc4;
@@ -1152,8 +1192,10 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
     return st;
   if (pk) {
     bp_lds = (size_t)(ps.sch.Mpk + 1) * 16 + (size_t)(ps.sch.Npk + 1) * 4;
-    team_bytes = (bp_lds + 255) & ~(size_t)255;
     if (!gstate && bp_lds > 160 * 1024) gstate = true;   // (the column slots' padding tipped it over)
+    // (state in device memory: check slots numbered i P + l, so up to P - 1 more)
+    if (gstate) bp_lds = (size_t)(ps.sch.Mpk4 + 1) * 16 + (size_t)(ps.sch.Npk + 1) * 4;
+    team_bytes = (bp_lds + 255) & ~(size_t)255;
     team_fit = gstate ? (cfg.bp_per_cu > 0 ? 32 : 1) : std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));
   }
   if (!gstate && bp_lds > 64 * 1024 && !bp_lds_allow(bp_lds)) return fail(TMCS_EUNSUPPORTED, "BP state does not fit in LDS");
@@ -1278,7 +1320,9 @@ BPArgs bp_args(const DecodePass& ps, const uint64_t* det_unused, uint64_t* pred,
   BPArgs a;
   a.csched = ps.sch.c; a.vsched = ps.sch.v; a.Kc = ps.sch.Kc; a.Kv = ps.sch.Kv; a.init = d->init; a.sign0 = d->sign0;
   a.pcs = ps.sch.pc; a.pvs = ps.sch.pv; a.pce = ps.sch.pce; a.pve = ps.sch.pve; a.vmap = ps.sch.vmap;
-  a.corig = ps.sch.corig; a.pinit = ps.sch.pinit; a.Mpk = ps.sch.Mpk; a.Npk = ps.sch.Npk;
+  a.corig = ps.gstate ? ps.sch.corig4 : ps.sch.corig; a.pinit = ps.gstate ? ps.sch.pinit4 : ps.sch.pinit;
+  a.Mpk = ps.gstate ? ps.sch.Mpk4 : ps.sch.Mpk; a.Npk = ps.sch.Npk;
+  a.pcs4 = ps.sch.pc4; a.pvs4 = ps.sch.pv4; a.lamp = ps.sch.lamp;
   a.Kc4 = ps.sch.Kc4; a.Kv4 = ps.sch.Kv4;
   a.lam = d->lam; a.obs_mask = d->obs_mask; a.ow = D.obs_words;
   a.m = D.rows; a.n = D.cols; a.E = D.edges; a.E32 = (int32_t)D.edges; a.E4 = d->E4; a.T = cfg.max_iter; a.alpha = cfg.alpha;

@@ -173,9 +173,14 @@ struct BPArgs {
   const int32_t* pce;        // [Kc4 + BP_AHEAD][P] CSR edge of each check-pass record (per-edge weights)
   const int32_t* pve;        // [Kv4 + BP_AHEAD][P] the same for the variable pass
   const int32_t* vmap;       // [n] v -> v' (-1: a column without edges)
-  const int32_t* corig;      // [Mpk] c' -> c
+  const int32_t* corig;      // [Mpk] c' -> c (-1: an empty slot)
   const int4* pinit;         // [Mpk] packed check state of iteration 1 (s_c = 0; argmin as 2 + position)
-  int32_t Mpk, Npk;          // check slots (the checks with edges), column slots
+  int32_t Mpk, Npk;          // check slots, column slots
+  // state in device memory: 4-byte records; the i-th check of lane l is at slot
+  // c' = i P + l (as its columns are), so the check pass needs no check index
+  const int32_t* pcs4;       // [Kc4 + BP_AHEAD][P] check pass: v' | flags
+  const int32_t* pvs4;       // [Kv4 + BP_AHEAD][P] variable pass: c' | flags
+  const float* lamp;         // [Npk] lambda_v by column slot
   int32_t Kc4, Kv4;          // Kc, Kv rounded up to BP_AHEAD (the arrays hold BP_AHEAD rows of padding past them)
 };
 
