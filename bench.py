@@ -55,8 +55,8 @@ TRAFFIC = {
     "sc_nlcnot_mixed": {
         # one multi-item launch per step (every instance whose BP state is in device memory)
         "k_bp_dev": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
-                     "sha256": "ff9f06465fb3f07b7ee6cb70cf1894e556f6c21ab2aa78cd6d294af63c4ad83a",
-                     "fetch_kib": 1401346850.2, "write_kib": 642598028.9},
+                     "sha256": "c3eeed1d3a112713461772bf46ec653f219edc5150bdd186523c17bcdef50502",
+                     "fetch_kib": 582173762.8, "write_kib": 277691560.0},
     },
     "sc5_nlcnot": {
         "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
