@@ -65,18 +65,20 @@ struct DecodeDevice {
   struct Sched {
     int P = 0; int mode = 1; int Kc = 0, Kv = 0; int4* c = nullptr; int4* v = nullptr;
     int Kf = 0; int4* f = nullptr;   // single-pass records (built on first use)
-    // packed-state team kernel (built on first use)
-    int2 *pc = nullptr, *pv = nullptr;
-    int32_t *pce = nullptr, *pve = nullptr, *vmap = nullptr, *corig = nullptr;
-    int4* pinit = nullptr;
-    int32_t Mpk = 0, Npk = 0;
-    int32_t Kc4 = 0, Kv4 = 0;        // list lengths rounded up to BP_AHEAD (arrays: [K4 + BP_AHEAD][P])
-    // the same lists for the state in device memory: 4-byte records, check
-    // slots numbered i P + l like the column slots, lambda per column slot
+    // packed-state team kernel (built on first use): 4-byte records over
+    // degree chunks, check and column slots k P + l, lambda per column slot
     int32_t *pc4 = nullptr, *pv4 = nullptr, *corig4 = nullptr;
+    int32_t *pce = nullptr, *pve = nullptr, *vmap = nullptr;
     int4* pinit4 = nullptr;
     float* lamp = nullptr;
-    int32_t Mpk4 = 0;
+    int32_t Mpk4 = 0, Npk = 0;
+    int32_t Kc4 = 0, Kv4 = 0;        // list lengths rounded up to BP_AHEAD (arrays: [K4 + BP_AHEAD][P])
+    // the LDS flavour (longest-processing-time lists of get_sched; checks numbered
+    // in the order the lanes first reach them, columns i P + l; int2 records)
+    int2 *pcL = nullptr, *pvL = nullptr;
+    int32_t *pceL = nullptr, *pveL = nullptr, *vmapL = nullptr, *corigL = nullptr;
+    int4* pinitL = nullptr;
+    int32_t MpkL = 0, NpkL = 0;
   };
   std::vector<Sched> scheds;
   // scratch
@@ -249,13 +251,13 @@ template <bool WEIGHTED, bool GSTATE, bool MULTI, bool PK>
 __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
   extern __shared__ __align__(16) unsigned char sm[];
   unsigned char* base = nullptr;
-  float4* state = nullptr;                            // [m + 1] (slot m: padding records); PK: [Mpk + 1]
-  float* L = nullptr;                                 // [n]; PK: [Npk + 1]
+  float4* state = nullptr;                            // [m + 1] (slot m: padding records); PK: [Mpk + 2] (LDS: [Mpk + 1])
+  float* L = nullptr;                                 // [n]; PK: [Npk + 1] (slot Npk: +BIG for no-op edges)
   uint8_t* sgn = nullptr;                             // [E4 + 4] (byte E4: padding records); !PK only
   auto bind = [&]() {
     base = GSTATE ? a.gstate + (size_t)blockIdx.x * a.team_bytes : sm;
     state = (float4*)base;
-    L = (float*)(state + (PK ? a.Mpk : a.m) + 1);
+    L = (float*)(state + (PK ? (GSTATE ? a.Mpk + 2 : a.Mpk + 1) : a.m + 1));
     sgn = (uint8_t*)(L + a.n);
   };
   // state and L accesses (device memory: kept global in a multi launch, whose slab pointer is read from memory)
@@ -354,12 +356,13 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
       const uint64_t* sy = a.synd + ls * a.mw;
       int fl = 0;
       if constexpr (PK) {
-        // (L needs no start value: the variable pass writes every slot the check pass reads)
-        for (int c = tid; c < a.Mpk; c += P) {
+        // (L needs no start value: the variable pass writes every slot the check
+        // pass reads, but slot Npk, which no-op check edges read)
+        if (GSTATE && tid == 0) st_L(a.Npk, BP_BIG);
+        for (int c = tid; c < (GSTATE ? a.Mpk + 2 : a.Mpk); c += P) {
           int4 s0 = gload(a.pinit + c);
-          const int co = gload(a.corig + c);
-          if (co < 0) continue;                         // an empty slot (never read)
-          const int sb = (int)((gload(sy + (co >> 6)) >> (co & 63)) & 1ull);
+          const int co = gload(a.corig + c);          // (-1: an empty, padding or sink slot)
+          const int sb = co < 0 ? 0 : (int)((gload(sy + (co >> 6)) >> (co & 63)) & 1ull);
           fl |= sb;
           s0.w ^= sb ? (int)0xFFFFFFFEu : 0;   // s_c = 1 flips every message sign
           st_state(c, make_float4(__int_as_float(s0.x), __int_as_float(s0.y), __int_as_float(s0.z),
@@ -391,7 +394,56 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
       conv = false;
       for (int t = 1;; ++t) {
         // variable pass: L^t from the state of iteration t
-        if constexpr (PK) {
+        if constexpr (PK && GSTATE) {
+          // degree chunks: a column's first and last edge are on the same step
+          // in every lane of the wave, so those branches are uniform (lane 0's
+          // flags).  BP_AHEAD steps' loads go out before any of their stores (the
+          // compiler cannot tell that L and the check states do not overlap);
+          // records are read BP_AHEAD steps ahead.
+          const float* wt = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;
+          float acc = 0.0f;
+          int vo = tid;                                   // v' of the lane's current column
+          const int32_t* rp = a.pvs4 + tid;
+          const int32_t* ep = a.pve + tid;
+          constexpr int U = GSTATE ? BP_AHEAD : 2;   // (LDS: two steps, fewer registers)
+          int r[U];
+          int ev[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            r[u] = rec(rp + (size_t)u * P);
+            ev[u] = use_w ? rec(ep + (size_t)u * P) : 0;
+          }
+          for (int k = 0; k < a.Kv4; k += U) {
+            float4 sv[U];
+            float lv[U];
+            int vu = vo;                                  // the column slot of step u
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int f = __builtin_amdgcn_readfirstlane(r[u]);
+              sv[u] = ld_state(r[u] & R_IDX);
+              lv[u] = (f & R_FIRST) ? gload(a.lamp + vu) : 0.0f;
+              vu += (f & R_LAST) ? P : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const int x = r[u], f = __builtin_amdgcn_readfirstlane(x);
+              const int sh = (x >> R_SH) & 31;
+              const float4 st = sv[u];
+              const float at = use_w ? rec(wt + ev[u]) : a.alpha;
+              const float mag = __fmul_rn(at, sh == __float_as_int(st.z) ? st.y : st.x);
+              if (f & R_FIRST) acc = lv[u];               // lambda_v on a column's first edge
+              acc = __fadd_rn(acc, ((__float_as_int(st.w) >> sh) & 1) ? -mag : mag);
+              if (f & R_LAST) {
+                st_L(vo, acc);
+                vo += P;
+              }
+              r[u] = rec(rp + (size_t)(k + U + u) * P);
+              if (use_w) ev[u] = rec(ep + (size_t)(k + U + u) * P);
+            }
+          }
+        } else if constexpr (PK) {
+          // state in LDS: per-lane flags, int2 records read two steps ahead (the
+          // schedule holds two rows of padding past its even length)
           const float* wt = use_w ? a.w + (int64_t)(t - 1) * a.E : nullptr;
           float acc = 0.0f;
           int vo = tid;                                   // v' of the lane's current column
@@ -407,41 +459,8 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
               vo += P;
             }
           };
-          // records are read two steps ahead; the schedule holds two rows of
-          // padding past its (even) length, so every read is in bounds
           const int32_t* ep = a.pve + tid;
-          if constexpr (GSTATE) {
-            // device memory: 4-byte records (lambda_v from its column slot);
-            // BP_AHEAD steps' loads go out before any of their stores (the
-            // compiler cannot tell that L and the check states do not
-            // overlap); records are read BP_AHEAD steps ahead
-            const int32_t* rp = a.pvs4 + tid;
-            constexpr int U = BP_AHEAD;
-            int r[U];
-            int ev[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              r[u] = rec(rp + (size_t)u * P);
-              ev[u] = use_w ? rec(ep + (size_t)u * P) : 0;
-            }
-            for (int k = 0; k < a.Kv4; k += U) {
-              float4 sv[U];
-              float lv[U];
-              int vu = vo;                                  // the column slot of step u
-#pragma unroll
-              for (int u = 0; u < U; ++u) {
-                sv[u] = ld_state(r[u] & R_IDX);
-                lv[u] = (r[u] & R_FIRST) ? gload(a.lamp + vu) : 0.0f;
-                vu += (r[u] & R_LAST) ? P : 0;
-              }
-#pragma unroll
-              for (int u = 0; u < U; ++u) {
-                vstep(r[u], lv[u], ev[u], sv[u]);
-                r[u] = rec(rp + (size_t)(k + U + u) * P);
-                if (use_w) ev[u] = rec(ep + (size_t)(k + U + u) * P);
-              }
-            }
-          } else {
+          {
             const int2* rp = a.pvs + tid;
             int2 ra = rec(rp), rb = rec(rp + P);
             int ea = 0, eb = 0;
@@ -539,42 +558,85 @@ __global__ void __launch_bounds__(1024) k_bp(BPArgs a, BPMulti mu) {
               }
             }
           };
-          if constexpr (PK) {
+          if constexpr (PK && GSTATE) {
+            // degree chunks: a check's first and last edge are on the same step in
+            // every lane of the wave, so those branches are uniform (lane 0's
+            // flags) and the check states are read and written a whole wave at a
+            // time.  BP_AHEAD steps' loads go out before any of their stores (a
+            // lane's checks are distinct, so a store never feeds a later read of
+            // the pass).
+            const int32_t* rp = a.pcs4 + tid;
             const int32_t* ep = a.pce + tid;
-            if constexpr (GSTATE) {
-              // 4-byte records: the lane's i-th check is at slot i P + tid.
-              // BP_AHEAD steps' loads go out before any of their stores (a lane's
-              // checks are distinct, so a store never feeds a later read of the pass)
-              const int32_t* rp = a.pcs4 + tid;
-              constexpr int U = BP_AHEAD;
-              int r[U];
-              int ev[U];
+            constexpr int U = GSTATE ? BP_AHEAD : 2;   // (LDS: two steps, fewer registers)
+            int r[U];
+            int ev[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              r[u] = rec(rp + (size_t)u * P);
+              ev[u] = use_w ? rec(ep + (size_t)u * P) : 0;
+            }
+            int co = tid;                                 // the slot of the lane's current check
+            for (int k = 0; k < a.Kc4; k += U) {
+              float Lu[U];
               float4 sv[U];
+              int cu[U];
 #pragma unroll
               for (int u = 0; u < U; ++u) {
-                r[u] = rec(rp + (size_t)u * P);
-                ev[u] = use_w ? rec(ep + (size_t)u * P) : 0;
-                sv[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const int f = __builtin_amdgcn_readfirstlane(r[u]);
+                Lu[u] = ld_L(r[u] & R_IDX);
+                cu[u] = co;
+                sv[u] = (f & R_FIRST) ? ld_state(co) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                co += (f & R_LAST) ? P : 0;
               }
-              int co = tid;                                 // the slot of the lane's current check
-              for (int k = 0; k < a.Kc4; k += U) {
-                float Lu[U];
-                int cu[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                  Lu[u] = ld_L(r[u] & R_IDX);
-                  cu[u] = co;
-                  if (r[u] & R_FIRST) sv[u] = ld_state(co);
-                  co += (r[u] & R_LAST) ? P : 0;
+              for (int u = 0; u < U; ++u) {
+                const int x = r[u], f = __builtin_amdgcn_readfirstlane(x);
+                const int sh = (x >> R_SH) & 31;
+                if (f & R_FIRST) {
+                  const float4 st = sv[u];
+                  n1o = st.x;
+                  n2o = st.y;
+                  nago = __float_as_int(st.z);
+                  flo = __float_as_int(st.w);
+                  sc = (flo >> 1) & 1;
+                  n1 = BP_BIG;
+                  n2 = BP_BIG;
+                  nag = -1;
+                  npar = 0;
+                  hard = 0;
+                  nbits = 0;
                 }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                  cstep(r[u], cu[u], ev[u], [&] { return sv[u]; }, [&] { return Lu[u]; });
-                  r[u] = rec(rp + (size_t)(k + U + u) * P);
-                  if (use_w) ev[u] = rec(ep + (size_t)(k + U + u) * P);
+                const float Lv = Lu[u];
+                hard ^= Lv < 0.0f ? 1 : 0;
+                if (update) {
+                  const float ao = use_w ? rec(wo + ev[u]) : a.alpha;
+                  const float mag = __fmul_rn(ao, sh == nago ? n2o : n1o);
+                  const float q = __fsub_rn(Lv, ((flo >> sh) & 1) ? -mag : mag);   // q = L_v - m_old
+                  const float aq = fabsf(q);
+                  const int ng = q < 0.0f ? 1 : 0;
+                  const bool lt1 = aq < n1, lt2 = aq < n2;
+                  n2 = lt1 ? n1 : (lt2 ? aq : n2);
+                  n1 = lt1 ? aq : n1;
+                  nag = lt1 ? sh : nag;
+                  npar ^= ng;
+                  nbits |= ng << sh;
                 }
+                if (f & R_LAST) {
+                  unsat |= hard != sc;
+                  if (update) {
+                    // message sign of edge j = s_c + parity + sgn q_j (mod 2)
+                    const int w = (sc << 1) | ((nbits ^ ((sc ^ npar) ? (int)0xFFFFFFFCu : 0)) & (int)0xFFFFFFFCu);
+                    st_state(cu[u], make_float4(n1, n2, __int_as_float(nag), __int_as_float(w)));
+                  }
+                }
+                r[u] = rec(rp + (size_t)(k + U + u) * P);
+                if (use_w) ev[u] = rec(ep + (size_t)(k + U + u) * P);
               }
-            } else {
+            }
+          } else if constexpr (PK) {
+            // state in LDS: per-lane flags, int2 records read two steps ahead
+            const int32_t* ep = a.pce + tid;
+            {
               const int2* rp = a.pcs + tid;
               int2 ra = rec(rp), rb = rec(rp + P);
               int ea = 0, eb = 0;
@@ -672,7 +734,8 @@ void free_device(DecodeDevice* d) {
   hipFree(d->rowmap); hipFree(d->retry); hipFree(d->lone);
   for (auto& q : d->scheds) {
     hipFree(q.c); hipFree(q.v); hipFree(q.f);
-    hipFree(q.pc); hipFree(q.pv); hipFree(q.pce); hipFree(q.pve); hipFree(q.vmap); hipFree(q.corig); hipFree(q.pinit);
+    hipFree(q.pce); hipFree(q.pve); hipFree(q.vmap);
+    hipFree(q.pcL); hipFree(q.pvL); hipFree(q.pceL); hipFree(q.pveL); hipFree(q.vmapL); hipFree(q.corigL); hipFree(q.pinitL);
     hipFree(q.pc4); hipFree(q.pv4); hipFree(q.corig4); hipFree(q.pinit4); hipFree(q.lamp);
   }
   *d = DecodeDevice();
@@ -917,17 +980,21 @@ tmcs_status get_fsched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
   return TMCS_OK;
 }
 
-// Records of the packed-state team kernel for team size P (the lane lists of
-// get_sched, same assignment): checks renumbered in the order the lanes first
-// reach them, the i-th column of lane l at v' = i P + l.
-tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevice::Sched* out) {
+// Records of the packed-state team kernel with its state in LDS, for team size
+// P: the longest-processing-time lane lists of get_sched; checks numbered in the
+// order the lanes first reach them (step i of lane l before step i of lane
+// l + 1, before step i + 1), the i-th column of lane l at v' = i P + l; int2
+// records {v' | position | flags, c'} and {c' | position | flags, lambda_v}.
+// (The degree chunks of get_psched pad small DEMs too much: on the d = 5 and
+// d = 11 surface-code DEMs they made this kernel 23-29 % slower.)
+tmcs_status get_psched_lds(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevice::Sched* out) {
   tmcs_status st = get_sched(D, d, P, mode, out);
   if (st != TMCS_OK) return st;
   DecodeDevice::Sched* q = nullptr;
   for (auto& x : d->scheds)
     if (x.P == P && x.mode == mode) q = &x;
   if (!q) return fail(TMCS_EDEVICE, "BP schedule cache");
-  if (q->pc) { *out = *q; return TMCS_OK; }
+  if (q->pcL) { *out = *q; return TMCS_OK; }
   if (d->init_pk.empty()) return fail(TMCS_EUNSUPPORTED, "packed BP state: a check has more than 30 edges");
   auto assign = mode == 2 ? strided_assign : lpt_assign;
   std::vector<int> rdeg(std::max(D.rows, 0)), cdeg(std::max(D.cols, 0));
@@ -944,24 +1011,12 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
       if (i < rl[l].size()) { cslot[rl[l][i]] = (int32_t)corig.size(); corig.push_back(rl[l][i]); }
   for (int l = 0; l < P; ++l)
     for (size_t i = 0; i < cl[l].size(); ++i) vmap[cl[l][i]] = (int32_t)(i * P + l);
-  const int32_t Mpk = (int32_t)corig.size(), Npk = (int32_t)(ci * P), Mpk4 = (int32_t)(ri * P);
-  if (Npk > R_IDX || Mpk4 > R_IDX) return fail(TMCS_EUNSUPPORTED, "BP: too many column or check slots");
-  // device-memory flavour: the i-th check of lane l at slot i P + l (-1: an empty slot)
-  std::vector<int32_t> cslot4(std::max(D.rows, 0), -1), corig4(std::max<int32_t>(Mpk4, 1), -1);
-  for (int l = 0; l < P; ++l)
-    for (size_t i = 0; i < rl[l].size(); ++i) {
-      cslot4[rl[l][i]] = (int32_t)(i * P + l);
-      corig4[i * P + l] = rl[l][i];
-    }
-  std::vector<float> lamp(std::max<int32_t>(Npk, 1), 0.0f);
-  // padding steps read the spare slots (check Mpk, column Npk) and never store
-  // (lists padded to a multiple of BP_AHEAD plus BP_AHEAD rows: the device-memory
-  // kernel reads BP_AHEAD steps ahead)
-  const int32_t Kc4 = (q->Kc + BP_AHEAD - 1) / BP_AHEAD * BP_AHEAD, Kv4 = (q->Kv + BP_AHEAD - 1) / BP_AHEAD * BP_AHEAD;
-  std::vector<int2> pc((size_t)(Kc4 + BP_AHEAD) * P, make_int2(Npk, Mpk)),
-      pv((size_t)(Kv4 + BP_AHEAD) * P, make_int2(Mpk, 0));
+  const int32_t Mpk = (int32_t)corig.size(), Npk = (int32_t)(ci * P);
+  if (Npk > R_IDX) return fail(TMCS_EUNSUPPORTED, "BP: too many column slots");
+  // padding steps read the spare slots (check Mpk, column Npk) and never store;
+  // the lists hold two rows of padding past their (even) length
+  std::vector<int2> pc((size_t)(q->Kc + 2) * P, make_int2(Npk, Mpk)), pv((size_t)(q->Kv + 2) * P, make_int2(Mpk, 0));
   std::vector<int32_t> pce(pc.size(), 0), pve(pv.size(), 0);
-  std::vector<int32_t> pc4(pc.size(), Npk), pv4(pv.size(), Mpk4);
   for (int l = 0; l < P; ++l) {
     size_t k = 0;
     for (int c : rl[l])
@@ -970,7 +1025,6 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
         if (e == D.row_ptr[c]) x |= R_FIRST;
         if (e == D.row_ptr[c + 1] - 1) x |= R_LAST;
         pc[k * P + l] = make_int2(x, cslot[c]);
-        pc4[k * P + l] = x;
         pce[k * P + l] = e;
       }
     k = 0;
@@ -978,34 +1032,171 @@ tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDev
       const float lv = (float)std::log((1.0 - D.priors[v]) / D.priors[v]);
       int32_t lbits;
       std::memcpy(&lbits, &lv, 4);
-      lamp[vmap[v]] = lv;
       for (int32_t j = D.col_ptr[v]; j < D.col_ptr[v + 1]; ++j, ++k) {
         const int c = D.row_idx[j], e = D.csc_edge[j];
         int32_t f = pos_bits(e - D.row_ptr[c]);
         if (j == D.col_ptr[v]) f |= R_FIRST;
         if (j == D.col_ptr[v + 1] - 1) f |= R_LAST;
         pv[k * P + l] = make_int2(cslot[c] | f, lbits);
-        pv4[k * P + l] = cslot4[c] | f;
         pve[k * P + l] = e;
       }
     }
   }
-  std::vector<int4> pinit(std::max<int32_t>(Mpk, 1)), pinit4(std::max<int32_t>(Mpk4, 1), make_int4(0, 0, 0, 0));
+  std::vector<int4> pinit(std::max<int32_t>(Mpk, 1));
   for (int32_t c = 0; c < Mpk; ++c) pinit[c] = d->init_pk[corig[c]];
-  for (int32_t c = 0; c < Mpk4; ++c)
-    if (corig4[c] >= 0) pinit4[c] = d->init_pk[corig4[c]];
   if (corig.empty()) corig.push_back(0);
   if (vmap.empty()) vmap.push_back(-1);
-  // (pc last: a schedule with pc set is complete)
-  if ((st = upload(&q->pv, pv)) != TMCS_OK || (st = upload(&q->pce, pce)) != TMCS_OK ||
+  // (pcL last: a schedule with pcL set is complete)
+  if ((st = upload(&q->pvL, pv)) != TMCS_OK || (st = upload(&q->pceL, pce)) != TMCS_OK ||
+      (st = upload(&q->pveL, pve)) != TMCS_OK || (st = upload(&q->vmapL, vmap)) != TMCS_OK ||
+      (st = upload(&q->corigL, corig)) != TMCS_OK || (st = upload(&q->pinitL, pinit)) != TMCS_OK ||
+      (st = upload(&q->pcL, pc)) != TMCS_OK)
+    return st;
+  q->MpkL = Mpk;
+  q->NpkL = Npk;
+  *out = *q;
+  return TMCS_OK;
+}
+
+// Records of the packed-state team kernel with its state in device memory, for
+// team size P.  The checks with
+// edges are sorted by (degree, index) and cut into chunks of 64, one check per
+// lane of a wave, and the chunks go to the P / 64 waves in turn; the columns
+// likewise.  A chunk takes as many steps as its largest degree: shorter checks
+// (columns) and empty lanes get no-op edges, so a check's (column's) first and
+// last edge fall on the same step in every lane of a wave and the kernel
+// branches on them uniformly.  Lane l's k-th check is at slot c' = k P + l and
+// its k-th column at v' = k P + l.  No-op edges: in the check pass they read
+// L slot Npk (+BIG in every shot: q stays +BIG, so the minima, the sign parity
+// and the hard decision do not change); in the variable pass they read check
+// slot Mpk + 1 (n1 = n2 = +0, every message sign set: the message is -0, and
+// x + (-0) = x for every x).  Empty check slots start with s_c = 0 and are
+// only ever read by their own no-op check.
+tmcs_status get_psched(const Dem& D, DecodeDevice* d, int P, int mode, DecodeDevice::Sched* out) {
+  tmcs_status st = get_sched(D, d, P, mode, out);
+  if (st != TMCS_OK) return st;
+  DecodeDevice::Sched* q = nullptr;
+  for (auto& x : d->scheds)
+    if (x.P == P && x.mode == mode) q = &x;
+  if (!q) return fail(TMCS_EDEVICE, "BP schedule cache");
+  if (q->pc4) { *out = *q; return TMCS_OK; }
+  if (d->init_pk.empty()) return fail(TMCS_EUNSUPPORTED, "packed BP state: a check has more than 30 edges");
+  if (P % 64) return fail(TMCS_EINVAL, "packed BP state: team size must be a multiple of 64");
+  const int NW = P / 64;
+  std::vector<int> rdeg(std::max(D.rows, 0)), cdeg(std::max(D.cols, 0));
+  for (int c = 0; c < D.rows; ++c) rdeg[c] = D.row_ptr[c + 1] - D.row_ptr[c];
+  for (int v = 0; v < D.cols; ++v) cdeg[v] = D.col_ptr[v + 1] - D.col_ptr[v];
+  // chunks of 64 items (-1: an empty lane) in (degree, index) order, and their widths
+  auto make_chunks = [](const std::vector<int>& deg, std::vector<std::vector<int>>* ch, std::vector<int>* width) {
+    std::vector<int> items;
+    for (int i = 0; i < (int)deg.size(); ++i)
+      if (deg[i] > 0) items.push_back(i);
+    std::stable_sort(items.begin(), items.end(), [&](int a, int b) { return deg[a] < deg[b]; });
+    for (size_t i = 0; i < items.size(); i += 64) {
+      std::vector<int> c(64, -1);
+      int w = 0;
+      for (size_t j = 0; j < 64 && i + j < items.size(); ++j) {
+        c[j] = items[i + j];
+        w = std::max(w, deg[items[i + j]]);
+      }
+      ch->push_back(c);
+      width->push_back(w);
+    }
+  };
+  std::vector<std::vector<int>> cch, vch;
+  std::vector<int> cw, vw;
+  make_chunks(rdeg, &cch, &cw);
+  make_chunks(cdeg, &vch, &vw);
+  // chunk i goes to wave i mod NW, as its (i / NW)-th; steps per wave
+  auto steps = [&](const std::vector<int>& width) {
+    int kmax = 0;
+    for (int w = 0; w < NW; ++w) {
+      int k = 0;
+      for (size_t i = w; i < width.size(); i += NW) k += width[i];
+      kmax = std::max(kmax, k);
+    }
+    return kmax;
+  };
+  const int Kc = steps(cw), Kv = steps(vw);
+  const int32_t Kc4 = (Kc + BP_AHEAD - 1) / BP_AHEAD * BP_AHEAD, Kv4 = (Kv + BP_AHEAD - 1) / BP_AHEAD * BP_AHEAD;
+  const int32_t Mpk4 = (int32_t)((cch.size() + NW - 1) / NW) * P, Npk = (int32_t)((vch.size() + NW - 1) / NW) * P;
+  if (Npk + 1 > R_IDX || Mpk4 + 2 > R_IDX) return fail(TMCS_EUNSUPPORTED, "BP: too many column or check slots");
+  const int32_t SINK = Mpk4 + 1;
+  std::vector<int32_t> cslot(std::max(D.rows, 0), -1), vmap(std::max(D.cols, 0), -1);
+  std::vector<int32_t> corig4((size_t)Mpk4 + 2, -1);
+  for (size_t i = 0; i < cch.size(); ++i)
+    for (int j = 0; j < 64; ++j)
+      if (cch[i][j] >= 0) {
+        const int32_t slot = (int32_t)((i / NW) * P + (i % NW) * 64 + j);
+        cslot[cch[i][j]] = slot;
+        corig4[slot] = cch[i][j];
+      }
+  for (size_t i = 0; i < vch.size(); ++i)
+    for (int j = 0; j < 64; ++j)
+      if (vch[i][j] >= 0) vmap[vch[i][j]] = (int32_t)((i / NW) * P + (i % NW) * 64 + j);
+  // records; the rows past a wave's last chunk carry no flags and are never stored
+  std::vector<int32_t> pc4((size_t)(Kc4 + BP_AHEAD) * P, Npk), pv4((size_t)(Kv4 + BP_AHEAD) * P, Mpk4);
+  std::vector<int32_t> pce(pc4.size(), 0), pve(pv4.size(), 0);
+  std::vector<float> lamp((size_t)Npk + 1, 0.0f);
+  for (int w = 0; w < NW; ++w) {
+    size_t k = 0;
+    for (size_t i = w; i < cch.size(); i += NW)
+      for (int sx = 0; sx < cw[i]; ++sx, ++k) {
+        const int32_t f = (sx == 0 ? R_FIRST : 0) | (sx == cw[i] - 1 ? R_LAST : 0);
+        for (int j = 0; j < 64; ++j) {
+          const int c = cch[i][j];
+          const size_t at = k * P + w * 64 + j;
+          if (c >= 0 && sx < rdeg[c]) {
+            const int32_t e = D.row_ptr[c] + sx;
+            pc4[at] = vmap[D.col_idx[e]] | pos_bits(sx) | f;
+            pce[at] = e;
+          } else {
+            pc4[at] = Npk | pos_bits(sx) | f;              // no-op edge
+          }
+        }
+      }
+    k = 0;
+    for (size_t i = w; i < vch.size(); i += NW)
+      for (int sx = 0; sx < vw[i]; ++sx, ++k) {
+        const int32_t f = (sx == 0 ? R_FIRST : 0) | (sx == vw[i] - 1 ? R_LAST : 0);
+        for (int j = 0; j < 64; ++j) {
+          const int v = vch[i][j];
+          const size_t at = k * P + w * 64 + j;
+          if (v >= 0 && sx < cdeg[v]) {
+            const int32_t jj = D.col_ptr[v] + sx;
+            const int c = D.row_idx[jj], e = D.csc_edge[jj];
+            pv4[at] = cslot[c] | pos_bits(e - D.row_ptr[c]) | f;
+            pve[at] = e;
+          } else {
+            pv4[at] = SINK | f;                            // no-op edge (message -0)
+          }
+        }
+      }
+  }
+  for (int v = 0; v < D.cols; ++v)
+    if (vmap[v] >= 0) lamp[vmap[v]] = (float)std::log((1.0 - D.priors[v]) / D.priors[v]);
+  // check slots: the iteration-1 state of a real check; empty and padding slots
+  // s_c = 0 with no minima; the sink the no-op message state
+  int4 empty;
+  {
+    const float big = BP_BIG;
+    std::memcpy(&empty.x, &big, 4);
+    std::memcpy(&empty.y, &big, 4);
+    empty.z = -1;
+    empty.w = 0;
+  }
+  std::vector<int4> pinit4((size_t)Mpk4 + 2, empty);
+  for (int32_t c = 0; c < Mpk4; ++c)
+    if (corig4[c] >= 0) pinit4[c] = d->init_pk[corig4[c]];
+  pinit4[SINK] = make_int4(0, 0, -1, -1);                  // +0, +0, no argmin, every sign set
+  if (vmap.empty()) vmap.push_back(-1);
+  // (pc4 last: a schedule with pc4 set is complete)
+  if ((st = upload(&q->pv4, pv4)) != TMCS_OK || (st = upload(&q->pce, pce)) != TMCS_OK ||
       (st = upload(&q->pve, pve)) != TMCS_OK || (st = upload(&q->vmap, vmap)) != TMCS_OK ||
-      (st = upload(&q->corig, corig)) != TMCS_OK || (st = upload(&q->pinit, pinit)) != TMCS_OK ||
-      (st = upload(&q->pc4, pc4)) != TMCS_OK || (st = upload(&q->pv4, pv4)) != TMCS_OK ||
       (st = upload(&q->corig4, corig4)) != TMCS_OK || (st = upload(&q->pinit4, pinit4)) != TMCS_OK ||
-      (st = upload(&q->lamp, lamp)) != TMCS_OK || (st = upload(&q->pc, pc)) != TMCS_OK)
+      (st = upload(&q->lamp, lamp)) != TMCS_OK || (st = upload(&q->pc4, pc4)) != TMCS_OK)
     return st;
   q->Mpk4 = Mpk4;
-  q->Mpk = Mpk;
   q->Npk = Npk;
   q->Kc4 = Kc4;
   q->Kv4 = Kv4;
@@ -1188,13 +1379,19 @@ tmcs_status decode_prepare(const Dem& D, const tmcs_decoder_cfg& cfg, uint64_t n
   P = std::min(1024, std::max(64, (P + 63) / 64 * 64));
   const int sched_mode = cfg.bp_sched > 0 ? cfg.bp_sched : 1;
   const bool pk = pk_ok && !lanes && !fused;
-  if (!lanes && (st = (fused ? get_fsched : pk ? get_psched : get_sched)(D, d, P, sched_mode, &ps.sch)) != TMCS_OK)
+  if (!lanes && (st = (fused ? get_fsched : pk ? (gstate ? get_psched : get_psched_lds) : get_sched)(
+                     D, d, P, sched_mode, &ps.sch)) != TMCS_OK)
     return st;
   if (pk) {
-    bp_lds = (size_t)(ps.sch.Mpk + 1) * 16 + (size_t)(ps.sch.Npk + 1) * 4;
-    if (!gstate && bp_lds > 160 * 1024) gstate = true;   // (the column slots' padding tipped it over)
-    // (state in device memory: check slots numbered i P + l, so up to P - 1 more)
-    if (gstate) bp_lds = (size_t)(ps.sch.Mpk4 + 1) * 16 + (size_t)(ps.sch.Npk + 1) * 4;
+    if (!gstate) {
+      bp_lds = (size_t)(ps.sch.MpkL + 1) * 16 + (size_t)(ps.sch.NpkL + 1) * 4;
+      if (bp_lds > 160 * 1024) {                       // (the column slots' padding tipped it over)
+        gstate = true;
+        if ((st = get_psched(D, d, P, sched_mode, &ps.sch)) != TMCS_OK) return st;
+      }
+    }
+    // device memory: check slots (plus padding and sink), column slots (plus the +BIG slot)
+    if (gstate) bp_lds = (size_t)(ps.sch.Mpk4 + 2) * 16 + (size_t)(ps.sch.Npk + 1) * 4;
     team_bytes = (bp_lds + 255) & ~(size_t)255;
     team_fit = gstate ? (cfg.bp_per_cu > 0 ? 32 : 1) : std::max(1, (int)((160 * 1024) / (bp_lds + 1024)));
   }
@@ -1319,9 +1516,14 @@ BPArgs bp_args(const DecodePass& ps, const uint64_t* det_unused, uint64_t* pred,
   const tmcs_decoder_cfg& cfg = ps.cfg;
   BPArgs a;
   a.csched = ps.sch.c; a.vsched = ps.sch.v; a.Kc = ps.sch.Kc; a.Kv = ps.sch.Kv; a.init = d->init; a.sign0 = d->sign0;
-  a.pcs = ps.sch.pc; a.pvs = ps.sch.pv; a.pce = ps.sch.pce; a.pve = ps.sch.pve; a.vmap = ps.sch.vmap;
-  a.corig = ps.gstate ? ps.sch.corig4 : ps.sch.corig; a.pinit = ps.gstate ? ps.sch.pinit4 : ps.sch.pinit;
-  a.Mpk = ps.gstate ? ps.sch.Mpk4 : ps.sch.Mpk; a.Npk = ps.sch.Npk;
+  if (ps.gstate) {
+    a.pce = ps.sch.pce; a.pve = ps.sch.pve; a.vmap = ps.sch.vmap;
+    a.corig = ps.sch.corig4; a.pinit = ps.sch.pinit4; a.Mpk = ps.sch.Mpk4; a.Npk = ps.sch.Npk;
+  } else {
+    a.pce = ps.sch.pceL; a.pve = ps.sch.pveL; a.vmap = ps.sch.vmapL;
+    a.corig = ps.sch.corigL; a.pinit = ps.sch.pinitL; a.Mpk = ps.sch.MpkL; a.Npk = ps.sch.NpkL;
+  }
+  a.pcs = ps.sch.pcL; a.pvs = ps.sch.pvL;
   a.pcs4 = ps.sch.pc4; a.pvs4 = ps.sch.pv4; a.lamp = ps.sch.lamp;
   a.Kc4 = ps.sch.Kc4; a.Kv4 = ps.sch.Kv4;
   a.lam = d->lam; a.obs_mask = d->obs_mask; a.ow = D.obs_words;

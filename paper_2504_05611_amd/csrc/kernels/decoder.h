@@ -106,12 +106,12 @@ __device__ __forceinline__ uint64_t block_xor_u64(uint64_t v, uint64_t* scratch)
 //               (entries of a column are consecutive in one lane, in CSC order)
 //   both:       bits R_SH.. of x = 2 + the edge's position within its check
 //               (0 where the check has more than PK_MAX_DEG edges)
-// The packed-state team kernel (PK) reads compact records instead (int2):
-//   check pass: x = v' | flags, y = c'
-//   var pass:   x = c' | flags, y = lambda_v bits
-// where c' numbers the checks in the order the lanes first reach them (step i
-// of lane l before step i of lane l + 1, before step i + 1) and v' = i P + l
-// for the i-th column of lane l, so state and L are written in lane order.
+// The packed-state team kernel (PK) reads one int32 per edge and pass instead:
+//   check pass: v' | position bits | flags;  var pass: c' | position bits | flags
+// over checks and columns grouped by degree into chunks of 64 (one per lane of
+// a wave, padded with no-op edges), so the flags are the same in every lane of
+// a wave at every step; lane l's k-th check is at slot c' = k P + l and its
+// k-th column at v' = k P + l.
 // A team kernel gives every lane its own record list; the lanes kernel gives
 // every wave one.
 constexpr int32_t R_FIRST = 1 << 30;    // first edge of its check / column
@@ -167,20 +167,21 @@ struct BPArgs {
   const int32_t* csc_row;    // [E] check of each CSC entry (columns of degree >= 3)
   const int32_t* csc_edge;   // [E] CSR edge of each CSC entry
   uint64_t pm_iso[MAX_OW];   // observables of the columns without edges whose lambda < 0
-  // packed-state team kernel: compact records over renumbered checks (c') and columns (v')
-  const int2* pcs;           // [Kc4 + BP_AHEAD][P] check-pass records
-  const int2* pvs;           // [Kv4 + BP_AHEAD][P] variable-pass records
-  const int32_t* pce;        // [Kc4 + BP_AHEAD][P] CSR edge of each check-pass record (per-edge weights)
-  const int32_t* pve;        // [Kv4 + BP_AHEAD][P] the same for the variable pass
+  // packed-state team kernel.  State in device memory: 4-byte records over
+  // degree chunks, lane l's k-th check at slot c' = k P + l and its k-th column
+  // at v' = k P + l.  State in LDS: int2 records over longest-processing-time
+  // lists, checks numbered in the order the lanes first reach them.
+  const int2* pcs;           // LDS: [Kc + 2][P] check pass {v' | position | flags, c'}
+  const int2* pvs;           // LDS: [Kv + 2][P] variable pass {c' | position | flags, lambda_v bits}
+  const int32_t* pce;        // CSR edge of each check-pass record (per-edge weights), laid out as its records
+  const int32_t* pve;        // the same for the variable pass
   const int32_t* vmap;       // [n] v -> v' (-1: a column without edges)
-  const int32_t* corig;      // [Mpk] c' -> c (-1: an empty slot)
-  const int4* pinit;         // [Mpk] packed check state of iteration 1 (s_c = 0; argmin as 2 + position)
+  const int32_t* corig;      // c' -> c; device memory: [Mpk + 2] (-1: an empty slot, the padding slot Mpk, the sink Mpk + 1)
+  const int4* pinit;         // packed check state of iteration 1 by slot (s_c = 0; argmin as 2 + position)
   int32_t Mpk, Npk;          // check slots, column slots
-  // state in device memory: 4-byte records; the i-th check of lane l is at slot
-  // c' = i P + l (as its columns are), so the check pass needs no check index
-  const int32_t* pcs4;       // [Kc4 + BP_AHEAD][P] check pass: v' | flags
-  const int32_t* pvs4;       // [Kv4 + BP_AHEAD][P] variable pass: c' | flags
-  const float* lamp;         // [Npk] lambda_v by column slot
+  const int32_t* pcs4;       // [Kc4 + BP_AHEAD][P] check pass: v' | position | flags
+  const int32_t* pvs4;       // [Kv4 + BP_AHEAD][P] variable pass: c' | position | flags
+  const float* lamp;         // [Npk + 1] lambda_v by column slot
   int32_t Kc4, Kv4;          // Kc, Kv rounded up to BP_AHEAD (the arrays hold BP_AHEAD rows of padding past them)
 };
 
