@@ -55,8 +55,8 @@ TRAFFIC = {
     "sc_nlcnot_mixed": {
         # one multi-item launch per step (every instance whose BP state is in device memory)
         "k_bp_dev": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
-                     "sha256": "c3eeed1d3a112713461772bf46ec653f219edc5150bdd186523c17bcdef50502",
-                     "fetch_kib": 582173762.8, "write_kib": 277691560.0},
+                     "sha256": "7bbfd03b8fdf7bebbd81ee30899e2387f8008489a7e25b65337e3f9f77a6beb3",
+                     "fetch_kib": 603414084.9, "write_kib": 268491566.8},
     },
     "sc5_nlcnot": {
         "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
