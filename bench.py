@@ -54,9 +54,10 @@ EVENT_APPLY_OPS = 4
 TRAFFIC = {
     "sc_nlcnot_mixed": {
         # one multi-item launch per step (every instance whose BP state is in device memory)
-        "k_bp_dev": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
-                     "sha256": "7bbfd03b8fdf7bebbd81ee30899e2387f8008489a7e25b65337e3f9f77a6beb3",
-                     "fetch_kib": 603414084.9, "write_kib": 268491566.8},
+        "k_bp_dev": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip',
+                             'paper_2504_05611_amd/csrc/kernels/decoder.h'],
+                     "sha256": "bd640f41db7c835dc1ab506711c1267ae09c4119bec7b41bf3389b191842ffdc",
+                     "fetch_kib": 655496494.5, "write_kib": 270698199.7},
     },
     "sc5_nlcnot": {
         "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],

@@ -186,7 +186,7 @@ struct BPArgs {
 };
 
 // Steps whose loads the device-memory team kernel keeps in flight per lane.
-constexpr int BP_AHEAD = 4;
+constexpr int BP_AHEAD = 6;
 
 // Several decode items' BP queues served by one launch.
 struct BPMulti {
