@@ -59,6 +59,12 @@ struct Plan {
   uint64_t batches_done = 0;
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
+  // the items' samplers run side by side (a large circuit's frame kernel fills
+  // a fraction of the GPU): one stream per item, forked from and joined back
+  // to the plan's stream by events (branches of the captured graph)
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // the items' decoders as one batch (one BP launch per kernel variant, one
@@ -70,13 +76,19 @@ static constexpr int DEV_WORDS = 3 + (int)(sizeof(tmcs_decode_stats) / sizeof(ui
 
 static tmcs_status enqueue_batch(Plan& p, hipStream_t s) {
   if (p.multi) {
-    // sample every item, decode them together, then count
-    for (Item& it : p.items) {
-      tmcs_status st = sample_run(*it.c, it.seed, it.instance, 0, p.batch, it.det, it.obs, s, it.dev + 0,
-                                  (uint32_t*)(it.dev + 2), it.sstate);
-      if (st != TMCS_OK) return st;
+    // sample every item (side by side), decode them together, then count
+    tmcs_status st = hip_check(hipEventRecord(p.fork, s), "plan fork");
+    for (size_t i = 0; i < p.items.size() && st == TMCS_OK; ++i) {
+      Item& it = p.items[i];
+      st = hip_check(hipStreamWaitEvent(p.side[i], p.fork, 0), "plan fork wait");
+      if (st == TMCS_OK)
+        st = sample_run(*it.c, it.seed, it.instance, 0, p.batch, it.det, it.obs, p.side[i], it.dev + 0,
+                        (uint32_t*)(it.dev + 2), it.sstate);
+      if (st == TMCS_OK) st = hip_check(hipEventRecord(p.join[i], p.side[i]), "plan join");
+      if (st == TMCS_OK) st = hip_check(hipStreamWaitEvent(s, p.join[i], 0), "plan join wait");
     }
-    tmcs_status st = decode_multi_enqueue(p.multi, s);
+    if (st != TMCS_OK) return st;
+    st = decode_multi_enqueue(p.multi, s);
     if (st != TMCS_OK) return st;
     for (Item& it : p.items) {
       st = count_errors_async(it.pred, it.obs, (uint32_t)it.c->num_obs, p.batch, (unsigned long long*)(it.dev + 1), s);
@@ -106,6 +118,9 @@ static void destroy(Plan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (hipStream_t x : p->side) (void)hipStreamDestroy(x);
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  for (hipEvent_t e : p->join) (void)hipEventDestroy(e);
   for (Item& it : p->items) {
     sample_state_free(it.sstate);
     decode_state_free(it.dstate);
@@ -173,6 +188,15 @@ tmcs_status tmcs_plan_create(const tmcs_plan_item* items, int32_t n_items, uint6
     p->items.push_back(it);
   }
   if (st == TMCS_OK) st = hip_check(hipStreamCreate(&p->cap_stream), "hipStreamCreate");
+  if (st == TMCS_OK) st = hip_check(hipEventCreateWithFlags(&p->fork, hipEventDisableTiming), "hipEventCreate");
+  for (size_t i = 0; i < p->items.size() && st == TMCS_OK; ++i) {
+    hipStream_t x = nullptr;
+    hipEvent_t e = nullptr;
+    st = hip_check(hipStreamCreate(&x), "hipStreamCreate");
+    if (st == TMCS_OK) p->side.push_back(x);
+    if (st == TMCS_OK) st = hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+    if (st == TMCS_OK) p->join.push_back(e);
+  }
   if (st == TMCS_OK) {
     std::vector<MultiItemSpec> specs;
     for (Item& it : p->items)
