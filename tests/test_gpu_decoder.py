@@ -403,7 +403,9 @@ def test_lanes_kernel_refills_lanes(gpu_lib, T, weighted):
     workgroup run different iterations (and, with per-iteration weights,
     different weight rows).  Every per-shot output and the prediction equal the
     team kernel's with its state in LDS, in the per-shot output path and in
-    the compacted one; T = 1 and 2 exercise the last-iteration paths."""
+    the compacted one; T = 1 and 2 exercise the last-iteration paths.  The
+    team kernel with its state in device memory (degree-chunked schedules, no-op
+    edges reading per-edge weights of edge 0) is held to the same outputs."""
     import torch
     spec = sc(5, NLCNOT, 5, 5, 3e-3, 2e-2)
     shots = 40000 + 37
@@ -436,7 +438,7 @@ def test_lanes_kernel_refills_lanes(gpu_lib, T, weighted):
     for full in (True, False):
         ref = run(full)
         for kw in (dict(bp_global_state=2), dict(bp_global_state=2, bp_sched=1, bp_per_cu=2),
-                   dict(bp_global_state=3)):
+                   dict(bp_global_state=3), dict(bp_global_state=1), dict(bp_global_state=1, bp_threads=128)):
             got = run(full, **kw)
             for k in ref:
                 if k == "stats":
