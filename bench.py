@@ -56,8 +56,8 @@ TRAFFIC = {
         # one multi-item launch per step (every instance whose BP state is in device memory)
         "k_bp_dev": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip',
                              'paper_2504_05611_amd/csrc/kernels/decoder.h'],
-                     "sha256": "bd640f41db7c835dc1ab506711c1267ae09c4119bec7b41bf3389b191842ffdc",
-                     "fetch_kib": 655496494.5, "write_kib": 270698199.7},
+                     "sha256": "63535d3b4ea821861c54c069d0a3d4ab847e93347b805aee1b5c79653f27acf8",
+                     "fetch_kib": 644234866.4, "write_kib": 270637499.7},
     },
     "sc5_nlcnot": {
         "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],

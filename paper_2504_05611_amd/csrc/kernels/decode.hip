@@ -1745,6 +1745,19 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
     g->grid = std::min(g->grid, ps.bp_grid_max);
     if (!ps.gstate) g->lds = std::max(g->lds, ps.bp_lds);
   }
+  // Heaviest items first in every group (workgroups take the items in order):
+  // the launch then ends on the cheapest shots instead of waiting for the last
+  // teams of the largest DEM.  Weight: edges, then the expected detection events
+  // (at one DEM size, more events mean more BP iterations).
+  {
+    std::vector<double> ev(m->items.size());
+    for (size_t i = 0; i < m->items.size(); ++i) ev[i] = expected_events(*m->items[i].ps.D);
+    for (auto& g : m->bp)
+      std::stable_sort(g.items.begin(), g.items.end(), [&](int x, int y) {
+        const int64_t ex = m->items[x].ps.D->edges, ey = m->items[y].ps.D->edges;
+        return ex != ey ? ex > ey : ev[x] > ev[y];
+      });
+  }
   const int cus = device_cus();
   for (auto& g : m->bp) {
     if (!g.gstate) {
@@ -1757,11 +1770,7 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
       }
     }
     if (g.lanes) {
-      // heaviest items first (workgroups take the items in order), one state
-      // slab per workgroup sized for the largest item
-      std::stable_sort(g.items.begin(), g.items.end(), [&](int x, int y) {
-        return m->items[x].ps.D->edges > m->items[y].ps.D->edges;
-      });
+      // one state slab per workgroup sized for the largest item
       size_t slab = 0;
       for (int i : g.items) slab = std::max(slab, m->items[i].ps.team_bytes);
       g.lds = slab;
