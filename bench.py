@@ -56,8 +56,8 @@ TRAFFIC = {
         # one multi-item launch per step (every instance whose BP state is in device memory)
         "k_bp_dev": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip',
                              'paper_2504_05611_amd/csrc/kernels/decoder.h'],
-                     "sha256": "63535d3b4ea821861c54c069d0a3d4ab847e93347b805aee1b5c79653f27acf8",
-                     "fetch_kib": 644234866.4, "write_kib": 270637499.7},
+                     "sha256": "2b6a8f200bbd177d2567d627c8565e7a49121cb2faaa2885323da00ae7d0dfa5",
+                     "fetch_kib": 643348669.0, "write_kib": 270640247.1},
     },
     "sc5_nlcnot": {
         "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],

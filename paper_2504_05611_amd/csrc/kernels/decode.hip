@@ -1666,7 +1666,8 @@ tmcs_status decode_run(const Dem& D, const tmcs_decoder_cfg& cfg, const uint64_t
 // A plan's decode items run as one batch: staging per item, then one BP launch
 // per group of items that share the kernel variant (state in LDS or in device
 // memory) and team size, and one windowed-OSD launch for the items that use
-// the windowed OSD-0 with the same grid; any other OSD runs per item.
+// the windowed OSD-0 with the same grid; any other OSD runs per item, beside
+// that launch on a stream of its own.
 struct MultiDecode {
   struct Item {
     DecodePass ps;
@@ -1697,6 +1698,11 @@ struct MultiDecode {
   int osd_grid = 0;
   size_t osd_lds = 0;
   int32_t* next = nullptr;   // device [2]: BP and OSD job counters of the multi launches
+  // with both windowed and other OSD items: the other items' OSD runs on its own
+  // stream beside the windowed launch (forked from and joined back to the
+  // caller's stream by events; branches of a captured graph)
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 void decode_multi_free(MultiDecode* m) {
@@ -1705,6 +1711,9 @@ void decode_multi_free(MultiDecode* m) {
   hipFree(m->osd_tab);
   hipFree(m->osd_tab2);
   hipFree(m->next);
+  if (m->side) (void)hipStreamDestroy(m->side);
+  if (m->fork) (void)hipEventDestroy(m->fork);
+  if (m->join) (void)hipEventDestroy(m->join);
   delete m;
 }
 
@@ -1837,6 +1846,12 @@ tmcs_status decode_multi_create(const std::vector<MultiItemSpec>& specs, uint64_
     decode_multi_free(m);
     return fail(TMCS_ENOMEM, "hipMalloc failed (multi decode counters)");
   }
+  if (!m->osd_win_items.empty() && !m->osd_other_items.empty()) {
+    st = hip_check(hipStreamCreate(&m->side), "hipStreamCreate");
+    if (st == TMCS_OK) st = hip_check(hipEventCreateWithFlags(&m->fork, hipEventDisableTiming), "hipEventCreate");
+    if (st == TMCS_OK) st = hip_check(hipEventCreateWithFlags(&m->join, hipEventDisableTiming), "hipEventCreate");
+    if (st != TMCS_OK) { decode_multi_free(m); return st; }
+  }
   *out = m;
   return TMCS_OK;
 }
@@ -1867,6 +1882,19 @@ tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream) {
     launch_k_bp<true>(g.weighted, g.gstate, g.pk, grid, g.P, g.gstate ? 0 : g.lds, stream, a0, mu);
     if ((st = hip_check(hipGetLastError(), "k_bp launch")) != TMCS_OK) return st;
   }
+  // Items outside the windowed launch (another window shape, or no window) take
+  // their OSD on the side stream when there is one: the two chains then share
+  // the GPU, and each one's full-window retries (a few shots, one workgroup each,
+  // bound by a workgroup's latency) run while the other still fills it.
+  if (m->side) {
+    if ((st = hip_check(hipEventRecord(m->fork, stream), "multi decode fork")) != TMCS_OK) return st;
+    if ((st = hip_check(hipStreamWaitEvent(m->side, m->fork, 0), "multi decode fork wait")) != TMCS_OK) return st;
+    for (int i : m->osd_other_items) {
+      auto& it = m->items[i];
+      if ((st = decode_osd_launch(it.ps, it.pred, it.stats, 0, m->side)) != TMCS_OK) return st;
+    }
+    if ((st = hip_check(hipEventRecord(m->join, m->side), "multi decode join")) != TMCS_OK) return st;
+  }
   if (!m->osd_win_items.empty()) {
     const OSDMulti mu{m->osd_tab, (int32_t)m->osd_win_items.size(), m->next + 1};
     if (m->osd_win2) {
@@ -1878,6 +1906,7 @@ tmcs_status decode_multi_enqueue(MultiDecode* m, hipStream_t stream) {
       return st;
     }
   }
+  if (m->side) return hip_check(hipStreamWaitEvent(stream, m->join, 0), "multi decode join wait");
   for (int i : m->osd_other_items) {
     auto& it = m->items[i];
     if ((st = decode_osd_launch(it.ps, it.pred, it.stats, 0, stream)) != TMCS_OK) return st;
