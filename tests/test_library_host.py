@@ -151,6 +151,45 @@ def test_nondeterministic_outputs_are_rejected(tmp_path):
     assert got["bell_half"][1].startswith("detector 0")
 
 
+def test_host_builders_under_sanitizers(tmp_path):
+    """The circuit, code, DEM, program and distance builders, built with g++ under
+    AddressSanitizer and UndefinedBehaviorSanitizer (any report aborts the run),
+    on surface-code and BB memory, non-local CNOT, teleportation, decoherence and
+    Pauli-string circuits; invalid specs fail with TMCS_EINVAL.  The exact
+    distance searches give the code distance 3 of the d = 3 operations (Table I)
+    and 3 for the [[18,4,4]] memory circuit."""
+    import shutil
+    import subprocess
+    from concurrent.futures import ThreadPoolExecutor
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("no host C++ compiler")
+    csrc = os.path.join(ROOT, "paper_2504_05611_amd", "csrc")
+    flags = ["-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined", "-I" + os.path.join(ROOT, "include"), "-I" + csrc]
+    srcs = [os.path.join(ROOT, "tests", "native", "host_sanitize.cpp")] + [
+        os.path.join(csrc, "host", f + ".cpp") for f in ("circuit", "codes", "dem", "distance", "program")]
+    objs = [str(tmp_path / (os.path.basename(x) + ".o")) for x in srcs]
+    with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        for r in ex.map(lambda so: subprocess.run([gxx] + flags + ["-c", so[0], "-o", so[1]], capture_output=True,
+                                                  text=True), zip(srcs, objs)):
+            assert r.returncode == 0, r.stderr[-2000:]
+    exe = str(tmp_path / "host_sanitize")
+    subprocess.run([gxx, "-fsanitize=address,undefined"] + objs + ["-o", exe], check=True, capture_output=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0 and "runtime error" not in r.stderr and "Sanitizer" not in r.stderr, r.stderr[-4000:]
+    got = {line.split()[0]: [int(x) for x in line.split()[1:]] for line in r.stdout.splitlines()}
+    assert len(got) == 15
+    for name, (st, dets, cols, edges, dist) in got.items():
+        if name.startswith("bad_"):
+            assert st == 1, name
+        else:
+            assert st == 0 and dets > 0 and cols > 0 and edges >= cols, (name, st)
+    for name in ("sc3_memory", "sc3_nlcnot", "sc3_teleport", "bb18_memory"):
+        assert got[name][4] == 3, (name, got[name])
+
+
 def test_more_than_64_observables_match_oracle(lib):
     """A Pauli string of weight 16 on [[18,4,4]] blocks has 17 x 4 = 68 observables:
     the DEM's masks take two words per column, and columns with equal detector
