@@ -60,11 +60,12 @@ TRAFFIC = {
                      "fetch_kib": 643348669.0, "write_kib": 270640247.1},
     },
     "sc5_nlcnot": {
-        "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip'],
-                 "sha256": "03be1640d29e262e7fa79b55d7c89ae35d2a88b8fc854330c6b0d2413b9f1bfa",
-                 "fetch_kib": 72915.6, "write_kib": 133335.7},
+        "k_bp": {"src": ['paper_2504_05611_amd/csrc/kernels/decode.hip',
+                         'paper_2504_05611_amd/csrc/kernels/decoder.h'],
+                 "sha256": "2b6a8f200bbd177d2567d627c8565e7a49121cb2faaa2885323da00ae7d0dfa5",
+                 "fetch_kib": 72902.9, "write_kib": 133817.9},
         "k_frame": {"src": ['paper_2504_05611_amd/csrc/kernels/sample.hip', 'paper_2504_05611_amd/csrc/host/program.cpp'],
-                    "sha256": "a995ee3c19865f8598c874400fecec85e360bbb766f1e7164d0f5f422eff8eb4",
+                    "sha256": "00f029fb29532a447cb003e411236ebcd32b0891f81c819f6e0dbc44fb9670ad",
                     "fetch_kib": 59909.7, "write_kib": 38549.7},
     },
 }
